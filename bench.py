@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""Throughput of the fused FFT spectral solve on one MI355X.
+
+Workload: the 2D wave equation u_tt = c^2 lap(u) on the periodic unit square
+at 2048 x 2048 (c = 1, dt = 1e-4, u0 = Gaussian pulse of width 0.02 at a
+seeded centre plus the standing mode sin(6 pi x) sin(10 pi y), v0 = 0).
+One step solves a batch of B independent such problems (seeded centres)
+at t_n = n dt: forward 2D FFT -> propagator cos(c|k| t_n) -> inverse 2D FFT,
+FP32 butterflies with FP64 twiddle generation and FP64 phase.  The batch
+keeps the working set (2 x 512 MiB at B = 16) well above the 256 MiB
+Infinity Cache, so the passes run from HBM.  The same workload in FP64
+(B = 8) is reported beside it.
+
+Prints one JSON line.  Inputs are resident in HBM before timing starts.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "2D spectral solves/s + HBM GB/s at N=2048, FP32 vs FP64; serving p50/p99 ms"
+HBM_PEAK_GBS = 8000.0
+N_SIDE = 2048
+DT = 1e-4
+C_SPEED = 1.0
+
+
+def make_inputs(n: int, batch: int, seed: int = 3):
+    import numpy as np
+
+    import workloads as W
+    out = np.empty((batch, n, n), dtype=np.complex128)
+    for i in range(batch):
+        s = seed if i == 0 else W._child_seed(seed, i)
+        out[i] = W.wave_ic(n, seed=s).field
+    return out
+
+
+def run_leg(fp, torch, host_fields, dtype_name: str, steps: int, warmup: int):
+    """Time `steps` batched solves; returns a dict of measurements."""
+    dev = torch.device("cuda:0")
+    tdt = {"c64": torch.complex64, "c128": torch.complex128}[dtype_name]
+    u0 = torch.from_numpy(host_fields).to(tdt).to(dev)
+    out = torch.empty_like(u0)
+    batch, ny, nx = u0.shape
+    bpp = 8 if dtype_name == "c64" else 16
+    for w in range(warmup):
+        fp.solve_wave(u0, None, C_SPEED, (w + 1) * DT, 1.0, 1.0, out=out)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    fp.profile(0, True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    e0.record(stream)
+    for s in range(steps):
+        fp.solve_wave(u0, None, C_SPEED, (s + 1) * DT, 1.0, 1.0, out=out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    ms = e0.elapsed_time(e1)
+    kstats = fp.profile_read(0)
+    fp.profile(0, False)
+    solves = batch * steps
+    alg_bytes = 6.0 * bpp * nx * ny * solves
+    # dominant kernel: the one with the largest share of the timed region
+    dom = max(kstats, key=lambda k: k["total_ms"])
+    avg_ms = dom["total_ms"] / dom["launches"]
+    bytes_per_launch = dom["bytes"] / dom["launches"]
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    return {
+        "batch": batch, "steps": steps, "ms_total": ms, "wall_s": wall,
+        "solves_per_s": solves / (ms * 1e-3),
+        "ms_per_step": ms / steps,
+        "eff_gbs": alg_bytes / (ms * 1e-3) / 1e9,
+        "kernels": [{**k, "avg_us": 1e3 * k["total_ms"] / k["launches"],
+                     "gbs": (k["bytes"] / k["launches"]) / (k["total_ms"] / k["launches"] * 1e-3) / 1e9}
+                    for k in kstats],
+        "dominant": {"kernel": dom["kernel"], "avg_us": 1e3 * avg_ms,
+                     "bytes_per_launch": bytes_per_launch, "achieved_gbs": achieved},
+        "last_out": out, "last_t": steps * DT,
+    }
+
+
+def oracle_check(out_dev, host_field, dtype_name, t):
+    """Relative L2 error of one GPU result against the FP64 oracle."""
+    import numpy as np
+
+    import oracle
+    x = host_field.astype(np.complex64).astype(np.complex128) if dtype_name == "c64" else host_field
+    ref, _ = oracle.solve_wave(x, None, 1.0, 1.0, C_SPEED, t, threads=oracle.default_threads())
+    got = out_dev.cpu().numpy().astype(np.complex128)
+    return oracle.rel_l2(got, ref)
+
+
+def cpu_baseline(host_field, seconds: float = 10.0):
+    """The FP64 oracle (recursive radix-2, all host threads) on the same
+    workload: as many single-field solves as fit in about `seconds`."""
+    import oracle
+    threads = oracle.default_threads()
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        oracle.solve_wave(host_field, None, 1.0, 1.0, C_SPEED, (n + 1) * DT, threads=threads)
+        n += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    el = time.perf_counter() - t0
+    return {"value": n / el, "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} FP64 wave solves of one 2048x2048 field (fwd 2D FFT, propagator, "
+                      f"inverse 2D FFT), {el:.1f} s on {threads} threads"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--batch", type=int, default=16, help="FP32 batch (FP64 uses half)")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    a = ap.parse_args(argv)
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported "
+              "(independent solves would shard by request across GPUs).", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2412_12308_amd as fp
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 1
+    print(f"# generating inputs: {a.batch} x {N_SIDE}^2", file=sys.stderr, flush=True)
+    fields = make_inputs(N_SIDE, a.batch)
+    print("# fp32 leg", file=sys.stderr, flush=True)
+    r32 = run_leg(fp, torch, fields, "c64", a.steps, a.warmup)
+    err32 = None if a.no_check else oracle_check(r32["last_out"][0], fields[0], "c64", r32["last_t"])
+    r64 = None
+    err64 = None
+    if not a.no_fp64:
+        print("# fp64 leg", file=sys.stderr, flush=True)
+        f64 = fields[: max(1, a.batch // 2)]
+        r64 = run_leg(fp, torch, f64, "c128", a.steps, a.warmup)
+        err64 = None if a.no_check else oracle_check(r64["last_out"][0], f64[0], "c128", r64["last_t"])
+    print("# cpu baseline", file=sys.stderr, flush=True)
+    cpu = cpu_baseline(fields[0], a.cpu_seconds)
+
+    dom = r32["dominant"]
+    tol32 = 2 * 2e-6 * math.log2(N_SIDE)
+    line = {
+        "metric": METRIC,
+        "value": round(r32["solves_per_s"], 2),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(r32["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "wave2d_2048x2048_periodic_unit_square", "nx": N_SIDE, "ny": N_SIDE,
+                   "batch": r32["batch"], "c": C_SPEED, "dt": DT,
+                   "precision": "FP32 butterflies; FP64 twiddle generation and FP64 phase",
+                   "solve": "fwd 2D FFT + cos(c|k|t_n) + inverse 2D FFT, 3 HBM passes"},
+        "eff_hbm_gbs": round(r32["eff_gbs"], 1),
+        "eff_hbm_frac": round(r32["eff_gbs"] / HBM_PEAK_GBS, 4),
+        "err_vs_oracle": err32,
+        "err_tol": tol32,
+        "roofline": {"bound": "hbm", "achieved": round(dom["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(dom["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                     "traffic": None, "kernel": dom["kernel"], "avg_us": round(dom["avg_us"], 2),
+                     "bytes_per_launch": dom["bytes_per_launch"]},
+        "kernels": [{"kernel": k["kernel"], "launches": k["launches"], "avg_us": round(k["avg_us"], 2),
+                     "gbs": round(k["gbs"], 1)} for k in r32["kernels"]],
+        "cpu_baseline": cpu,
+    }
+    if r64:
+        line["fp64"] = {"value": round(r64["solves_per_s"], 2), "unit": "solves/s", "batch": r64["batch"],
+                        "ms_per_step": round(r64["ms_per_step"], 4), "eff_hbm_gbs": round(r64["eff_gbs"], 1),
+                        "eff_hbm_frac": round(r64["eff_gbs"] / HBM_PEAK_GBS, 4), "err_vs_oracle": err64,
+                        "err_tol": 1e-12,
+                        "kernels": [{"kernel": k["kernel"], "launches": k["launches"],
+                                     "avg_us": round(k["avg_us"], 2), "gbs": round(k["gbs"], 1)}
+                                    for k in r64["kernels"]]}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

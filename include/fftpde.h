@@ -1,0 +1,151 @@
+/*
+ * fftpde.h -- C ABI of libfftpde.so: 2D FFTs and FFT spectral solves of the
+ * periodic Poisson, diffusion and wave equations on one AMD Instinct MI355X
+ * (gfx950) GPU.  Method: arXiv 2412.12308, "Numerical Solution of Partial
+ * Differential Equations using the Discrete Fourier Transform".
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ *  Fields.  Complex, interleaved (re, im).  FFTPDE_C64 = FP32 complex
+ *    (8 bytes per point), FFTPDE_C128 = FP64 complex (16 bytes per point).
+ *    A field is nx*ny points stored row-major as [ny][nx] with x contiguous:
+ *    point (x_j, y_k) is element k*nx + j.  A batch of `batch` fields is
+ *    stored back to back (field b starts at element b*nx*ny).  Sampling
+ *    follows Sec. II.B/II.D: x_j = x0 + j*lx/nx, j = 0..nx-1 (periodic,
+ *    endpoint excluded); the origin x0 never enters a solve.
+ *  Sizes.  nx and ny are powers of two in [2, 4096] (the FFT's 2^m
+ *    restriction, Sec. II.C); batch >= 1.
+ *  Pointers.  Every field pointer is a DEVICE pointer on the context's GPU,
+ *    aligned to the element size.  The caller owns every field buffer.
+ *    in == out (in place) is allowed wherever an input and an output have the
+ *    same size; other partial overlaps are not.
+ *  Streams.  `stream` is a hipStream_t (NULL = the legacy default stream).
+ *    Calls only enqueue work: outputs are valid once the stream has reached
+ *    the call.  Calls on one context from several host threads must be
+ *    serialised by the caller.
+ *  Transform sign.  Forward = exp(-2 pi i (a j/nx + b k/ny)), unnormalised;
+ *    inverse = exp(+2 pi i ...) times 1/(nx ny).  This is the sign of the
+ *    row-column derivation of Sec. II.D; the paper's Eq. (DFT) writes the
+ *    opposite sign, which only reverses the frequency index and leaves every
+ *    solve below unchanged (their symbols are even in k).
+ *  Wavenumbers.  k_x = 2 pi a'/lx with a' = a for a < nx/2, else a - nx
+ *    (the shifted frequencies of Sec. II.B and II.D); likewise k_y;
+ *    |k|^2 = k_x^2 + k_y^2.
+ *  Status.  Every function returns an int status (FFTPDE_OK = 0, negative =
+ *    error); no C++ exception crosses this boundary.  Arguments are checked
+ *    before any device work; a rejected call enqueues nothing.
+ *    FFTPDE_EDEVICE may report an earlier asynchronous launch failure.
+ */
+#ifndef FFTPDE_H
+#define FFTPDE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define FFTPDE_OK 0
+#define FFTPDE_PENDING 1      /* serving: request not finished yet */
+#define FFTPDE_EINVAL (-1)    /* bad size, pointer, dtype or coefficient */
+#define FFTPDE_ENOMEM (-2)    /* host or device allocation failed */
+#define FFTPDE_EDEVICE (-3)   /* a HIP call or kernel launch failed */
+#define FFTPDE_EBUDGET (-4)   /* serving: request larger than the whole budget */
+#define FFTPDE_ENOTFOUND (-5) /* unknown request id or plan */
+#define FFTPDE_ECANCELED (-6) /* serving: request cancelled */
+#define FFTPDE_ETIMEOUT (-7)  /* serving: deadline passed before completion */
+
+/* ---- dtypes and operators ---------------------------------------------- */
+#define FFTPDE_C64 0  /* FP32 complex; FP64 twiddles rounded once, FP64 phases */
+#define FFTPDE_C128 1 /* FP64 complex throughout */
+
+#define FFTPDE_POISSON 0   /* lap(u) = s                  (Sec. III.A) */
+#define FFTPDE_DIFFUSION 1 /* u_t = kappa lap(u)          (Sec. III.B) */
+#define FFTPDE_WAVE 2      /* u_tt = c^2 lap(u)           (Sec. III.C) */
+
+typedef void *fftpde_stream; /* a hipStream_t */
+typedef struct fftpde_ctx fftpde_ctx;
+typedef struct fftpde_evolve fftpde_evolve;
+typedef struct fftpde_batch fftpde_batch;
+typedef struct fftpde_server fftpde_server;
+
+/* ---- lifecycle ----------------------------------------------------------
+ * fftpde_create: make `device` current, build the twiddle tables
+ *   w^e = exp(-2 pi i e/4096), e = 0..4095, in FP64 on the host and round them
+ *   once to FP32 for the C64 table (the w_N^k of Sec. II.B/II.C; a length-N
+ *   transform reads every (4096/N)-th entry), and upload both.  *ctx receives
+ *   an opaque handle owned by the caller until fftpde_destroy.
+ * fftpde_destroy: frees everything the context owns (tables, plan cache,
+ *   workspace); NULL is accepted.  The caller must first finish or destroy
+ *   evolutions, batches and servers made from it.
+ * fftpde_strerror: static text for a status code, never NULL.
+ * fftpde_version: library version string. */
+int fftpde_create(fftpde_ctx **ctx, int device);
+int fftpde_destroy(fftpde_ctx *ctx);
+const char *fftpde_strerror(int status);
+const char *fftpde_version(void);
+/* fftpde_last_error: text of the last HIP failure seen by this host thread
+ * (the detail behind an FFTPDE_EDEVICE), "" if none; valid until the next
+ * call on the same thread. */
+const char *fftpde_last_error(void);
+
+/* ---- kernel timing ------------------------------------------------------
+ * fftpde_profile: enable (1) or disable (0) timing of every kernel this
+ *   context launches from now on; either call drops earlier records.  Each
+ *   launch is bracketed by two HIP events recorded on the launch's stream.
+ * fftpde_profile_read: wait for the recorded launches and write a JSON array
+ *   [{"kernel": name, "launches": n, "total_ms": t, "bytes": b}, ...] into
+ *   buf (cap bytes, NUL-terminated), where b is the algorithmic HBM traffic
+ *   (each field read once and written once per launch).  *needed (if not
+ *   NULL) receives the size required; a too-small buf gives FFTPDE_ENOMEM. */
+int fftpde_profile(fftpde_ctx *ctx, int enable);
+int fftpde_profile_read(fftpde_ctx *ctx, char *buf, size_t cap, size_t *needed);
+
+/* ---- 2D transforms (Sec. II.D, Eq. (2D_DFT); iDFT of Sec. II.B) ----------
+ * fft2d_forward: out = unnormalised forward 2D transform of in, for each of
+ *   `batch` fields.  Done as all x-direction (row) transforms for fixed y,
+ *   then all y-direction (column) transforms for fixed x frequency.
+ * fft2d_inverse: out = exp(+) transform times 1/(nx ny).
+ *   in/out: device fields of the given dtype, batch*nx*ny points each. */
+int fft2d_forward(fftpde_ctx *ctx, const void *in, void *out, int nx, int ny, int batch,
+                  int dtype, fftpde_stream stream);
+int fft2d_inverse(fftpde_ctx *ctx, const void *in, void *out, int nx, int ny, int batch,
+                  int dtype, fftpde_stream stream);
+
+/* ---- spectral solves ----------------------------------------------------
+ * Each is forward 2D FFT -> pointwise multiply by the equation's Fourier
+ * symbol -> inverse 2D FFT.  The multiply and the 1/(nx ny) of the inverse
+ * run inside the column pass, between its forward and inverse transforms.
+ *
+ * solve_poisson: lap(u) = s on a periodic lx-by-ly box (Eq. (Poisson)).
+ *   The mean of s is removed (g = s - mean(s), Eq. (Poisson2)) by dropping the
+ *   k = 0 coefficient, and u is the zero-mean solution
+ *   u = F^-1{ -F{g} / |k|^2 } (Eq. (SolutionPoisson)) with u^(0) = 0.
+ *   s: input fields, u: output fields (may equal s).
+ * solve_diffusion: u(t) for u_t = kappa lap(u), u(0) = u0, source-free
+ *   (Eq. (EcuacionDeCalor) with diffusivity kappa):
+ *   u^(t) = u0^ exp(-kappa |k|^2 t) (Eq. (solCalorFourier)).  kappa >= 0,
+ *   t >= 0 (the backward heat equation is rejected), both finite.  The
+ *   exponent kappa |k|^2 t is formed in FP64 for both dtypes.
+ * solve_wave: u(t) (and u_t(t)) for u_tt = c^2 lap(u), u(0) = u0,
+ *   u_t(0) = v0, source-free (Eq. (wave_equation), (OndaCI)):
+ *   u^ = u0^ cos(w t) + v0^ sin(w t)/w with w = c|k|, and u0^ + v0^ t at
+ *   w = 0 (Eq. (OmegaNonZero), (OmegaZero) with s = 0); the velocity is
+ *   v^ = -w u0^ sin(w t) + v0^ cos(w t).  v0 = NULL means v0 = 0; v = NULL
+ *   means the velocity is not written.  c >= 0, t any finite value (negative
+ *   t runs the wave backwards).  The phase w t is formed and reduced in FP64
+ *   for both dtypes. */
+int solve_poisson(fftpde_ctx *ctx, const void *s, void *u, int nx, int ny, int batch, double lx,
+                  double ly, int dtype, fftpde_stream stream);
+int solve_diffusion(fftpde_ctx *ctx, const void *u0, void *u, int nx, int ny, int batch,
+                    double lx, double ly, double kappa, double t, int dtype,
+                    fftpde_stream stream);
+int solve_wave(fftpde_ctx *ctx, const void *u0, const void *v0, void *u, void *v, int nx, int ny,
+               int batch, double lx, double ly, double c, double t, int dtype,
+               fftpde_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FFTPDE_H */

@@ -1,0 +1,243 @@
+"""fftpde -- FFT spectral solvers for periodic 2D PDEs on AMD Instinct MI355X.
+
+A thin ctypes binding over libfftpde.so (C ABI in include/fftpde.h).  Every
+step of every transform and solve runs in the library's HIP kernels; this
+module only checks tensors, passes device pointers and the current HIP
+stream, and turns status codes into exceptions.  PyTorch provides device
+memory and streams.  There is no CPU fallback: if the library is missing or
+no GPU is present, calls raise.
+
+Tensors are complex64 (FP32 complex) or complex128 (FP64 complex) on a ROCm
+device, contiguous, shaped [..., ny, nx] with x contiguous; leading
+dimensions form the batch.
+"""
+from __future__ import annotations
+
+import atexit
+import ctypes
+import os
+import threading
+from typing import Optional, Tuple
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfftpde.so")
+
+OK, PENDING = 0, 1
+EINVAL, ENOMEM, EDEVICE, EBUDGET, ENOTFOUND, ECANCELED, ETIMEOUT = -1, -2, -3, -4, -5, -6, -7
+C64, C128 = 0, 1
+POISSON, DIFFUSION, WAVE = 0, 1, 2
+
+
+class FftpdeError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str = ""):
+        self.status = status
+        msg = f"{where}: {strerror(status)} ({status})"
+        if detail:
+            msg += f" [{detail}]"
+        super().__init__(msg)
+
+
+_lib = None
+_lib_lock = threading.Lock()
+
+
+def lib() -> ctypes.CDLL:
+    """Load libfftpde.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    with _lib_lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise ImportError(f"{LIB_PATH} is missing: build it with "
+                                  "`python -m paper_2412_12308_amd.build`")
+            L = ctypes.CDLL(LIB_PATH)
+            _declare(L)
+            _lib = L
+    return _lib
+
+
+def _declare(L):
+    vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    L.fftpde_create.argtypes = [ctypes.POINTER(vp), i]
+    L.fftpde_destroy.argtypes = [vp]
+    L.fftpde_strerror.argtypes = [i]
+    L.fftpde_strerror.restype = ctypes.c_char_p
+    L.fftpde_version.restype = ctypes.c_char_p
+    L.fftpde_last_error.restype = ctypes.c_char_p
+    L.fft2d_forward.argtypes = [vp, vp, vp, i, i, i, i, vp]
+    L.fft2d_inverse.argtypes = [vp, vp, vp, i, i, i, i, vp]
+    L.solve_poisson.argtypes = [vp, vp, vp, i, i, i, d, d, i, vp]
+    L.solve_diffusion.argtypes = [vp, vp, vp, i, i, i, d, d, d, d, i, vp]
+    L.solve_wave.argtypes = [vp, vp, vp, vp, vp, i, i, i, d, d, d, d, i, vp]
+    L.fftpde_profile.argtypes = [vp, i]
+    L.fftpde_profile_read.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t,
+                                      ctypes.POINTER(ctypes.c_size_t)]
+    for f in ("fftpde_profile", "fftpde_profile_read", "fftpde_create", "fftpde_destroy", "fft2d_forward", "fft2d_inverse", "solve_poisson",
+              "solve_diffusion", "solve_wave"):
+        getattr(L, f).restype = i
+
+
+def strerror(status: int) -> str:
+    try:
+        return lib().fftpde_strerror(status).decode()
+    except ImportError:
+        return f"status {status}"
+
+
+def version() -> str:
+    return lib().fftpde_version().decode()
+
+
+def _check(rc: int, where: str):
+    if rc != OK:
+        detail = ""
+        if rc == EDEVICE:
+            detail = lib().fftpde_last_error().decode(errors="replace")
+        raise FftpdeError(rc, where, detail)
+
+
+# ---------------------------------------------------------------------------
+# contexts (one per device, created on first use)
+# ---------------------------------------------------------------------------
+_ctx = {}
+
+
+def context(device: int) -> int:
+    h = _ctx.get(device)
+    if h is None:
+        p = ctypes.c_void_p()
+        _check(lib().fftpde_create(ctypes.byref(p), int(device)), "fftpde_create")
+        h = _ctx[device] = p.value
+    return h
+
+
+@atexit.register
+def _destroy_contexts():
+    if _lib is None:
+        return
+    for dev, h in list(_ctx.items()):
+        _lib.fftpde_destroy(h)
+    _ctx.clear()
+
+
+def profile(device: int, enable: bool):
+    """Time every kernel launched on `device` from now on with HIP events."""
+    _check(lib().fftpde_profile(context(device), 1 if enable else 0), "fftpde_profile")
+
+
+def profile_read(device: int):
+    """Per-kernel launches, total milliseconds and algorithmic bytes since profiling began."""
+    import json
+    need = ctypes.c_size_t(0)
+    _check(lib().fftpde_profile_read(context(device), None, 0, ctypes.byref(need)), "fftpde_profile_read")
+    buf = ctypes.create_string_buffer(max(2, need.value))
+    _check(lib().fftpde_profile_read(context(device), buf, len(buf), None), "fftpde_profile_read")
+    return json.loads(buf.value.decode())
+
+
+# ---------------------------------------------------------------------------
+# tensor marshalling
+# ---------------------------------------------------------------------------
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.complex64:
+        return C64
+    if t.dtype == torch.complex128:
+        return C128
+    raise TypeError(f"expected complex64 or complex128, got {t.dtype}")
+
+
+def _field(t, name: str):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on a ROCm device (got {t.device}); there is no CPU path")
+    if t.dim() < 2:
+        raise ValueError(f"{name} must have shape [..., ny, nx]")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    ny, nx = t.shape[-2], t.shape[-1]
+    batch = t.numel() // (nx * ny) if nx * ny else 0
+    return nx, ny, batch, _dtype_code(t)
+
+
+def _like(x, out, name="out"):
+    torch = _torch()
+    if out is None:
+        return torch.empty_like(x)
+    if out.shape != x.shape or out.dtype != x.dtype or out.device != x.device:
+        raise ValueError(f"{name} must match the input's shape, dtype and device")
+    if not out.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return out
+
+
+def _stream(t) -> int:
+    return _torch().cuda.current_stream(t.device).cuda_stream
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+# ---------------------------------------------------------------------------
+# API (names as in the C ABI)
+# ---------------------------------------------------------------------------
+def fft2d_forward(x, out=None):
+    """Unnormalised forward 2D FFT, exponent exp(-2 pi i (a j/nx + b k/ny))."""
+    nx, ny, batch, dt = _field(x, "x")
+    out = _like(x, out)
+    _check(lib().fft2d_forward(context(x.device.index), _ptr(x), _ptr(out), nx, ny, batch, dt,
+                               _stream(x)), "fft2d_forward")
+    return out
+
+
+def fft2d_inverse(x, out=None):
+    """Inverse 2D FFT, exponent exp(+2 pi i ...) times 1/(nx ny)."""
+    nx, ny, batch, dt = _field(x, "x")
+    out = _like(x, out)
+    _check(lib().fft2d_inverse(context(x.device.index), _ptr(x), _ptr(out), nx, ny, batch, dt,
+                               _stream(x)), "fft2d_inverse")
+    return out
+
+
+def solve_poisson(s, lx: float = 1.0, ly: float = 1.0, out=None):
+    """Zero-mean u with lap(u) = s - mean(s) on a periodic lx-by-ly box."""
+    nx, ny, batch, dt = _field(s, "s")
+    out = _like(s, out)
+    _check(lib().solve_poisson(context(s.device.index), _ptr(s), _ptr(out), nx, ny, batch,
+                               float(lx), float(ly), dt, _stream(s)), "solve_poisson")
+    return out
+
+
+def solve_diffusion(u0, kappa: float, t: float, lx: float = 1.0, ly: float = 1.0, out=None):
+    """u(t) for u_t = kappa lap(u), u(0) = u0, periodic box, t >= 0."""
+    nx, ny, batch, dt = _field(u0, "u0")
+    out = _like(u0, out)
+    _check(lib().solve_diffusion(context(u0.device.index), _ptr(u0), _ptr(out), nx, ny, batch,
+                                 float(lx), float(ly), float(kappa), float(t), dt, _stream(u0)),
+           "solve_diffusion")
+    return out
+
+
+def solve_wave(u0, v0=None, c: float = 1.0, t: float = 0.0, lx: float = 1.0, ly: float = 1.0,
+               out=None, v_out=None, want_v: bool = False) -> Tuple:
+    """(u(t), u_t(t) or None) for u_tt = c^2 lap(u), u(0) = u0, u_t(0) = v0 (None => 0)."""
+    nx, ny, batch, dt = _field(u0, "u0")
+    if v0 is not None:
+        if _field(v0, "v0") != (nx, ny, batch, dt) or v0.device != u0.device:
+            raise ValueError("v0 must match u0")
+    out = _like(u0, out)
+    if want_v or v_out is not None:
+        v_out = _like(u0, v_out, "v_out")
+    _check(lib().solve_wave(context(u0.device.index), _ptr(u0), _ptr(v0), _ptr(out), _ptr(v_out),
+                            nx, ny, batch, float(lx), float(ly), float(c), float(t), dt,
+                            _stream(u0)), "solve_wave")
+    return out, v_out

@@ -1,0 +1,49 @@
+// context.hpp -- state behind an fftpde_ctx handle: the device, the twiddle
+// tables, the per-shape kernel choices and a reusable workspace.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+
+namespace fftpde {
+
+// index of a (dtype, pass kind, log2 length, fields per pass) plan slot
+constexpr int plan_key(int dtype, int kind, int logn, int nf) {
+  return ((dtype * 2 + kind) * 13 + logn) * 2 + (nf - 1);
+}
+constexpr int kPlanSlots = 2 * 2 * 13 * 2;
+
+struct Context {
+  int device = 0;
+  cx<float>* tw32 = nullptr;   // exp(-2 pi i e/4096), FP64-generated, rounded once
+  cx<double>* tw64 = nullptr;  // the same in FP64
+  void* work = nullptr;        // scratch field for solves that need one
+  size_t work_bytes = 0;
+  // Kernel choice per plan slot; null = the first compiled variant of that length.
+  const RowVariant* row_choice[kPlanSlots] = {};
+  const ColVariant* col_choice[kPlanSlots] = {};
+
+  // Optional per-kernel timing: a HIP event pair around every launch.
+  struct TimedLaunch {
+    const char* name;
+    double bytes;  // algorithmic HBM bytes of the launch
+    hipEvent_t start, stop;
+  };
+  bool profiling = false;
+  std::vector<TimedLaunch> timed;
+  std::vector<hipEvent_t> event_pool;
+  hipEvent_t take_event();
+
+  const RowVariant* row_variant(int dtype, int logn) const;
+  const ColVariant* col_variant(int dtype, int logn, int nf) const;
+  int workspace(size_t bytes, void** p);
+};
+
+void set_last_error(const char* what, hipError_t e);
+
+}  // namespace fftpde

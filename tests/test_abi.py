@@ -1,0 +1,119 @@
+"""The C ABI without a GPU: the library loads, exports every function that
+include/fftpde.h declares, and rejects bad arguments with FFTPDE_EINVAL before
+touching the device."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "fftpde.h")
+
+
+def _lib():
+    import paper_2412_12308_amd as fp
+    if not os.path.exists(fp.LIB_PATH):
+        pytest.skip("libfftpde.so not built (run __graft_entry__.build())")
+    return fp, fp.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:int|const char \*|void)\s*\**\s*(\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for n in ("fftpde_create", "fftpde_destroy", "fftpde_strerror", "fft2d_forward", "fft2d_inverse",
+              "solve_poisson", "solve_diffusion", "solve_wave"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    fp, L = _lib()
+    for name in declared_functions():
+        assert hasattr(L, name), f"libfftpde.so does not export {name}"
+
+
+def test_strerror_and_version():
+    fp, L = _lib()
+    for code in (0, 1, -1, -2, -3, -4, -5, -6, -7, 99):
+        assert isinstance(fp.strerror(code), str) and fp.strerror(code)
+    assert "gfx950" in fp.version()
+
+
+def test_binding_fails_loudly_without_a_device_tensor():
+    fp, _ = _lib()
+    import torch
+    x = torch.zeros(4, 4, dtype=torch.complex64)
+    with pytest.raises(ValueError, match="ROCm device"):
+        fp.fft2d_forward(x)
+
+
+# A non-null dummy context: every call below has at least one invalid argument,
+# so the library must return EINVAL before it ever reads the context.
+_DUMMY = ctypes.create_string_buffer(64)
+DUMMY = ctypes.cast(_DUMMY, ctypes.c_void_p).value
+BUF = ctypes.create_string_buffer(256)
+P = (ctypes.cast(BUF, ctypes.c_void_p).value + 15) // 16 * 16  # 16-byte aligned "field"
+
+
+@pytest.mark.parametrize("nx,ny,batch,dtype", [
+    (3, 4, 1, 0), (4, 6, 1, 0), (1, 4, 1, 0), (4, 1, 1, 1), (8192, 4, 1, 0), (4, 8192, 1, 1),
+    (0, 4, 1, 0), (-4, 4, 1, 0), (4, 4, 0, 0), (4, 4, -1, 1), (4, 4, 1, 2), (4, 4, 1, -1),
+])
+def test_transforms_reject_bad_shape_or_dtype(nx, ny, batch, dtype):
+    fp, L = _lib()
+    assert L.fft2d_forward(DUMMY, P, P, nx, ny, batch, dtype, None) == fp.EINVAL
+    assert L.fft2d_inverse(DUMMY, P, P, nx, ny, batch, dtype, None) == fp.EINVAL
+    assert L.solve_poisson(DUMMY, P, P, nx, ny, batch, 1.0, 1.0, dtype, None) == fp.EINVAL
+
+
+def test_null_context_and_null_or_misaligned_pointers():
+    fp, L = _lib()
+    assert L.fft2d_forward(None, P, P, 4, 4, 1, 0, None) == fp.EINVAL
+    assert L.fft2d_forward(DUMMY, None, P, 4, 4, 1, 0, None) == fp.EINVAL
+    assert L.fft2d_forward(DUMMY, P, None, 4, 4, 1, 0, None) == fp.EINVAL
+    assert L.fft2d_forward(DUMMY, P + 4, P, 4, 4, 1, 0, None) == fp.EINVAL   # FP32 needs 8 B
+    assert L.fft2d_forward(DUMMY, P + 8, P, 4, 4, 1, 1, None) == fp.EINVAL   # FP64 needs 16 B
+    assert L.solve_wave(DUMMY, None, None, P, None, 4, 4, 1, 1.0, 1.0, 1.0, 0.5, 0, None) == fp.EINVAL
+
+
+@pytest.mark.parametrize("lx,ly", [(0.0, 1.0), (1.0, -1.0), (math.inf, 1.0), (1.0, math.nan)])
+def test_solves_reject_bad_box(lx, ly):
+    fp, L = _lib()
+    assert L.solve_poisson(DUMMY, P, P, 4, 4, 1, lx, ly, 0, None) == fp.EINVAL
+    assert L.solve_diffusion(DUMMY, P, P, 4, 4, 1, lx, ly, 0.1, 0.1, 0, None) == fp.EINVAL
+    assert L.solve_wave(DUMMY, P, None, P, None, 4, 4, 1, lx, ly, 1.0, 0.1, 0, None) == fp.EINVAL
+
+
+@pytest.mark.parametrize("kappa,t", [(-0.1, 1.0), (0.1, -1e-9), (math.nan, 1.0), (0.1, math.inf)])
+def test_diffusion_rejects_bad_coefficients_and_backward_time(kappa, t):
+    fp, L = _lib()
+    assert L.solve_diffusion(DUMMY, P, P, 4, 4, 1, 1.0, 1.0, kappa, t, 1, None) == fp.EINVAL
+
+
+def test_wave_rejects_bad_speed_time_and_aliasing():
+    fp, L = _lib()
+    assert L.solve_wave(DUMMY, P, None, P, None, 4, 4, 1, 1.0, 1.0, -1.0, 0.1, 0, None) == fp.EINVAL
+    assert L.solve_wave(DUMMY, P, None, P, None, 4, 4, 1, 1.0, 1.0, 1.0, math.nan, 0, None) == fp.EINVAL
+    # the velocity output may not alias the displacement
+    Q = P + 64
+    assert L.solve_wave(DUMMY, P, None, Q, Q, 4, 4, 1, 1.0, 1.0, 1.0, 0.1, 0, None) == fp.EINVAL
+    assert L.solve_wave(DUMMY, P, Q, Q, None, 4, 4, 1, 1.0, 1.0, 1.0, 0.1, 0, None) == fp.EINVAL
+
+
+def test_create_without_a_gpu_fails_cleanly():
+    fp, L = _lib()
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p(123)
+    rc = L.fftpde_create(ctypes.byref(h), 0)
+    assert rc != fp.OK and h.value is None
+    assert L.fftpde_destroy(None) == fp.OK
