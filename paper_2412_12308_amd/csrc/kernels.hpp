@@ -131,7 +131,9 @@ __device__ __forceinline__ void wave_coeffs(const SymParams& p, int a, int b, T&
   const double hx = p.hx * ai, hy = p.hy * bi;
   const double kx = p.kxs * ai, ky = p.kys * bi;
   const double w = p.c * sqrt(kx * kx + ky * ky);
+  // w t / pi; hx, hy carry t squared away, so restore its sign (sin is odd)
   double h = sqrt(hx * hx + hy * hy);
+  if (p.t < 0) h = -h;
   if constexpr (sizeof(T) == 4) {
     h -= 2.0 * rint(0.5 * h);
     float s, c;
