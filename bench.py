@@ -129,6 +129,10 @@ def main(argv=None):
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain elementwise copy of the FP32 batch (512 MiB at B = 16), "
+                         "the known-size reference for hardware byte counters")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported "
@@ -144,6 +148,14 @@ def main(argv=None):
         return 1
     print(f"# generating inputs: {a.batch} x {N_SIDE}^2", file=sys.stderr, flush=True)
     fields = make_inputs(N_SIDE, a.batch)
+    if a.copy_probe:
+        src = torch.from_numpy(fields).to(torch.complex64).to("cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.add(src, 0, out=dst)
+        torch.cuda.synchronize()
+        print(f"# copy probe: 3 x {src.numel() * 8} bytes read + written", file=sys.stderr, flush=True)
+        del src, dst
     print("# fp32 leg", file=sys.stderr, flush=True)
     r32 = run_leg(fp, torch, fields, "c64", a.steps, a.warmup)
     err32 = None if a.no_check else oracle_check(r32["last_out"][0], fields[0], "c64", r32["last_t"])
@@ -154,8 +166,10 @@ def main(argv=None):
         f64 = fields[: max(1, a.batch // 2)]
         r64 = run_leg(fp, torch, f64, "c128", a.steps, a.warmup)
         err64 = None if a.no_check else oracle_check(r64["last_out"][0], f64[0], "c128", r64["last_t"])
-    print("# cpu baseline", file=sys.stderr, flush=True)
-    cpu = cpu_baseline(fields[0], a.cpu_seconds)
+    cpu = None
+    if not a.no_cpu:
+        print("# cpu baseline", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(fields[0], a.cpu_seconds)
 
     dom = r32["dominant"]
     tol32 = 2 * 2e-6 * math.log2(N_SIDE)

@@ -102,6 +102,40 @@ const char *fftpde_last_error(void);
 int fftpde_profile(fftpde_ctx *ctx, int enable);
 int fftpde_profile_read(fftpde_ctx *ctx, char *buf, size_t cap, size_t *needed);
 
+/* ---- kernel plans -------------------------------------------------------
+ * Every pass is one of several compiled kernel variants (radix schedule,
+ * tile width, threads, LDS exchange, prefetch); each (dtype, pass, length,
+ * fields) slot has a default.
+ * fftpde_plan_variants: JSON array describing every compiled variant
+ *   ({"name", "dtype", "pass", "logn", "fields", ..., "active"}), written
+ *   like fftpde_profile_read.
+ * fftpde_plan_select: make the named variant the one used for its slot on
+ *   this context (FFTPDE_ENOTFOUND if no such name); NULL or "" restores every
+ *   slot's default.  Every variant computes the same transform; they differ
+ *   in speed and in rounding order only. */
+int fftpde_plan_variants(fftpde_ctx *ctx, char *buf, size_t cap, size_t *needed);
+int fftpde_plan_select(fftpde_ctx *ctx, const char *name);
+
+/* fftpde_autotune: for an (nx, ny, batch, dtype, op) solve (op one of
+ *   FFTPDE_POISSON / DIFFUSION / WAVE, zero initial velocity), time every
+ *   compiled variant of the row pass for nx and of the column pass for ny on
+ *   library-owned scratch fields filled with a fixed pseudo-random pattern,
+ *   `reps` timed solves each (HIP events on `stream`).  A variant is admitted
+ *   only if its result matches the plan in use at the call to relative L2
+ *   <= 1e-12 (C128) or 2 * 2e-6 * log2(max(nx, ny)) (C64); the fastest admitted
+ *   variant becomes this context's plan for its slot.  A JSON report
+ *   ({"candidates": [{"name", "pass", "us", "err", "ok"}], "row", "col"}) is
+ *   written like fftpde_profile_read (report may be NULL).  Synchronises the
+ *   stream; allocates and frees 3 * batch * nx * ny elements of scratch.
+ * fftpde_plan_save / fftpde_plan_load: write / apply the variants chosen on
+ *   this context as a text file, one variant name per line ('#' comments).
+ *   Loading a name that is not compiled in gives FFTPDE_ENOTFOUND (the other
+ *   lines still apply). */
+int fftpde_autotune(fftpde_ctx *ctx, int nx, int ny, int batch, int dtype, int op, int reps,
+                    fftpde_stream stream, char *report, size_t cap, size_t *needed);
+int fftpde_plan_save(fftpde_ctx *ctx, const char *path);
+int fftpde_plan_load(fftpde_ctx *ctx, const char *path);
+
 /* ---- 2D transforms (Sec. II.D, Eq. (2D_DFT); iDFT of Sec. II.B) ----------
  * fft2d_forward: out = unnormalised forward 2D transform of in, for each of
  *   `batch` fields.  Done as all x-direction (row) transforms for fixed y,

@@ -73,7 +73,15 @@ def _declare(L):
     L.fftpde_profile.argtypes = [vp, i]
     L.fftpde_profile_read.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t,
                                       ctypes.POINTER(ctypes.c_size_t)]
-    for f in ("fftpde_profile", "fftpde_profile_read", "fftpde_create", "fftpde_destroy", "fft2d_forward", "fft2d_inverse", "solve_poisson",
+    L.fftpde_plan_variants.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t,
+                                       ctypes.POINTER(ctypes.c_size_t)]
+    L.fftpde_plan_select.argtypes = [vp, ctypes.c_char_p]
+    L.fftpde_autotune.argtypes = [vp, i, i, i, i, i, i, vp, ctypes.c_char_p, ctypes.c_size_t,
+                                  ctypes.POINTER(ctypes.c_size_t)]
+    L.fftpde_plan_save.argtypes = [vp, ctypes.c_char_p]
+    L.fftpde_plan_load.argtypes = [vp, ctypes.c_char_p]
+    for f in ("fftpde_autotune", "fftpde_plan_save", "fftpde_plan_load", "fftpde_plan_variants",
+              "fftpde_plan_select", "fftpde_profile", "fftpde_profile_read", "fftpde_create", "fftpde_destroy", "fft2d_forward", "fft2d_inverse", "solve_poisson",
               "solve_diffusion", "solve_wave"):
         getattr(L, f).restype = i
 
@@ -134,6 +142,45 @@ def profile_read(device: int):
     buf = ctypes.create_string_buffer(max(2, need.value))
     _check(lib().fftpde_profile_read(context(device), buf, len(buf), None), "fftpde_profile_read")
     return json.loads(buf.value.decode())
+
+
+def plan_variants(device: int = 0):
+    """Every compiled kernel variant, with the one in use per slot marked active."""
+    import json
+    need = ctypes.c_size_t(0)
+    _check(lib().fftpde_plan_variants(context(device), None, 0, ctypes.byref(need)), "fftpde_plan_variants")
+    buf = ctypes.create_string_buffer(max(2, need.value))
+    _check(lib().fftpde_plan_variants(context(device), buf, len(buf), None), "fftpde_plan_variants")
+    return json.loads(buf.value.decode())
+
+
+def plan_select(name: Optional[str], device: int = 0):
+    """Use the named kernel variant for its slot (None restores all defaults)."""
+    _check(lib().fftpde_plan_select(context(device), None if name is None else name.encode()),
+           "fftpde_plan_select")
+
+
+def autotune(nx: int, ny: int, batch: int = 1, dtype: str = "c64", op: int = POISSON, reps: int = 5,
+             device: int = 0):
+    """Time every kernel variant for this solve shape and keep the fastest (see
+    fftpde_autotune); returns the library's JSON report as a dict."""
+    import json
+    torch = _torch()
+    code = {"c64": C64, "c128": C128}[dtype]
+    stream = torch.cuda.current_stream(device).cuda_stream
+    need = ctypes.c_size_t(0)
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(lib().fftpde_autotune(context(device), nx, ny, batch, code, op, reps, stream, buf, len(buf),
+                                 ctypes.byref(need)), "fftpde_autotune")
+    return json.loads(buf.value.decode())
+
+
+def plan_save(path: str, device: int = 0):
+    _check(lib().fftpde_plan_save(context(device), os.fsencode(path)), "fftpde_plan_save")
+
+
+def plan_load(path: str, device: int = 0):
+    _check(lib().fftpde_plan_load(context(device), os.fsencode(path)), "fftpde_plan_load")
 
 
 # ---------------------------------------------------------------------------

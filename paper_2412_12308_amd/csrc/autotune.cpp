@@ -1,0 +1,204 @@
+// autotune.cpp -- per-shape kernel selection.  For a (nx, ny, batch, dtype,
+// operator) problem every compiled variant of the row pass for nx and of the
+// column pass for ny is timed on scratch fields with HIP events; a variant is
+// admitted only if its result matches the current plan's result to the
+// dtype's tolerance; the fastest admitted variant becomes the context's plan
+// for that slot.  Plans can be written to and read from a text file (one
+// variant name per line).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <string>
+#include <vector>
+
+#include "../../include/fftpde.h"
+#include "context.hpp"
+#include "solve.hpp"
+#include "util.hpp"
+
+using namespace fftpde;
+
+namespace {
+
+int ilog2i(int n) {
+  int l = 0;
+  while ((1 << l) < n) l++;
+  return l;
+}
+
+struct Scratch {
+  void* in = nullptr;
+  void* out = nullptr;
+  void* ref = nullptr;
+  double* acc = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ~Scratch() {
+    if (in) (void)hipFree(in);
+    if (out) (void)hipFree(out);
+    if (ref) (void)hipFree(ref);
+    if (acc) (void)hipFree(acc);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  }
+};
+
+}  // namespace
+
+extern "C" int fftpde_autotune(fftpde_ctx* ctx, int nx, int ny, int batch, int dtype, int op, int reps,
+                               fftpde_stream stream, char* report, size_t cap, size_t* needed) {
+  if (!ctx || nx < 2 || ny < 2 || nx > 4096 || ny > 4096 || (nx & (nx - 1)) || (ny & (ny - 1)) || batch < 1 ||
+      (dtype != FFTPDE_C64 && dtype != FFTPDE_C128) || op < FFTPDE_POISSON || op > FFTPDE_WAVE)
+    return FFTPDE_EINVAL;
+  if (reps < 1) reps = 5;
+  Context* c = reinterpret_cast<Context*>(ctx);
+  int prev = -1;
+  (void)hipGetDevice(&prev);
+  if (prev != c->device) (void)hipSetDevice(c->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const long long n = (long long)nx * ny * batch;
+  const size_t bytes = (size_t)n * (dtype == FFTPDE_C64 ? 8 : 16);
+  const double tol = dtype == FFTPDE_C64 ? 2.0 * 2e-6 * std::log2((double)std::max(nx, ny)) : 1e-12;
+  Scratch sc;
+  int rc = FFTPDE_OK;
+  auto fail = [&](int code) {
+    if (prev >= 0 && prev != c->device) (void)hipSetDevice(prev);
+    return code;
+  };
+  if (hipMalloc(&sc.in, bytes) != hipSuccess || hipMalloc(&sc.out, bytes) != hipSuccess ||
+      hipMalloc(&sc.ref, bytes) != hipSuccess || hipMalloc(&sc.acc, 2 * sizeof(double)) != hipSuccess)
+    return fail(FFTPDE_ENOMEM);
+  if (hipEventCreate(&sc.e0) != hipSuccess || hipEventCreate(&sc.e1) != hipSuccess) return fail(FFTPDE_EDEVICE);
+  if (fill_pattern(sc.in, n, dtype, 12345u, s) != hipSuccess) return fail(FFTPDE_EDEVICE);
+  const double lx = 1.0, ly = 1.0, coef = op == FFTPDE_DIFFUSION ? 0.01 : 1.0, t = op == FFTPDE_POISSON ? 0.0 : 0.05;
+  auto solve = [&](void* out) { return run_solve(c, dtype, op, sc.in, nullptr, out, nullptr, nx, ny, batch, lx, ly, coef, t, s); };
+  rc = solve(sc.ref);
+  if (rc != FFTPDE_OK) return fail(rc);
+
+  // time the current plan of every slot, then each candidate in turn
+  auto time_solve = [&](double* us, double* err) -> int {
+    int r = solve(sc.out);  // warm-up (and occupancy queries)
+    if (r != FFTPDE_OK) return r;
+    if (hipEventRecord(sc.e0, s) != hipSuccess) return FFTPDE_EDEVICE;
+    for (int i = 0; i < reps && r == FFTPDE_OK; i++) r = solve(sc.out);
+    if (r != FFTPDE_OK) return r;
+    if (hipEventRecord(sc.e1, s) != hipSuccess || hipEventSynchronize(sc.e1) != hipSuccess) return FFTPDE_EDEVICE;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, sc.e0, sc.e1) != hipSuccess) return FFTPDE_EDEVICE;
+    *us = 1e3 * ms / reps;
+    if (zero_doubles(sc.acc, 2, s) != hipSuccess || diff_norms(sc.out, sc.ref, n, dtype, sc.acc, s) != hipSuccess)
+      return FFTPDE_EDEVICE;
+    double h[2] = {0, 0};
+    if (hipMemcpyAsync(h, sc.acc, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return FFTPDE_EDEVICE;
+    *err = h[1] > 0 ? std::sqrt(h[0] / h[1]) : std::sqrt(h[0]);
+    return FFTPDE_OK;
+  };
+
+  std::string out = "{\"nx\": " + std::to_string(nx) + ", \"ny\": " + std::to_string(ny) + ", \"batch\": " +
+                    std::to_string(batch) + ", \"dtype\": " + std::to_string(dtype) + ", \"op\": " +
+                    std::to_string(op) + ", \"candidates\": [";
+  bool first = true;
+  auto note = [&](const char* name, const char* pass, double us, double err, bool ok) {
+    char line[256];
+    std::snprintf(line, sizeof(line), "%s{\"name\": \"%s\", \"pass\": \"%s\", \"us\": %.3f, \"err\": %.3e, \"ok\": %d}",
+                  first ? "" : ", ", name, pass, us, err, ok ? 1 : 0);
+    out += line;
+    first = false;
+  };
+  const int lgx = ilog2i(nx), lgy = ilog2i(ny);
+  // rows
+  {
+    const int k = plan_key(dtype, 0, lgx, 1);
+    const RowVariant* best = c->row_variant(dtype, lgx);
+    double best_us = 1e30;
+    int cnt = 0;
+    const RowVariant* tab = dtype == FFTPDE_C64 ? row_variants_f32(&cnt) : row_variants_f64(&cnt);
+    const RowVariant* keep = c->row_choice[k];
+    for (int i = 0; i < cnt; i++) {
+      if (tab[i].logn != lgx) continue;
+      c->row_choice[k] = &tab[i];
+      double us = 0, err = 0;
+      rc = time_solve(&us, &err);
+      if (rc != FFTPDE_OK) {
+        c->row_choice[k] = keep;
+        return fail(rc);
+      }
+      const bool ok = err <= tol;
+      note(tab[i].name, "row", us, err, ok);
+      if (ok && us < best_us) {
+        best_us = us;
+        best = &tab[i];
+      }
+    }
+    c->row_choice[k] = best;
+  }
+  // columns
+  {
+    const int k = plan_key(dtype, 1, lgy, 1);
+    const ColVariant* best = c->col_variant(dtype, lgy, 1);
+    double best_us = 1e30;
+    int cnt = 0;
+    const ColVariant* tab = dtype == FFTPDE_C64 ? col_variants_f32_nf1(&cnt) : col_variants_f64_nf1(&cnt);
+    const ColVariant* keep = c->col_choice[k];
+    for (int i = 0; i < cnt; i++) {
+      if (tab[i].logn != lgy) continue;
+      c->col_choice[k] = &tab[i];
+      double us = 0, err = 0;
+      rc = time_solve(&us, &err);
+      if (rc != FFTPDE_OK) {
+        c->col_choice[k] = keep;
+        return fail(rc);
+      }
+      const bool ok = err <= tol;
+      note(tab[i].name, "col", us, err, ok);
+      if (ok && us < best_us) {
+        best_us = us;
+        best = &tab[i];
+      }
+    }
+    c->col_choice[k] = best;
+  }
+  out += "], \"row\": \"";
+  out += c->row_variant(dtype, lgx)->name;
+  out += "\", \"col\": \"";
+  out += c->col_variant(dtype, lgy, 1)->name;
+  out += "\"}";
+  if (prev >= 0 && prev != c->device) (void)hipSetDevice(prev);
+  if (needed) *needed = out.size() + 1;
+  if (report && cap >= out.size() + 1) std::memcpy(report, out.c_str(), out.size() + 1);
+  else if (report && cap) return FFTPDE_ENOMEM;
+  return FFTPDE_OK;
+}
+
+extern "C" int fftpde_plan_save(fftpde_ctx* ctx, const char* path) {
+  if (!ctx || !path) return FFTPDE_EINVAL;
+  Context* c = reinterpret_cast<Context*>(ctx);
+  std::ofstream f(path);
+  if (!f) return FFTPDE_EINVAL;
+  f << "# fftpde plan: one kernel variant per line\n";
+  for (int k = 0; k < kPlanSlots; k++) {
+    if (c->row_choice[k]) f << c->row_choice[k]->name << "\n";
+    if (c->col_choice[k]) f << c->col_choice[k]->name << "\n";
+  }
+  return f.good() ? FFTPDE_OK : FFTPDE_EINVAL;
+}
+
+extern "C" int fftpde_plan_load(fftpde_ctx* ctx, const char* path) {
+  if (!ctx || !path) return FFTPDE_EINVAL;
+  std::ifstream f(path);
+  if (!f) return FFTPDE_ENOTFOUND;
+  std::string line;
+  int rc = FFTPDE_OK;
+  while (std::getline(f, line)) {
+    while (!line.empty() && (line.back() == '\r' || line.back() == ' ')) line.pop_back();
+    if (line.empty() || line[0] == '#') continue;
+    const int r = fftpde_plan_select(ctx, line.c_str());
+    if (r != FFTPDE_OK) rc = r;
+  }
+  return rc;
+}

@@ -17,6 +17,7 @@
 #include "../../include/fftpde.h"
 #include "context.hpp"
 #include "kernels.hpp"
+#include "solve.hpp"
 
 using namespace fftpde;
 
@@ -138,6 +139,19 @@ int Context::workspace(size_t bytes, void** p) {
 
 void set_last_error(const char* what, hipError_t e) { set_error(what, e); }
 
+long long Context::max_blocks(const void* variant, OccFn occ) {
+  auto it = occupancy.find(variant);
+  int per = 0;
+  if (it != occupancy.end()) {
+    per = it->second;
+  } else {
+    per = occ ? occ() : 0;
+    occupancy[variant] = per;
+  }
+  if (per <= 0 || num_cus <= 0) return 0;  // unknown: one workgroup per tile
+  return (long long)per * num_cus;
+}
+
 hipEvent_t Context::take_event() {
   if (!event_pool.empty()) {
     hipEvent_t e = event_pool.back();
@@ -146,19 +160,6 @@ hipEvent_t Context::take_event() {
   }
   hipEvent_t e = nullptr;
   if (hipEventCreate(&e) != hipSuccess) return nullptr;
-  return e;
-}
-
-// Launch through `fn`, bracketed by events when profiling is on.
-template <class F>
-hipError_t timed_launch(Context* c, const char* name, double bytes, hipStream_t s, F&& fn) {
-  if (!c->profiling) return fn();
-  hipEvent_t a = c->take_event(), b = c->take_event();
-  if (!a || !b) return fn();
-  (void)hipEventRecord(a, s);
-  hipError_t e = fn();
-  (void)hipEventRecord(b, s);
-  c->timed.push_back({name, bytes, a, b});
   return e;
 }
 
@@ -195,6 +196,8 @@ int fftpde_create(fftpde_ctx** out, int device) {
   Context* c = new (std::nothrow) Context();
   if (!c) return FFTPDE_ENOMEM;
   c->device = device;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->num_cus = prop.multiProcessorCount;
   std::vector<cx<double>> t64(kTw);
   std::vector<cx<float>> t32(kTw);
   for (int e = 0; e < kTw; e++) {
@@ -273,6 +276,97 @@ int fftpde_profile_read(fftpde_ctx* ctx, char* buf, size_t cap, size_t* needed) 
   return FFTPDE_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+struct VariantRef {
+  const char* name;
+  int dtype, pass, logn, nf;
+  const RowVariant* row;
+  const ColVariant* col;
+};
+
+template <class F>
+void for_each_variant(F&& f) {
+  int n = 0;
+  const RowVariant* r32 = row_variants_f32(&n);
+  for (int i = 0; i < n; i++) f(VariantRef{r32[i].name, FFTPDE_C64, 0, r32[i].logn, 1, &r32[i], nullptr});
+  const RowVariant* r64 = row_variants_f64(&n);
+  for (int i = 0; i < n; i++) f(VariantRef{r64[i].name, FFTPDE_C128, 0, r64[i].logn, 1, &r64[i], nullptr});
+  const ColVariant* (*tabs[4])(int*) = {col_variants_f32_nf1, col_variants_f32_nf2, col_variants_f64_nf1,
+                                        col_variants_f64_nf2};
+  for (int k = 0; k < 4; k++) {
+    const ColVariant* t = tabs[k](&n);
+    for (int i = 0; i < n; i++)
+      f(VariantRef{t[i].name, k < 2 ? FFTPDE_C64 : FFTPDE_C128, 1, t[i].logn, t[i].nf, nullptr, &t[i]});
+  }
+}
+
+int copy_out(const std::string& text, char* buf, size_t cap, size_t* needed) {
+  if (needed) *needed = text.size() + 1;
+  if (!buf) return cap ? FFTPDE_EINVAL : FFTPDE_OK;
+  if (cap < text.size() + 1) return FFTPDE_ENOMEM;
+  std::memcpy(buf, text.c_str(), text.size() + 1);
+  return FFTPDE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fftpde_plan_variants(fftpde_ctx* ctx, char* buf, size_t cap, size_t* needed) {
+  if (!ctx) return FFTPDE_EINVAL;
+  Context* c = reinterpret_cast<Context*>(ctx);
+  std::string out = "[";
+  bool first = true;
+  for_each_variant([&](const VariantRef& v) {
+    const int k = plan_key(v.dtype, v.pass, v.logn, v.nf);
+    const bool chosen = v.row ? (c->row_variant(v.dtype, v.logn) == v.row)
+                              : (c->col_variant(v.dtype, v.logn, v.nf) == v.col);
+    (void)k;
+    char line[384];
+    if (v.row)
+      std::snprintf(line, sizeof(line),
+                    "%s{\"name\": \"%s\", \"dtype\": %d, \"pass\": \"row\", \"logn\": %d, \"fields\": 1, "
+                    "\"e\": %d, \"threads\": %d, \"lines\": %d, \"prefetch\": %d, \"lds\": %d, \"active\": %d}",
+                    first ? "" : ", ", v.name, v.dtype, v.logn, v.row->e, v.row->th, v.row->lines, v.row->pf,
+                    v.row->lds_bytes, chosen ? 1 : 0);
+    else
+      std::snprintf(line, sizeof(line),
+                    "%s{\"name\": \"%s\", \"dtype\": %d, \"pass\": \"col\", \"logn\": %d, \"fields\": %d, "
+                    "\"e\": %d, \"threads\": %d, \"cols\": %d, \"split\": %d, \"prefetch\": %d, \"lds\": %d, "
+                    "\"active\": %d}",
+                    first ? "" : ", ", v.name, v.dtype, v.logn, v.nf, v.col->e, v.col->th, 1 << v.col->logt,
+                    v.col->split, v.col->pf, v.col->lds_bytes, chosen ? 1 : 0);
+    out += line;
+    first = false;
+  });
+  out += "]";
+  return copy_out(out, buf, cap, needed);
+}
+
+int fftpde_plan_select(fftpde_ctx* ctx, const char* name) {
+  if (!ctx) return FFTPDE_EINVAL;
+  Context* c = reinterpret_cast<Context*>(ctx);
+  if (!name || !*name) {
+    for (int k = 0; k < kPlanSlots; k++) {
+      c->row_choice[k] = nullptr;
+      c->col_choice[k] = nullptr;
+    }
+    return FFTPDE_OK;
+  }
+  int rc = FFTPDE_ENOTFOUND;
+  for_each_variant([&](const VariantRef& v) {
+    if (rc == FFTPDE_OK || std::strcmp(v.name, name) != 0) return;
+    const int k = plan_key(v.dtype, v.pass, v.logn, v.nf);
+    if (v.row) c->row_choice[k] = v.row;
+    else c->col_choice[k] = v.col;
+    rc = FFTPDE_OK;
+  });
+  return rc;
+}
+
 int fftpde_destroy(fftpde_ctx* ctx) {
   if (!ctx) return FFTPDE_OK;
   Context* c = reinterpret_cast<Context*>(ctx);
@@ -291,117 +385,6 @@ int fftpde_destroy(fftpde_ctx* ctx) {
 }
 
 }  // extern "C"
-
-// ---------------------------------------------------------------------------
-// launch sequences
-// ---------------------------------------------------------------------------
-namespace fftpde {
-
-template <typename T>
-static const cx<T>* twiddles(const Context* c) {
-  if constexpr (sizeof(T) == 4) return c->tw32;
-  else return c->tw64;
-}
-
-template <typename T>
-int row_pass(Context* c, const void* in, void* out, int lognx, long long nrows, bool inverse, double scale,
-             hipStream_t s) {
-  const RowVariant* v = c->row_variant(sizeof(T) == 4 ? FFTPDE_C64 : FFTPDE_C128, lognx);
-  if (!v) return FFTPDE_EINVAL;
-  RowArgs<T> a{static_cast<const cx<T>*>(in), static_cast<cx<T>*>(out), twiddles<T>(c), nrows, inverse ? 1 : 0,
-               T(scale)};
-  const double bytes = 2.0 * sizeof(cx<T>) * (double)nrows * (double)(1 << lognx);
-  hipError_t e = timed_launch(c, v->name, bytes, s, [&] { return v->launch(&a, nrows, s); });
-  if (e != hipSuccess) {
-    set_last_error(v->name, e);
-    return FFTPDE_EDEVICE;
-  }
-  return FFTPDE_OK;
-}
-
-template <typename T>
-int col_pass(Context* c, const void* in0, const void* in1, void* out0, void* out1, int lognx, int logny,
-             long long batch, int mode, const SymParams& sym, int nf, hipStream_t s) {
-  const ColVariant* v = c->col_variant(sizeof(T) == 4 ? FFTPDE_C64 : FFTPDE_C128, logny, nf);
-  if (!v) return FFTPDE_EINVAL;
-  ColArgs<T> a{static_cast<const cx<T>*>(in0), static_cast<const cx<T>*>(in1), static_cast<cx<T>*>(out0),
-               static_cast<cx<T>*>(out1), twiddles<T>(c), batch << lognx, lognx, mode, sym};
-  const double field = sizeof(cx<T>) * (double)batch * (double)(1ll << (lognx + logny));
-  const double bytes = field * ((in0 ? 1 : 0) + (in1 ? 1 : 0) + (out0 ? 1 : 0) + (out1 ? 1 : 0));
-  hipError_t e = timed_launch(c, v->name, bytes, s, [&] { return v->launch(&a, batch << lognx, s); });
-  if (e != hipSuccess) {
-    set_last_error(v->name, e);
-    return FFTPDE_EDEVICE;
-  }
-  return FFTPDE_OK;
-}
-
-SymParams make_sym(int op, int nx, int ny, double lx, double ly, double coef, double t) {
-  SymParams p{};
-  p.op = op;
-  p.lognx = ilog2(nx);
-  p.logny = ilog2(ny);
-  p.kxs = 2.0 * kPi / lx;
-  p.kys = 2.0 * kPi / ly;
-  p.scale = 1.0 / ((double)nx * (double)ny);
-  if (op == kSymDiffusion) p.kt = coef * t;
-  if (op == kSymWave) {
-    p.c = coef;
-    p.t = t;
-    p.hx = 2.0 * coef * t / lx;
-    p.hy = 2.0 * coef * t / ly;
-  }
-  return p;
-}
-
-template <typename T>
-int transform(Context* c, const void* in, void* out, int nx, int ny, int batch, bool inverse, hipStream_t s) {
-  const int lx = ilog2(nx), ly = ilog2(ny);
-  SymParams sym = make_sym(kSymScale, nx, ny, 1.0, 1.0, 0.0, 0.0);
-  int rc;
-  if (!inverse) {
-    rc = row_pass<T>(c, in, out, lx, (long long)ny * batch, false, 1.0, s);
-    if (rc == FFTPDE_OK) rc = col_pass<T>(c, out, nullptr, out, nullptr, lx, ly, batch, kColForward, sym, 1, s);
-  } else {
-    rc = col_pass<T>(c, in, nullptr, out, nullptr, lx, ly, batch, kColInverse, sym, 1, s);
-    if (rc == FFTPDE_OK) rc = row_pass<T>(c, out, out, lx, (long long)ny * batch, true, 1.0, s);
-  }
-  return rc;
-}
-
-// forward rows -> fused column pass -> inverse rows, for one real symbol
-template <typename T>
-int solve_real_symbol(Context* c, const void* in, void* out, int nx, int ny, int batch, const SymParams& sym,
-                      hipStream_t s) {
-  const int lx = ilog2(nx), ly = ilog2(ny);
-  const long long nrows = (long long)ny * batch;
-  int rc = row_pass<T>(c, in, out, lx, nrows, false, 1.0, s);
-  if (rc == FFTPDE_OK) rc = col_pass<T>(c, out, nullptr, out, nullptr, lx, ly, batch, kColFwdMulInv, sym, 1, s);
-  if (rc == FFTPDE_OK) rc = row_pass<T>(c, out, out, lx, nrows, true, 1.0, s);
-  return rc;
-}
-
-template <typename T>
-int solve_wave_two(Context* c, const void* u0, const void* v0, void* u, void* v, int nx, int ny, int batch,
-                   const SymParams& sym, hipStream_t s) {
-  const int lx = ilog2(nx), ly = ilog2(ny);
-  const long long nrows = (long long)ny * batch;
-  void* vbuf = v;
-  if (v0 && !v) {
-    const size_t bytes = sizeof(cx<T>) * (size_t)nx * ny * batch;
-    int rc = c->workspace(bytes, &vbuf);
-    if (rc != FFTPDE_OK) return rc;
-  }
-  int rc = row_pass<T>(c, u0, u, lx, nrows, false, 1.0, s);
-  if (rc == FFTPDE_OK && v0) rc = row_pass<T>(c, v0, vbuf, lx, nrows, false, 1.0, s);
-  if (rc == FFTPDE_OK)
-    rc = col_pass<T>(c, u, v0 ? vbuf : nullptr, u, v, lx, ly, batch, kColFwdMulInv, sym, 2, s);
-  if (rc == FFTPDE_OK) rc = row_pass<T>(c, u, u, lx, nrows, true, 1.0, s);
-  if (rc == FFTPDE_OK && v) rc = row_pass<T>(c, v, v, lx, nrows, true, 1.0, s);
-  return rc;
-}
-
-}  // namespace fftpde
 
 // ---------------------------------------------------------------------------
 // entry points
@@ -431,9 +414,7 @@ int fft2d_forward(fftpde_ctx* ctx, const void* in, void* out, int nx, int ny, in
   if (rc != FFTPDE_OK) return rc;
   Context* c = reinterpret_cast<Context*>(ctx);
   DeviceGuard g(c->device);
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  return dtype == FFTPDE_C64 ? transform<float>(c, in, out, nx, ny, batch, false, s)
-                             : transform<double>(c, in, out, nx, ny, batch, false, s);
+  return run_transform(c, dtype, false, in, out, nx, ny, batch, static_cast<hipStream_t>(stream));
 }
 
 int fft2d_inverse(fftpde_ctx* ctx, const void* in, void* out, int nx, int ny, int batch, int dtype,
@@ -444,9 +425,7 @@ int fft2d_inverse(fftpde_ctx* ctx, const void* in, void* out, int nx, int ny, in
   if (rc != FFTPDE_OK) return rc;
   Context* c = reinterpret_cast<Context*>(ctx);
   DeviceGuard g(c->device);
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  return dtype == FFTPDE_C64 ? transform<float>(c, in, out, nx, ny, batch, true, s)
-                             : transform<double>(c, in, out, nx, ny, batch, true, s);
+  return run_transform(c, dtype, true, in, out, nx, ny, batch, static_cast<hipStream_t>(stream));
 }
 
 int solve_poisson(fftpde_ctx* ctx, const void* s_in, void* u, int nx, int ny, int batch, double lx, double ly,
@@ -458,10 +437,8 @@ int solve_poisson(fftpde_ctx* ctx, const void* s_in, void* u, int nx, int ny, in
   if (rc != FFTPDE_OK) return rc;
   Context* c = reinterpret_cast<Context*>(ctx);
   DeviceGuard g(c->device);
-  const SymParams sym = make_sym(kSymPoisson, nx, ny, lx, ly, 0.0, 0.0);
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  return dtype == FFTPDE_C64 ? solve_real_symbol<float>(c, s_in, u, nx, ny, batch, sym, s)
-                             : solve_real_symbol<double>(c, s_in, u, nx, ny, batch, sym, s);
+  return run_solve(c, dtype, FFTPDE_POISSON, s_in, nullptr, u, nullptr, nx, ny, batch, lx, ly, 0.0, 0.0,
+                   static_cast<hipStream_t>(stream));
 }
 
 int solve_diffusion(fftpde_ctx* ctx, const void* u0, void* u, int nx, int ny, int batch, double lx, double ly,
@@ -475,10 +452,8 @@ int solve_diffusion(fftpde_ctx* ctx, const void* u0, void* u, int nx, int ny, in
   if (rc != FFTPDE_OK) return rc;
   Context* c = reinterpret_cast<Context*>(ctx);
   DeviceGuard g(c->device);
-  const SymParams sym = make_sym(kSymDiffusion, nx, ny, lx, ly, kappa, t);
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  return dtype == FFTPDE_C64 ? solve_real_symbol<float>(c, u0, u, nx, ny, batch, sym, s)
-                             : solve_real_symbol<double>(c, u0, u, nx, ny, batch, sym, s);
+  return run_solve(c, dtype, FFTPDE_DIFFUSION, u0, nullptr, u, nullptr, nx, ny, batch, lx, ly, kappa, t,
+                   static_cast<hipStream_t>(stream));
 }
 
 int solve_wave(fftpde_ctx* ctx, const void* u0, const void* v0, void* u, void* v, int nx, int ny, int batch,
@@ -495,13 +470,8 @@ int solve_wave(fftpde_ctx* ctx, const void* u0, const void* v0, void* u, void* v
   if (rc != FFTPDE_OK) return rc;
   Context* c = reinterpret_cast<Context*>(ctx);
   DeviceGuard g(c->device);
-  const SymParams sym = make_sym(kSymWave, nx, ny, lx, ly, c_speed, t);
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  if (!v0 && !v)
-    return dtype == FFTPDE_C64 ? solve_real_symbol<float>(c, u0, u, nx, ny, batch, sym, s)
-                               : solve_real_symbol<double>(c, u0, u, nx, ny, batch, sym, s);
-  return dtype == FFTPDE_C64 ? solve_wave_two<float>(c, u0, v0, u, v, nx, ny, batch, sym, s)
-                             : solve_wave_two<double>(c, u0, v0, u, v, nx, ny, batch, sym, s);
+  return run_solve(c, dtype, FFTPDE_WAVE, u0, v0, u, v, nx, ny, batch, lx, ly, c_speed, t,
+                   static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

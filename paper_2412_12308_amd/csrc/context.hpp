@@ -6,6 +6,7 @@
 
 #include <cstddef>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "kernels.hpp"
@@ -38,6 +39,11 @@ struct Context {
   std::vector<TimedLaunch> timed;
   std::vector<hipEvent_t> event_pool;
   hipEvent_t take_event();
+
+  int num_cus = 0;
+  std::unordered_map<const void*, int> occupancy;  // variant -> resident workgroups per CU
+  // Workgroup cap for a persistent (prefetching) launch: all resident at once.
+  long long max_blocks(const void* variant, OccFn occ);
 
   const RowVariant* row_variant(int dtype, int logn) const;
   const ColVariant* col_variant(int dtype, int logn, int nf) const;

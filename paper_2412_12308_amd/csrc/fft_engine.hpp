@@ -31,6 +31,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace fftpde {
 
 constexpr int kTwLog = 12;  // twiddle table: 2^12 entries, the largest side
@@ -69,6 +71,24 @@ __device__ __forceinline__ cx<T> mul_mi(cx<T> a) {
 template <typename T>
 __device__ __forceinline__ cx<T> mulc(cx<T> a, T c, T s) {
   return {a.re * c - a.im * s, a.re * s + a.im * c};
+}
+
+// Workgroup barrier that orders LDS only: outstanding global loads (the next
+// tile's prefetch) stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Returns v unchanged but opaque to the optimiser.  Used on the thread index
+// once per tile so that per-element addresses are recomputed inside the
+// persistent tile loop instead of being hoisted out of it and held in
+// registers for the whole kernel.  (An empty asm with a register operand:
+// no instruction is emitted and no memory is touched.)
+__device__ __forceinline__ int opaque(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
 }
 
 // ---------------------------------------------------------------------------
@@ -193,49 +213,83 @@ constexpr int plan_max_lr(int logn, int maxlr) {
 
 // ---------------------------------------------------------------------------
 // Line maps: how a butterfly index g splits into (line, j) and where element
-// n of a line lives in LDS.
+// n of a line lives in LDS.  Element n is stored at padded position
+// n + floor(n / P), P = 2^LP, which spreads the strided accesses of the
+// exchanges over the LDS banks.  The engine picks P so that within every
+// butterfly the R positions it writes or reads are one base plus a
+// compile-time stride, which the LDS instructions take as an immediate.
 // ---------------------------------------------------------------------------
 
-// Rows: j fastest, so consecutive lanes walk along a row.  One padding
-// element every 8 spreads the stride-R writes of the early stages over banks.
-template <int LOGN, int LINES>
+// Rows: j fastest, so consecutive lanes walk along a row.
+template <int LOGN, int LINES, int LP>
 struct RowMap {
+  static constexpr int kLP = LP;
   static constexpr int N = 1 << LOGN;
-  static constexpr int kStride = N + (N >> 3);
+  static constexpr int kUnit = 1;  // LDS words between lines' neighbours in n
+  static constexpr int kStride = N + (N >> LP);
   static constexpr int kLdsElems = LINES * kStride;
   __device__ __forceinline__ static void split(int g, int lm, int& line, int& j) {
     j = g & ((1 << lm) - 1);
     line = g >> lm;
   }
-  __device__ __forceinline__ static int lds(int line, int n) { return line * kStride + n + (n >> 3); }
+  __device__ __forceinline__ static int lds(int line, int n) { return line * kStride + n + (n >> LP); }
 };
 
 // Columns: the T lines of a tile fastest, so a wavefront covers T adjacent
 // columns of 64/T consecutive rows (T * element size bytes per row segment).
-template <int LOGN, int LOGT>
+template <int LOGN, int LOGT, int LP>
 struct ColMap {
+  static constexpr int kLP = LP;
   static constexpr int N = 1 << LOGN;
   static constexpr int T = 1 << LOGT;
-  static constexpr int kLdsElems = (N + (N >> 3)) * T;
+  static constexpr int kUnit = T;
+  static constexpr int kLdsElems = (N + (N >> LP)) * T;
   __device__ __forceinline__ static void split(int g, int lm, int& line, int& j) {
     line = g & (T - 1);
     j = g >> LOGT;
     (void)lm;
   }
-  __device__ __forceinline__ static int lds(int line, int n) { return (n + (n >> 3)) * T + line; }
+  __device__ __forceinline__ static int lds(int line, int n) { return (n + (n >> LP)) * T + line; }
 };
+
+// Affine padding: with P = 2^lp, stage s's writes (groups of R outputs at
+// stride Ns starting at a multiple of R*Ns plus k < Ns) and the next stage's
+// reads (R inputs at stride N/R) must each stay affine in t: either the stride
+// is a multiple of P, or the whole group lies inside one P-aligned block.
+constexpr bool plan_affine(int logn, int maxlr, bool rev, int lp) {
+  const int ns = plan_nstages(logn, maxlr);
+  for (int s = 0; s + 1 < ns; s++) {
+    const int lr = plan_lr(logn, maxlr, s, rev), lns = plan_lns(logn, maxlr, s, rev);
+    const bool w_ok = lns >= lp || lns + lr <= lp;
+    const int lr2 = plan_lr(logn, maxlr, s + 1, rev);
+    const bool r_ok = logn - lr2 >= lp;
+    if (!w_ok || !r_ok) return false;
+  }
+  return true;
+}
+// the padding granularity used by an engine: the finest affine P among 2^3..2^6
+// (finer padding spreads more), else P = 2^5 with per-element addressing
+constexpr int plan_pad(int logn, int maxlr, bool rev) {
+  for (int lp = 3; lp <= 6; lp++)
+    if (plan_affine(logn, maxlr, rev, lp)) return lp;
+  return 5;
+}
 
 // ---------------------------------------------------------------------------
 // The engine.  x[q R + t] holds element (line(g), j(g) + t N/R) of the
 // current stage's input, g = tid + TH q.
 // ---------------------------------------------------------------------------
-template <typename T, int LOGN, int E, int TH, int MAXLR, bool REV, class Map>
+template <typename T, int LOGN, int E, int TH, int MAXLR, bool REV, class Map, bool SPLIT = false>
 struct Engine {
   static constexpr int N = 1 << LOGN;
   static constexpr int NST = plan_nstages(LOGN, MAXLR);
   static_assert(NST >= 1, "length must be at least 2");
   static_assert((E & (E - 1)) == 0 && E >= (1 << plan_max_lr(LOGN, MAXLR)),
                 "elements per thread must be a multiple of every radix");
+  // LDS words per exchange buffer: complex values, or (SPLIT) one real
+  // component at a time, which halves the buffer at twice the barriers.
+  using Word = typename std::conditional<SPLIT, T, cx<T>>::type;
+  static constexpr int kLdsWords = NST > 1 ? Map::kLdsElems : 1;
 
   template <int S>
   static constexpr int lr() { return plan_lr(LOGN, MAXLR, S, REV); }
@@ -267,42 +321,204 @@ struct Engine {
     for_each<NST - 1>(tid, f);
   }
 
-  template <int S = 0>
-  __device__ __forceinline__ static void run(cx<T> (&x)[E], cx<T>* lds, const cx<T>* __restrict__ tw,
-                                             int tid) {
+  // Stage S's outputs go to LDS; stage S+1's inputs come back.  When the map's
+  // padding is affine for this plan, each butterfly's R positions are one
+  // base plus a compile-time stride (an immediate LDS offset).
+  template <int S>
+  __device__ __forceinline__ static void exchange(cx<T> (&x)[E], Word* lds, int tid) {
     constexpr int LR = lr<S>();
     constexpr int R = 1 << LR;
     constexpr int LNS = lns<S>();
     constexpr int NS = 1 << LNS;
-    constexpr int M = N >> LR;
-#pragma unroll
-    for (int q = 0; q < E / R; q++) {
-      cx<T>* v = &x[q * R];
-      if constexpr (NS > 1) {
-        int line, j;
-        Map::split(tid + TH * q, LOGN - LR, line, j);
-        const int k = j & (NS - 1);
-#pragma unroll
-        for (int t = 1; t < R; t++) v[t] = cmul(v[t], tw[(t * k) << (kTwLog - LNS - LR)]);
-      }
-      dft<R>(v);
-    }
-    if constexpr (S + 1 < NST) {
+    constexpr int LR2 = lr<S + 1>();
+    constexpr int R2 = 1 << LR2;
+    constexpr int M2 = N >> LR2;
+    constexpr int LP = Map::kLP;
+    constexpr bool kAffine = plan_affine(LOGN, MAXLR, REV, LP);
+    // padded distance of a step d within a group (d multiple of P, or the
+    // group inside one P-block)
+    constexpr int wstep = (LNS >= LP ? NS + (NS >> LP) : NS) * Map::kUnit;
+    constexpr int rstep = (M2 + (M2 >> LP)) * Map::kUnit;
+    auto put = [&](auto get) {
 #pragma unroll
       for (int q = 0; q < E / R; q++) {
         int line, j;
         Map::split(tid + TH * q, LOGN - LR, line, j);
         const int k = j & (NS - 1);
         const int o = ((j - k) << LR) + k;
+        if constexpr (kAffine) {
+          Word* b = lds + Map::lds(line, o);
 #pragma unroll
-        for (int t = 0; t < R; t++) lds[Map::lds(line, o + t * NS)] = x[q * R + t];
+          for (int t = 0; t < R; t++) b[t * wstep] = get(x[q * R + t]);
+        } else {
+#pragma unroll
+          for (int t = 0; t < R; t++) lds[Map::lds(line, o + t * NS)] = get(x[q * R + t]);
+        }
       }
-      __syncthreads();
-      for_each<S + 1>(tid, [&](int i, int line, int n) { x[i] = lds[Map::lds(line, n)]; });
-      __syncthreads();
-      run<S + 1>(x, lds, tw, tid);
+    };
+    auto take = [&](auto set) {
+#pragma unroll
+      for (int q = 0; q < E / R2; q++) {
+        int line, j;
+        Map::split(tid + TH * q, LOGN - LR2, line, j);
+        if constexpr (kAffine) {
+          const Word* b = lds + Map::lds(line, j);
+#pragma unroll
+          for (int t = 0; t < R2; t++) set(x[q * R2 + t], b[t * rstep]);
+        } else {
+#pragma unroll
+          for (int t = 0; t < R2; t++) set(x[q * R2 + t], lds[Map::lds(line, j + t * M2)]);
+        }
+      }
+    };
+    if constexpr (SPLIT) {
+      put([](const cx<T>& v) { return v.re; });
+      lds_barrier();
+      take([](cx<T>& v, T w) { v.re = w; });
+      lds_barrier();
+      put([](const cx<T>& v) { return v.im; });
+      lds_barrier();
+      take([](cx<T>& v, T w) { v.im = w; });
+      lds_barrier();
+    } else {
+      put([](const cx<T>& v) { return v; });
+      lds_barrier();
+      take([](cx<T>& v, const cx<T>& w) { v = w; });
+      lds_barrier();
     }
-    (void)M;
+  }
+
+  // Twiddles of stage S for this thread: w_{Ns R}^{t k}, t = 1..R-1, per butterfly.
+  template <int S>
+  static constexpr int twn() {
+    return lns<S>() > 0 ? (E >> lr<S>()) * ((1 << lr<S>()) - 1) : 0;
+  }
+  // offset of stage S's twiddles in the all-stage register set
+  template <int S>
+  static constexpr int twoff() {
+    if constexpr (S == 0) return 0;
+    else return twoff<S - 1>() + twn<S - 1>();
+  }
+  static constexpr int kTwAll = twoff<NST - 1>() + twn<NST - 1>();
+  static constexpr int kTwRegs = kTwAll > 0 ? kTwAll : 1;
+
+  // Where a stage finds its twiddles:
+  //   TwSrc::global  the global table, requested one stage ahead so the load
+  //                  latency hides behind the previous LDS exchange;
+  //   TwSrc::regs    all stages' twiddles held in registers (they do not
+  //                  depend on the tile, so a persistent workgroup loads them
+  //                  once);
+  //   TwSrc::lds     a workgroup copy of w_N^e, e < N, in LDS.
+  enum class TwSrc { global, regs, lds };
+
+  template <int S, class W>
+  __device__ __forceinline__ static void load_tw(W& w, int off, const cx<T>* __restrict__ tw, int tid) {
+    constexpr int LR = lr<S>();
+    constexpr int R = 1 << LR;
+    constexpr int LNS = lns<S>();
+    constexpr int NS = 1 << LNS;
+    if constexpr (NS > 1) {
+#pragma unroll
+      for (int q = 0; q < E / R; q++) {
+        int line, j;
+        Map::split(tid + TH * q, LOGN - LR, line, j);
+        const int k = j & (NS - 1);
+#pragma unroll
+        for (int t = 1; t < R; t++) w[off + q * (R - 1) + t - 1] = tw[(t * k) << (kTwLog - LNS - LR)];
+      }
+    }
+  }
+
+  // All stages' twiddles into registers (for TwSrc::regs).
+  template <int S = 1>
+  __device__ __forceinline__ static void load_all_tw(cx<T> (&w)[kTwRegs], const cx<T>* __restrict__ tw, int tid) {
+    if constexpr (S < NST) {
+      load_tw<S>(w, twoff<S>(), tw, tid);
+      load_all_tw<S + 1>(w, tw, tid);
+    }
+  }
+
+  // The N-point roots w_N^e for e < N into LDS (for TwSrc::lds); the caller
+  // synchronises before use.
+  __device__ __forceinline__ static void load_lds_table(cx<T>* twl, const cx<T>* __restrict__ tw, int tid) {
+    for (int e = tid; e < N; e += TH) twl[e] = tw[e << (kTwLog - LOGN)];
+  }
+
+  // Stage S on registers; `w` is the twiddle set (registers) and `off` where
+  // stage S's twiddles start in it.
+  template <int S, TwSrc SRC, class W>
+  __device__ __forceinline__ static void stage(cx<T> (&x)[E], Word* lds, const cx<T>* __restrict__ tw,
+                                               const cx<T>* twl, int tid, W& w) {
+    constexpr int LR = lr<S>();
+    constexpr int R = 1 << LR;
+    constexpr int LNS = lns<S>();
+    constexpr int NS = 1 << LNS;
+    constexpr int off = SRC == TwSrc::regs ? twoff<S>() : 0;
+#pragma unroll
+    for (int q = 0; q < E / R; q++) {
+      cx<T>* v = &x[q * R];
+      if constexpr (NS > 1) {
+        if constexpr (SRC == TwSrc::lds) {
+          int line, j;
+          Map::split(tid + TH * q, LOGN - LR, line, j);
+          const int k = j & (NS - 1);
+#pragma unroll
+          for (int t = 1; t < R; t++) v[t] = cmul(v[t], twl[(t * k) << (LOGN - LNS - LR)]);
+        } else {
+#pragma unroll
+          for (int t = 1; t < R; t++) v[t] = cmul(v[t], w[off + q * (R - 1) + t - 1]);
+        }
+      }
+      dft<R>(v);
+    }
+    if constexpr (S + 1 < NST) {
+      if constexpr (SRC == TwSrc::global) {
+        cx<T> wn[twn<S + 1>() > 0 ? twn<S + 1>() : 1];
+        load_tw<S + 1>(wn, 0, tw, tid);
+        exchange<S>(x, lds, tid);
+        stage<S + 1, SRC>(x, lds, tw, twl, tid, wn);
+      } else {
+        exchange<S>(x, lds, tid);
+        stage<S + 1, SRC>(x, lds, tw, twl, tid, w);
+      }
+    }
+  }
+
+  // Global-table twiddles.
+  __device__ __forceinline__ static void run(cx<T> (&x)[E], Word* lds, const cx<T>* __restrict__ tw, int tid) {
+    cx<T> w0[1];
+    stage<0, TwSrc::global>(x, lds, tw, nullptr, tid, w0);
+  }
+  // Register twiddles from load_all_tw.
+  __device__ __forceinline__ static void run_regs(cx<T> (&x)[E], Word* lds, const cx<T> (&w)[kTwRegs], int tid) {
+    stage<0, TwSrc::regs>(x, lds, nullptr, nullptr, tid, w);
+  }
+  // LDS table twiddles from load_lds_table.
+  __device__ __forceinline__ static void run_lds(cx<T> (&x)[E], Word* lds, const cx<T>* twl, int tid) {
+    cx<T> w0[1];
+    stage<0, TwSrc::lds>(x, lds, nullptr, twl, tid, w0);
+  }
+};
+
+// Persistent tile schedule: workgroup b of G walks tiles b0, b0 + step, ...
+// When G is a multiple of the 8 XCDs (workgroups are dealt to XCDs round
+// robin), each XCD gets one contiguous range of tiles, so neighbouring tiles
+// (which can share 128-byte lines) meet in the same L2.
+struct TileWalk {
+  long long next, end, step;
+  __device__ __forceinline__ TileWalk(long long ntiles) {
+    const int G = gridDim.x, b = blockIdx.x;
+    if ((G & 7) == 0 && ntiles >= G) {
+      const int x = b & 7, per = G >> 3;
+      const long long lo = ntiles * x / 8, hi = ntiles * (x + 1) / 8;
+      next = lo + (b >> 3);
+      end = hi;
+      step = per;
+    } else {
+      next = b;
+      end = ntiles;
+      step = G;
+    }
   }
 };
 

@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "fft_engine.hpp"
 
 namespace fftpde {
@@ -32,6 +34,9 @@ enum SymOp : int {
   kSymDiffusion = 2,  // exp(-kappa |k|^2 t)           (Eq. (solCalorFourier))
   kSymWave = 3,       // cos(w t); with a velocity field the full propagator
 };
+
+// Where the passes read their twiddles (see Engine::TwSrc).
+enum TwMode : int { kTwGlobal = 0, kTwRegs = 1, kTwLds = 2 };
 
 struct SymParams {
   int op;
@@ -71,284 +76,496 @@ __device__ __forceinline__ int signed_index(int a, int logn) {
   return a < (1 << (logn - 1)) ? a : a - (1 << logn);
 }
 
-// Real symbol M(a, b) for the single-field solves (scale folded in).
+// ---------------------------------------------------------------------------
+// Spectral symbols.  A column tile holds one x frequency a per line, so each
+// evaluator is built once per column (terms in k_x) and then called for each
+// y frequency b.  The multipliers include the inverse's 1/(nx ny).
+// ---------------------------------------------------------------------------
+
+// sqrt of a non-negative FP64 value to about 1e-14 relative: an FP32 square
+// root refined by one Newton step in FP64 (the error squares), cheaper than
+// the correctly rounded FP64 root and ample for an FP32 result.
+__device__ __forceinline__ double sqrt_fp64_from_fp32(double v) {
+  const float s0 = __builtin_amdgcn_sqrtf(float(v));
+  const double d = double(s0);
+  const double r = fma(-d, d, v);
+  const double h = fma(r, double(0.5f * __builtin_amdgcn_rcpf(s0)), d);
+  return v > 0.0 ? h : 0.0;
+}
+
+template <typename T, int OP>
+struct Symbol;
+
+// -1/|k|^2, k = 0 -> 0 (Eq. (SolutionPoisson) with the mean dropped, Eq. (Poisson2))
 template <typename T>
-__device__ __forceinline__ T symbol_real(const SymParams& p, int a, int b);
-
-template <>
-__device__ __forceinline__ float symbol_real<float>(const SymParams& p, int a, int b) {
-  const int ai = signed_index(a, p.lognx), bi = signed_index(b, p.logny);
-  switch (p.op) {
-    case kSymPoisson: {
-      if (ai == 0 && bi == 0) return 0.0f;
-      const float kx = float(p.kxs) * float(ai), ky = float(p.kys) * float(bi);
-      return -float(p.scale) / (kx * kx + ky * ky);
-    }
-    case kSymDiffusion: {
-      const double kx = p.kxs * ai, ky = p.kys * bi;
-      const double arg = p.kt * (kx * kx + ky * ky);  // FP64 exponent
-      return float(p.scale) * expf(-float(arg));
-    }
-    case kSymWave: {
-      const double hx = p.hx * ai, hy = p.hy * bi;
-      double h = sqrt(hx * hx + hy * hy);  // w t / pi in FP64
-      h -= 2.0 * rint(0.5 * h);           // exact reduction to [-1, 1]
-      return float(p.scale) * cospif(float(h));
-    }
-    default:
-      return float(p.scale);
+struct Symbol<T, kSymPoisson> {
+  T kx2, kys, nscale;
+  bool a0;
+  int logny;
+  __device__ __forceinline__ Symbol(const SymParams& p, int a) {
+    const int ai = signed_index(a, p.lognx);
+    const T kx = T(p.kxs) * T(ai);
+    kx2 = kx * kx;
+    kys = T(p.kys);
+    nscale = -T(p.scale);
+    a0 = ai == 0;
+    logny = p.logny;
   }
-}
-
-template <>
-__device__ __forceinline__ double symbol_real<double>(const SymParams& p, int a, int b) {
-  const int ai = signed_index(a, p.lognx), bi = signed_index(b, p.logny);
-  switch (p.op) {
-    case kSymPoisson: {
-      if (ai == 0 && bi == 0) return 0.0;
-      const double kx = p.kxs * ai, ky = p.kys * bi;
-      return -p.scale / (kx * kx + ky * ky);
-    }
-    case kSymDiffusion: {
-      const double kx = p.kxs * ai, ky = p.kys * bi;
-      return p.scale * exp(-p.kt * (kx * kx + ky * ky));
-    }
-    case kSymWave: {
-      const double hx = p.hx * ai, hy = p.hy * bi;
-      return p.scale * cospi(sqrt(hx * hx + hy * hy));
-    }
-    default:
-      return p.scale;
+  __device__ __forceinline__ T operator()(int b) const {
+    const int bi = signed_index(b, logny);
+    const T ky = kys * T(bi);
+    const T k2 = kx2 + ky * ky;
+    T m;
+    if constexpr (sizeof(T) == 4) m = nscale * __builtin_amdgcn_rcpf(k2);
+    else m = nscale / k2;
+    return (a0 && bi == 0) ? T(0) : m;
   }
-}
+};
 
-// Wave propagator coefficients at mode (a, b): cw = cos(w t), sw = sin(w t),
+// exp(-kappa |k|^2 t) (Eq. (solCalorFourier)); exponent formed in FP64
+template <typename T>
+struct Symbol<T, kSymDiffusion> {
+  double ex, kt, kys;
+  T scale;
+  int logny;
+  __device__ __forceinline__ Symbol(const SymParams& p, int a) {
+    const double kx = p.kxs * signed_index(a, p.lognx);
+    kt = p.kt;
+    ex = kt * kx * kx;
+    kys = p.kys;
+    scale = T(p.scale);
+    logny = p.logny;
+  }
+  __device__ __forceinline__ T operator()(int b) const {
+    const double ky = kys * signed_index(b, logny);
+    const double arg = fma(kt * ky, ky, ex);
+    if constexpr (sizeof(T) == 4) return scale * expf(-float(arg));
+    else return scale * exp(-arg);
+  }
+};
+
+// cos(c |k| t), the wave propagator with zero initial velocity
+// (Eq. (OmegaNonZero), (OmegaZero)); phase in FP64 half-turns, reduced in FP64
+template <typename T>
+struct Symbol<T, kSymWave> {
+  double hx2, hy;
+  T scale;
+  int logny;
+  __device__ __forceinline__ Symbol(const SymParams& p, int a) {
+    const double hx = p.hx * signed_index(a, p.lognx);
+    hx2 = hx * hx;
+    hy = p.hy;
+    scale = T(p.scale);
+    logny = p.logny;
+  }
+  __device__ __forceinline__ T operator()(int b) const {
+    const double hyb = hy * signed_index(b, logny);
+    const double h2 = fma(hyb, hyb, hx2);
+    if constexpr (sizeof(T) == 4) {
+      double h = sqrt_fp64_from_fp32(h2);  // w t / pi
+      h = fma(-2.0, rint(0.5 * h), h);     // exact reduction to [-1, 1]
+      return scale * cospif(float(h));
+    } else {
+      return scale * cospi(sqrt(h2));
+    }
+  }
+};
+
+template <typename T>
+struct Symbol<T, kSymScale> {
+  T scale;
+  __device__ __forceinline__ Symbol(const SymParams& p, int) : scale(T(p.scale)) {}
+  __device__ __forceinline__ T operator()(int) const { return scale; }
+};
+
+// Wave propagator with an initial velocity: cw = cos(w t), sw = sin(w t),
 // sow = sin(w t)/w (t at w = 0), w = c |k|; all but the final rounding in FP64.
 template <typename T>
-__device__ __forceinline__ void wave_coeffs(const SymParams& p, int a, int b, T& cw, T& sw, T& sow,
-                                            T& w_out) {
-  const int ai = signed_index(a, p.lognx), bi = signed_index(b, p.logny);
-  const double hx = p.hx * ai, hy = p.hy * bi;
-  const double kx = p.kxs * ai, ky = p.kys * bi;
-  const double w = p.c * sqrt(kx * kx + ky * ky);
-  // w t / pi; hx, hy carry t squared away, so restore its sign (sin is odd)
-  double h = sqrt(hx * hx + hy * hy);
-  if (p.t < 0) h = -h;
-  if constexpr (sizeof(T) == 4) {
-    h -= 2.0 * rint(0.5 * h);
-    float s, c;
-    sincospif(float(h), &s, &c);
-    cw = c;
-    sw = s;
-    sow = w == 0.0 ? T(p.t) : T(double(s) / w);
-  } else {
-    double s, c;
-    sincospi(h, &s, &c);
-    cw = c;
-    sw = s;
-    sow = w == 0.0 ? p.t : s / w;
+struct WaveCoeffs {
+  double hx2, hy, kx2, kys, c, t;
+  int logny;
+  __device__ __forceinline__ WaveCoeffs(const SymParams& p, int a) {
+    const int ai = signed_index(a, p.lognx);
+    const double hx = p.hx * ai, kx = p.kxs * ai;
+    hx2 = hx * hx;
+    kx2 = kx * kx;
+    hy = p.hy;
+    kys = p.kys;
+    c = p.c;
+    t = p.t;
+    logny = p.logny;
   }
-  w_out = T(w);
-}
+  __device__ __forceinline__ void operator()(int b, T& cw, T& sw, T& sow, T& w_out) const {
+    const int bi = signed_index(b, logny);
+    const double hyb = hy * bi, ky = kys * bi;
+    const double w = c * sqrt(fma(ky, ky, kx2));
+    // w t / pi; hx, hy carry t squared away, so restore its sign (sin is odd)
+    double h = sqrt(fma(hyb, hyb, hx2));
+    if (t < 0) h = -h;
+    if constexpr (sizeof(T) == 4) {
+      h = fma(-2.0, rint(0.5 * h), h);
+      float s, cc;
+      sincospif(float(h), &s, &cc);
+      cw = cc;
+      sw = s;
+      sow = w == 0.0 ? T(t) : T(double(s) / w);
+    } else {
+      double s, cc;
+      sincospi(h, &s, &cc);
+      cw = cc;
+      sw = s;
+      sow = w == 0.0 ? t : s / w;
+    }
+    w_out = T(w);
+  }
+};
 
 // ---------------------------------------------------------------------------
-// Row pass: LINES = E*TH/N rows per workgroup, x contiguous.
+// Row pass: LINES = E*TH/N rows per tile, x contiguous.  Workgroups walk
+// tiles persistently; with PF the next tile's rows are loaded into registers
+// while the current tile is transformed, so HBM reads continue through the
+// LDS exchanges.
 // ---------------------------------------------------------------------------
-template <typename T, int LOGN, int E, int TH, int MAXLR>
+template <typename T, int LOGN, int E, int TH, int MAXLR, bool PF, int TWM>
 __global__ void __launch_bounds__(TH) row_kernel(RowArgs<T> a) {
   constexpr int N = 1 << LOGN;
   constexpr int LINES = E * TH / N;
   static_assert(LINES >= 1 && LINES * N == E * TH, "tile must hold whole rows");
-  using Map = RowMap<LOGN, LINES>;
-  using Eng = Engine<T, LOGN, E, TH, MAXLR, false, Map>;
-  __shared__ cx<T> lds[Eng::NST > 1 ? Map::kLdsElems : 1];
+  static_assert(TWM == kTwGlobal || TWM == kTwRegs, "row pass twiddles: global table or registers");
+  using Map = RowMap<LOGN, LINES, plan_pad(LOGN, MAXLR, false)>;
+  using Eng = Engine<T, LOGN, E, TH, MAXLR, false, Map, false>;
+  __shared__ typename Eng::Word lds[Eng::kLdsWords];
 
-  const int tid = threadIdx.x;
-  const long long row0 = (long long)blockIdx.x * LINES;
+  int tid = threadIdx.x;
+  const long long ntiles = (a.nrows + LINES - 1) / LINES;
+  TileWalk walk(ntiles);
+  if (walk.next >= walk.end) return;
+  // raw loads; the inverse's conjugation is applied when the tile is consumed
+  // so that a prefetch never waits for its own data
+  auto load = [&](long long tile, cx<T>(&dst)[E]) {
+    const long long row0 = tile * LINES;
+    Eng::for_each_input(tid, [&](int i, int line, int n) {
+      // clamped, unconditional loads (padding rows reread the last row and are
+      // never stored) keep the loads free of branches
+      const long long row = min(row0 + line, a.nrows - 1);
+      dst[i] = a.in[row * N + n];
+    });
+  };
+  cx<T> wall[TWM == kTwRegs ? Eng::kTwRegs : 1];
+  if constexpr (TWM == kTwRegs) Eng::load_all_tw(wall, a.tw, tid);
   const T sgn = a.inverse ? T(-1) : T(1);
-  cx<T> x[E];
-  Eng::for_each_input(tid, [&](int i, int line, int n) {
-    const long long row = row0 + line;
-    cx<T> v = {T(0), T(0)};
-    if (row < a.nrows) v = a.in[row * N + n];
-    x[i] = {v.re, sgn * v.im};
-  });
-  Eng::run(x, lds, a.tw, tid);
   const T sr = a.scale, si = sgn * a.scale;
-  Eng::for_each_output(tid, [&](int i, int line, int n) {
-    const long long row = row0 + line;
-    if (row < a.nrows) a.out[row * N + n] = {x[i].re * sr, x[i].im * si};
-  });
+  cx<T> x[E];
+  cx<T> nxt[PF ? E : 1];
+  long long tile = walk.next;
+  load(tile, x);
+  while (true) {
+    tid = opaque(tid);
+    const long long nt = tile + walk.step;
+    const bool more = nt < walk.end;
+    if constexpr (PF) {
+      if (more) load(nt, nxt);
+    }
+#pragma unroll
+    for (int i = 0; i < E; i++) x[i].im *= sgn;
+    if constexpr (TWM == kTwRegs) Eng::run_regs(x, lds, wall, tid);
+    else Eng::run(x, lds, a.tw, tid);
+    const long long row0 = tile * LINES;
+    Eng::for_each_output(tid, [&](int i, int line, int n) {
+      const long long row = row0 + line;
+      if (row < a.nrows) a.out[row * N + n] = {x[i].re * sr, x[i].im * si};
+    });
+    if (!more) break;
+    if constexpr (PF) {
+#pragma unroll
+      for (int i = 0; i < E; i++) x[i] = nxt[i];
+    } else {
+      load(nt, x);
+    }
+    tile = nt;
+  }
 }
 
 // ---------------------------------------------------------------------------
 // Column pass: a tile of T = 2^LOGT adjacent columns of one field; columns
-// are numbered C = field * nx + x over the whole batch.
-// NF = 2 carries a second field (the wave's velocity) through the pass.
+// are numbered C = field * nx + x over the whole batch.  NF = 2 carries a
+// second field (the wave's velocity) through the pass.  SPLIT exchanges the
+// real and imaginary parts through LDS one after the other (half the LDS, so
+// two workgroups fit per CU at the large sizes); PF prefetches the next tile.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
-  // Workgroups go round-robin over the 8 XCDs; give each XCD a contiguous
-  // range of tiles so that neighbouring tiles (which share 128-byte lines)
-  // meet in the same L2.
-  const int per = nblocks >> 3;
-  if ((nblocks & 7) != 0 || per == 0) return bid;
-  return (bid & 7) * per + (bid >> 3);
-}
-
-template <typename T, int LOGN, int LOGT, int E, int TH, int MAXLR, int NF>
+template <typename T, int LOGN, int LOGT, int E, int TH, int MAXLR, int NF, bool SPLIT, bool PF, int TWM>
 __global__ void __launch_bounds__(TH) col_kernel(ColArgs<T> a) {
   constexpr int N = 1 << LOGN;
   constexpr int TT = 1 << LOGT;
   static_assert(N * TT == E * TH, "tile must hold whole columns");
-  using Map = ColMap<LOGN, LOGT>;
-  using Fwd = Engine<T, LOGN, E, TH, MAXLR, false, Map>;
-  using Inv = Engine<T, LOGN, E, TH, MAXLR, true, Map>;
-  __shared__ cx<T> lds[Fwd::NST > 1 ? Map::kLdsElems : 1];
+  static_assert(TWM == kTwGlobal || TWM == kTwLds, "column pass twiddles: global table or LDS");
+  // When TH is a multiple of T every thread stays on one column of the tile.
+  constexpr bool kOneCol = (TH % TT) == 0;
+  using FMap = ColMap<LOGN, LOGT, plan_pad(LOGN, MAXLR, false)>;
+  using IMap = ColMap<LOGN, LOGT, plan_pad(LOGN, MAXLR, true)>;
+  using Fwd = Engine<T, LOGN, E, TH, MAXLR, false, FMap, SPLIT>;
+  using Inv = Engine<T, LOGN, E, TH, MAXLR, true, IMap, SPLIT>;
+  constexpr int kLdsWords = Fwd::kLdsWords > Inv::kLdsWords ? Fwd::kLdsWords : Inv::kLdsWords;
+  __shared__ typename Fwd::Word lds[kLdsWords];
+  __shared__ cx<T> twl[TWM == kTwLds ? N : 1];
 
-  const int tid = threadIdx.x;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const long long col0 = (long long)tile * TT;
+  int tid = threadIdx.x;
+  const long long ntiles = (a.ncols + TT - 1) >> LOGT;
+  TileWalk walk(ntiles);
+  if (walk.next >= walk.end) return;
   const int lognx = a.lognx;
-  const long long nx = 1ll << lognx;
-  const long long fmask = nx - 1;
-  // address of element n of tile line `line`, or -1 when the column is padding
-  auto addr = [&](int line, int n) -> long long {
-    const long long C = col0 + line;
-    if (C >= a.ncols) return -1;
-    const long long f = C >> lognx, cxi = C & fmask;
-    return (f << (lognx + LOGN)) + ((long long)n << lognx) + cxi;
+  const long long fmask = (1ll << lognx) - 1;
+  const int mode = a.mode;
+  const bool spec_in = mode == kColMulInv;
+  const T sgn = mode == kColInverse ? T(-1) : T(1);
+  const bool has_in1 = a.in1 != nullptr;
+
+  // Element offset of (column C, row 0) of the batch; row n adds n * nx.
+  auto col_base = [&](long long C) -> long long {
+    return ((C >> lognx) << (lognx + LOGN)) + (C & fmask);
   };
-  auto colx = [&](int line) -> int { return int((col0 + line) & fmask); };
+  // Loads are clamped to the last column (padding columns are reread and never
+  // stored), so loads carry no branches and prefetches stay in flight.
+  auto load = [&](long long tile, cx<T>(&dx)[E], cx<T>(&dy)[NF == 2 ? E : 1]) {
+    const long long col0 = tile << LOGT;
+    long long cb = 0;
+    if constexpr (kOneCol) cb = col_base(min(col0 + (tid & (TT - 1)), a.ncols - 1));
+    auto f = [&](int i, int line, int n) {
+      long long p;
+      if constexpr (kOneCol) p = cb + ((long long)n << lognx);
+      else p = col_base(min(col0 + line, a.ncols - 1)) + ((long long)n << lognx);
+      dx[i] = a.in0[p];
+      if constexpr (NF == 2) dy[i] = has_in1 ? a.in1[p] : cx<T>{T(0), T(0)};
+    };
+    if (spec_in) Inv::for_each_input(tid, f);
+    else Fwd::for_each_input(tid, f);
+  };
+  // Stores of the last stage's outputs, skipping padding columns.
+  auto store = [&](long long col0, cx<T>* out, auto&& value) {
+    if constexpr (kOneCol) {
+      const long long C = col0 + (tid & (TT - 1));
+      if (C >= a.ncols) return;
+      cx<T>* o = out + col_base(C);
+      Inv::for_each_output(tid, [&](int i, int, int n) { o[(long long)n << lognx] = value(i); });
+    } else {
+      Inv::for_each_output(tid, [&](int i, int line, int n) {
+        const long long C = col0 + line;
+        if (C < a.ncols) out[col_base(C) + ((long long)n << lognx)] = value(i);
+      });
+    }
+  };
+
+  if constexpr (TWM == kTwLds) {
+    Fwd::load_lds_table(twl, a.tw, tid);
+    lds_barrier();
+  }
+  auto fwd = [&](cx<T>(&v)[E], int t) {
+    if constexpr (TWM == kTwLds) Fwd::run_lds(v, lds, twl, t);
+    else Fwd::run(v, lds, a.tw, t);
+  };
+  auto inv = [&](cx<T>(&v)[E], int t) {
+    if constexpr (TWM == kTwLds) Inv::run_lds(v, lds, twl, t);
+    else Inv::run(v, lds, a.tw, t);
+  };
+  // Multiply by a real symbol and conjugate (for the inverse by conjugation).
+  auto apply_real = [&](auto sym_tag, long long col0, cx<T>(&v)[E]) {
+    constexpr int OP = decltype(sym_tag)::value;
+    if constexpr (kOneCol) {
+      const Symbol<T, OP> sym(a.sym, int((col0 + (tid & (TT - 1))) & fmask));
+      Inv::for_each_input(tid, [&](int i, int, int n) {
+        const T m = sym(n);
+        v[i] = {v[i].re * m, -v[i].im * m};
+      });
+    } else {
+      Inv::for_each_input(tid, [&](int i, int line, int n) {
+        const Symbol<T, OP> sym(a.sym, int((col0 + line) & fmask));
+        const T m = sym(n);
+        v[i] = {v[i].re * m, -v[i].im * m};
+      });
+    }
+  };
 
   cx<T> x[E];
   cx<T> y[NF == 2 ? E : 1];
-  const int mode = a.mode;
-
-  if (mode == kColMulInv) {
-    // spectrum in: load at the inverse engine's first-stage positions
-    Inv::for_each_input(tid, [&](int i, int line, int n) {
-      const long long p = addr(line, n);
-      x[i] = p >= 0 ? a.in0[p] : cx<T>{T(0), T(0)};
-      if constexpr (NF == 2) y[i] = (p >= 0 && a.in1) ? a.in1[p] : cx<T>{T(0), T(0)};
-    });
-  } else {
-    const T sgn = mode == kColInverse ? T(-1) : T(1);
-    Fwd::for_each_input(tid, [&](int i, int line, int n) {
-      const long long p = addr(line, n);
-      cx<T> v = p >= 0 ? a.in0[p] : cx<T>{T(0), T(0)};
-      x[i] = {v.re, sgn * v.im};
-      if constexpr (NF == 2) y[i] = (p >= 0 && a.in1) ? a.in1[p] : cx<T>{T(0), T(0)};
-    });
-    Fwd::run(x, lds, a.tw, tid);
-    if constexpr (NF == 2) {
-      if (a.in1) Fwd::run(y, lds, a.tw, tid);
+  cx<T> nx_[PF ? E : 1];
+  cx<T> ny_[(PF && NF == 2) ? E : 1];
+  long long tile = walk.next;
+  load(tile, x, y);
+  while (true) {
+    tid = opaque(tid);
+    const long long nt = tile + walk.step;
+    const bool more = nt < walk.end;
+    if constexpr (PF) {
+      if (more) load(nt, nx_, ny_);
     }
+#pragma unroll
+    for (int i = 0; i < E; i++) x[i].im *= sgn;
+    const long long col0 = tile << LOGT;
     if (mode == kColForward || mode == kColInverse) {
-      const T s = mode == kColInverse ? T(a.sym.scale) : T(1);
-      Fwd::for_each_output(tid, [&](int i, int line, int n) {
-        const long long p = addr(line, n);
-        if (p >= 0) a.out0[p] = {x[i].re * s, sgn * x[i].im * s};
-      });
-      return;
-    }
-  }
-
-  // Pointwise symbol at (a = column x index, b = n), then conjugate for the
-  // inverse (conjugation identity).  The forward engine's last radix is the
-  // inverse engine's first, so the positions line up register by register.
-  if constexpr (NF == 1) {
-    Inv::for_each_input(tid, [&](int i, int line, int n) {
-      const T m = symbol_real<T>(a.sym, colx(line), n);
-      x[i] = {x[i].re * m, -x[i].im * m};
-    });
-  } else {
-    const bool want_v = a.out1 != nullptr;
-    const T sc = T(a.sym.scale);
-    Inv::for_each_input(tid, [&](int i, int line, int n) {
-      T cw, sw, sow, w;
-      wave_coeffs<T>(a.sym, colx(line), n, cw, sw, sow, w);
-      const cx<T> F = x[i], G = y[i];
-      const cx<T> U = {cw * F.re + sow * G.re, cw * F.im + sow * G.im};
-      x[i] = {U.re * sc, -U.im * sc};
-      if (want_v) {
-        const T ws = -w * sw;
-        const cx<T> V = {ws * F.re + cw * G.re, ws * F.im + cw * G.im};
-        y[i] = {V.re * sc, -V.im * sc};
+      // a plain column transform (forward, or inverse by conjugation)
+      fwd(x, tid);
+      const T sc = mode == kColInverse ? T(a.sym.scale) : T(1);
+      const T si = sgn * sc;
+      if constexpr (kOneCol) {
+        const long long C = col0 + (tid & (TT - 1));
+        if (C < a.ncols) {
+          cx<T>* o = a.out0 + col_base(C);
+          Fwd::for_each_output(tid, [&](int i, int, int n) {
+            o[(long long)n << lognx] = {x[i].re * sc, x[i].im * si};
+          });
+        }
+      } else {
+        Fwd::for_each_output(tid, [&](int i, int line, int n) {
+          const long long C = col0 + line;
+          if (C < a.ncols) a.out0[col_base(C) + ((long long)n << lognx)] = {x[i].re * sc, x[i].im * si};
+        });
       }
-    });
-  }
-  Inv::run(x, lds, a.tw, tid);
-  Inv::for_each_output(tid, [&](int i, int line, int n) {
-    const long long p = addr(line, n);
-    if (p >= 0) a.out0[p] = conjg(x[i]);
-  });
-  if constexpr (NF == 2) {
-    if (a.out1) {
-      Inv::run(y, lds, a.tw, tid);
-      Inv::for_each_output(tid, [&](int i, int line, int n) {
-        const long long p = addr(line, n);
-        if (p >= 0) a.out1[p] = conjg(y[i]);
-      });
+    } else {
+      if (!spec_in) {
+        fwd(x, tid);
+        if constexpr (NF == 2) {
+          if (has_in1) fwd(y, tid);
+        }
+      }
+      // Pointwise symbol at (a = column x index, b = n).  The forward
+      // engine's last radix is the inverse engine's first, so positions line
+      // up register by register.
+      if constexpr (NF == 1) {
+        switch (a.sym.op) {
+          case kSymPoisson: apply_real(std::integral_constant<int, kSymPoisson>(), col0, x); break;
+          case kSymDiffusion: apply_real(std::integral_constant<int, kSymDiffusion>(), col0, x); break;
+          case kSymWave: apply_real(std::integral_constant<int, kSymWave>(), col0, x); break;
+          default: apply_real(std::integral_constant<int, kSymScale>(), col0, x); break;
+        }
+      } else {
+        const bool want_v = a.out1 != nullptr;
+        const T sc = T(a.sym.scale);
+        Inv::for_each_input(tid, [&](int i, int line, int n) {
+          const WaveCoeffs<T> wc(a.sym, int((col0 + line) & fmask));
+          T cw, sw, sow, w;
+          wc(n, cw, sw, sow, w);
+          const cx<T> F = x[i], G = y[i];
+          const cx<T> U = {cw * F.re + sow * G.re, cw * F.im + sow * G.im};
+          x[i] = {U.re * sc, -U.im * sc};
+          if (want_v) {
+            const T ws = -w * sw;
+            const cx<T> V = {ws * F.re + cw * G.re, ws * F.im + cw * G.im};
+            y[i] = {V.re * sc, -V.im * sc};
+          }
+        });
+      }
+      inv(x, tid);
+      store(col0, a.out0, [&](int i) { return conjg(x[i]); });
+      if constexpr (NF == 2) {
+        if (a.out1) {
+          inv(y, tid);
+          store(col0, a.out1, [&](int i) { return conjg(y[i]); });
+        }
+      }
     }
+    if (!more) break;
+    if constexpr (PF) {
+#pragma unroll
+      for (int i = 0; i < E; i++) x[i] = nx_[i];
+      if constexpr (NF == 2) {
+#pragma unroll
+        for (int i = 0; i < E; i++) y[i] = ny_[i];
+      }
+    } else {
+      load(nt, x, y);
+    }
+    tile = nt;
   }
 }
 
 // ---------------------------------------------------------------------------
 // Variant tables (one entry per compiled kernel configuration).
 // ---------------------------------------------------------------------------
-using LaunchFn = hipError_t (*)(const void* args, long long units, hipStream_t stream);
+// Launch over `units` rows or columns with at most `max_blocks` workgroups.
+using LaunchFn = hipError_t (*)(const void* args, long long units, long long max_blocks, hipStream_t stream);
+// Resident workgroups per CU for this kernel (0 on error).
+using OccFn = int (*)();
 
 struct RowVariant {
   LaunchFn launch;
-  int logn, e, th, maxlr, lines;
+  OccFn occupancy;
+  int logn, e, th, maxlr, lines, pf, twm;
   int lds_bytes;
   const char* name;
 };
 
 struct ColVariant {
   LaunchFn launch;
-  int logn, logt, e, th, maxlr, nf;
+  OccFn occupancy;
+  int logn, logt, e, th, maxlr, nf, split, pf, twm;
   int lds_bytes;
   const char* name;
 };
 
-template <typename T, int LOGN, int E, int TH, int MAXLR>
-hipError_t launch_row(const void* args, long long nrows, hipStream_t s) {
+template <typename T, int LOGN, int E, int TH, int MAXLR, bool PF, int TWM>
+hipError_t launch_row(const void* args, long long nrows, long long max_blocks, hipStream_t s) {
   constexpr int LINES = E * TH / (1 << LOGN);
-  const long long grid = (nrows + LINES - 1) / LINES;
+  long long grid = (nrows + LINES - 1) / LINES;
+  if (max_blocks > 0 && grid > max_blocks) grid = max_blocks;
   if (grid <= 0 || grid > 0x7fffffffll) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((row_kernel<T, LOGN, E, TH, MAXLR>), dim3((unsigned)grid), dim3(TH), 0, s,
+  hipLaunchKernelGGL((row_kernel<T, LOGN, E, TH, MAXLR, PF, TWM>), dim3((unsigned)grid), dim3(TH), 0, s,
                      *static_cast<const RowArgs<T>*>(args));
   return hipGetLastError();
 }
 
-template <typename T, int LOGN, int LOGT, int E, int TH, int MAXLR, int NF>
-hipError_t launch_col(const void* args, long long ncols, hipStream_t s) {
-  const long long grid = (ncols + (1 << LOGT) - 1) >> LOGT;
+template <typename T, int LOGN, int E, int TH, int MAXLR, bool PF, int TWM>
+int occ_row() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, row_kernel<T, LOGN, E, TH, MAXLR, PF, TWM>, TH, 0) !=
+      hipSuccess)
+    return 0;
+  return n;
+}
+
+template <typename T, int LOGN, int LOGT, int E, int TH, int MAXLR, int NF, bool SPLIT, bool PF, int TWM>
+hipError_t launch_col(const void* args, long long ncols, long long max_blocks, hipStream_t s) {
+  long long grid = (ncols + (1 << LOGT) - 1) >> LOGT;
+  if (max_blocks > 0 && grid > max_blocks) grid = max_blocks;
   if (grid <= 0 || grid > 0x7fffffffll) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((col_kernel<T, LOGN, LOGT, E, TH, MAXLR, NF>), dim3((unsigned)grid), dim3(TH),
-                     0, s, *static_cast<const ColArgs<T>*>(args));
+  hipLaunchKernelGGL((col_kernel<T, LOGN, LOGT, E, TH, MAXLR, NF, SPLIT, PF, TWM>), dim3((unsigned)grid), dim3(TH), 0,
+                     s, *static_cast<const ColArgs<T>*>(args));
   return hipGetLastError();
+}
+
+template <typename T, int LOGN, int LOGT, int E, int TH, int MAXLR, int NF, bool SPLIT, bool PF, int TWM>
+int occ_col() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, col_kernel<T, LOGN, LOGT, E, TH, MAXLR, NF, SPLIT, PF, TWM>, TH,
+                                                   0) != hipSuccess)
+    return 0;
+  return n;
 }
 
 template <int LOGN, int MAXLR>
 constexpr int lds_elems_row(int lines) {
-  return plan_nstages(LOGN, MAXLR) > 1 ? lines * ((1 << LOGN) + ((1 << LOGN) >> 3)) : 1;
+  return plan_nstages(LOGN, MAXLR) > 1 ? lines * ((1 << LOGN) + ((1 << LOGN) >> plan_pad(LOGN, MAXLR, false))) : 1;
 }
 template <int LOGN, int MAXLR>
 constexpr int lds_elems_col(int logt) {
-  return plan_nstages(LOGN, MAXLR) > 1 ? (((1 << LOGN) + ((1 << LOGN) >> 3)) << logt) : 1;
+  constexpr int lp = plan_pad(LOGN, MAXLR, false) < plan_pad(LOGN, MAXLR, true) ? plan_pad(LOGN, MAXLR, false)
+                                                                                 : plan_pad(LOGN, MAXLR, true);
+  return plan_nstages(LOGN, MAXLR) > 1 ? (((1 << LOGN) + ((1 << LOGN) >> lp)) << logt) : 1;
 }
 
-#define FFTPDE_ROW_VARIANT(T, LOGN, E, TH, MAXLR)                                              \
-  {&::fftpde::launch_row<T, LOGN, E, TH, MAXLR>, LOGN, E, TH, MAXLR, (E) * (TH) >> (LOGN),     \
+#define FFTPDE_ROW_VARIANT(T, LOGN, E, TH, MAXLR, PF, TWM)                                     \
+  {&::fftpde::launch_row<T, LOGN, E, TH, MAXLR, PF, TWM>,                                      \
+   &::fftpde::occ_row<T, LOGN, E, TH, MAXLR, PF, TWM>,                                         \
+   LOGN, E, TH, MAXLR, (E) * (TH) >> (LOGN), PF, TWM,                                          \
    int(::fftpde::lds_elems_row<LOGN, MAXLR>((E) * (TH) >> (LOGN)) * sizeof(::fftpde::cx<T>)), \
-   "row_" #T "_n" #LOGN "_e" #E "_th" #TH "_r" #MAXLR}
+   "row_" #T "_n" #LOGN "_e" #E "_th" #TH "_r" #MAXLR "_pf" #PF "_tw" #TWM}
 
-#define FFTPDE_COL_VARIANT(T, LOGN, LOGT, E, TH, MAXLR, NF)                                       \
-  {&::fftpde::launch_col<T, LOGN, LOGT, E, TH, MAXLR, NF>, LOGN, LOGT, E, TH, MAXLR, NF,          \
-   int(::fftpde::lds_elems_col<LOGN, MAXLR>(LOGT) * sizeof(::fftpde::cx<T>)),                     \
-   "col_" #T "_n" #LOGN "_t" #LOGT "_e" #E "_th" #TH "_r" #MAXLR "_f" #NF}
+#define FFTPDE_COL_VARIANT(T, LOGN, LOGT, E, TH, MAXLR, NF, SPLIT, PF, TWM)                           \
+  {&::fftpde::launch_col<T, LOGN, LOGT, E, TH, MAXLR, NF, SPLIT, PF, TWM>,                            \
+   &::fftpde::occ_col<T, LOGN, LOGT, E, TH, MAXLR, NF, SPLIT, PF, TWM>,                               \
+   LOGN, LOGT, E, TH, MAXLR, NF, SPLIT, PF, TWM,                                                      \
+   int(::fftpde::lds_elems_col<LOGN, MAXLR>(LOGT) * ((SPLIT) ? sizeof(T) : sizeof(::fftpde::cx<T>)) + \
+       ((TWM) == 2 ? (1 << (LOGN)) * sizeof(::fftpde::cx<T>) : 0)),                                  \
+   "col_" #T "_n" #LOGN "_t" #LOGT "_e" #E "_th" #TH "_r" #MAXLR "_f" #NF "_s" #SPLIT "_pf" #PF "_tw" #TWM}
 
 // Tables defined in the per-dtype translation units.
 const RowVariant* row_variants_f32(int* count);

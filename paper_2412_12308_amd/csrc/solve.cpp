@@ -1,0 +1,169 @@
+// solve.cpp -- launch sequences of the 2D transforms and the spectral
+// solves: row pass (x transforms for every y, Sec. II.D), column pass (y
+// transforms, with the symbol between forward and inverse), row pass.
+#include "solve.hpp"
+
+#include <cmath>
+
+#include "../../include/fftpde.h"
+
+namespace fftpde {
+namespace {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+int ilog2(int n) {
+  int l = 0;
+  while ((1 << l) < n) l++;
+  return l;
+}
+
+// Launch through `fn`, bracketed by events when profiling is on.
+template <class F>
+hipError_t timed_launch(Context* c, const char* name, double bytes, hipStream_t s, F&& fn) {
+  if (!c->profiling) return fn();
+  hipEvent_t a = c->take_event(), b = c->take_event();
+  if (!a || !b) return fn();
+  (void)hipEventRecord(a, s);
+  hipError_t e = fn();
+  (void)hipEventRecord(b, s);
+  c->timed.push_back({name, bytes, a, b});
+  return e;
+}
+
+
+}  // namespace
+
+
+template <typename T>
+static const cx<T>* twiddles(const Context* c) {
+  if constexpr (sizeof(T) == 4) return c->tw32;
+  else return c->tw64;
+}
+
+template <typename T>
+int row_pass(Context* c, const void* in, void* out, int lognx, long long nrows, bool inverse, double scale,
+             hipStream_t s) {
+  const RowVariant* v = c->row_variant(sizeof(T) == 4 ? FFTPDE_C64 : FFTPDE_C128, lognx);
+  if (!v) return FFTPDE_EINVAL;
+  RowArgs<T> a{static_cast<const cx<T>*>(in), static_cast<cx<T>*>(out), twiddles<T>(c), nrows, inverse ? 1 : 0,
+               T(scale)};
+  const double bytes = 2.0 * sizeof(cx<T>) * (double)nrows * (double)(1 << lognx);
+  const long long maxb = v->pf ? c->max_blocks(v, v->occupancy) : 0;
+  hipError_t e = timed_launch(c, v->name, bytes, s, [&] { return v->launch(&a, nrows, maxb, s); });
+  if (e != hipSuccess) {
+    set_last_error(v->name, e);
+    return FFTPDE_EDEVICE;
+  }
+  return FFTPDE_OK;
+}
+
+template <typename T>
+int col_pass(Context* c, const void* in0, const void* in1, void* out0, void* out1, int lognx, int logny,
+             long long batch, int mode, const SymParams& sym, int nf, hipStream_t s) {
+  const ColVariant* v = c->col_variant(sizeof(T) == 4 ? FFTPDE_C64 : FFTPDE_C128, logny, nf);
+  if (!v) return FFTPDE_EINVAL;
+  ColArgs<T> a{static_cast<const cx<T>*>(in0), static_cast<const cx<T>*>(in1), static_cast<cx<T>*>(out0),
+               static_cast<cx<T>*>(out1), twiddles<T>(c), batch << lognx, lognx, mode, sym};
+  const double field = sizeof(cx<T>) * (double)batch * (double)(1ll << (lognx + logny));
+  const double bytes = field * ((in0 ? 1 : 0) + (in1 ? 1 : 0) + (out0 ? 1 : 0) + (out1 ? 1 : 0));
+  const long long maxb = v->pf ? c->max_blocks(v, v->occupancy) : 0;
+  hipError_t e = timed_launch(c, v->name, bytes, s, [&] { return v->launch(&a, batch << lognx, maxb, s); });
+  if (e != hipSuccess) {
+    set_last_error(v->name, e);
+    return FFTPDE_EDEVICE;
+  }
+  return FFTPDE_OK;
+}
+
+SymParams make_sym(int op, int nx, int ny, double lx, double ly, double coef, double t) {
+  SymParams p{};
+  p.op = op;
+  p.lognx = ilog2(nx);
+  p.logny = ilog2(ny);
+  p.kxs = 2.0 * kPi / lx;
+  p.kys = 2.0 * kPi / ly;
+  p.scale = 1.0 / ((double)nx * (double)ny);
+  if (op == kSymDiffusion) p.kt = coef * t;
+  if (op == kSymWave) {
+    p.c = coef;
+    p.t = t;
+    p.hx = 2.0 * coef * t / lx;
+    p.hy = 2.0 * coef * t / ly;
+  }
+  return p;
+}
+
+template <typename T>
+int transform(Context* c, const void* in, void* out, int nx, int ny, int batch, bool inverse, hipStream_t s) {
+  const int lx = ilog2(nx), ly = ilog2(ny);
+  SymParams sym = make_sym(kSymScale, nx, ny, 1.0, 1.0, 0.0, 0.0);
+  int rc;
+  if (!inverse) {
+    rc = row_pass<T>(c, in, out, lx, (long long)ny * batch, false, 1.0, s);
+    if (rc == FFTPDE_OK) rc = col_pass<T>(c, out, nullptr, out, nullptr, lx, ly, batch, kColForward, sym, 1, s);
+  } else {
+    rc = col_pass<T>(c, in, nullptr, out, nullptr, lx, ly, batch, kColInverse, sym, 1, s);
+    if (rc == FFTPDE_OK) rc = row_pass<T>(c, out, out, lx, (long long)ny * batch, true, 1.0, s);
+  }
+  return rc;
+}
+
+// forward rows -> fused column pass -> inverse rows, for one real symbol
+template <typename T>
+int solve_real_symbol(Context* c, const void* in, void* out, int nx, int ny, int batch, const SymParams& sym,
+                      hipStream_t s) {
+  const int lx = ilog2(nx), ly = ilog2(ny);
+  const long long nrows = (long long)ny * batch;
+  int rc = row_pass<T>(c, in, out, lx, nrows, false, 1.0, s);
+  if (rc == FFTPDE_OK) rc = col_pass<T>(c, out, nullptr, out, nullptr, lx, ly, batch, kColFwdMulInv, sym, 1, s);
+  if (rc == FFTPDE_OK) rc = row_pass<T>(c, out, out, lx, nrows, true, 1.0, s);
+  return rc;
+}
+
+template <typename T>
+int solve_wave_two(Context* c, const void* u0, const void* v0, void* u, void* v, int nx, int ny, int batch,
+                   const SymParams& sym, hipStream_t s) {
+  const int lx = ilog2(nx), ly = ilog2(ny);
+  const long long nrows = (long long)ny * batch;
+  void* vbuf = v;
+  if (v0 && !v) {
+    const size_t bytes = sizeof(cx<T>) * (size_t)nx * ny * batch;
+    int rc = c->workspace(bytes, &vbuf);
+    if (rc != FFTPDE_OK) return rc;
+  }
+  int rc = row_pass<T>(c, u0, u, lx, nrows, false, 1.0, s);
+  if (rc == FFTPDE_OK && v0) rc = row_pass<T>(c, v0, vbuf, lx, nrows, false, 1.0, s);
+  if (rc == FFTPDE_OK)
+    rc = col_pass<T>(c, u, v0 ? vbuf : nullptr, u, v, lx, ly, batch, kColFwdMulInv, sym, 2, s);
+  if (rc == FFTPDE_OK) rc = row_pass<T>(c, u, u, lx, nrows, true, 1.0, s);
+  if (rc == FFTPDE_OK && v) rc = row_pass<T>(c, v, v, lx, nrows, true, 1.0, s);
+  return rc;
+}
+
+
+int run_transform(Context* c, int dtype, bool inverse, const void* in, void* out, int nx, int ny, int batch,
+                  hipStream_t s) {
+  return dtype == FFTPDE_C64 ? transform<float>(c, in, out, nx, ny, batch, inverse, s)
+                             : transform<double>(c, in, out, nx, ny, batch, inverse, s);
+}
+
+int run_solve(Context* c, int dtype, int op, const void* in, const void* in2, void* out, void* out2, int nx, int ny,
+              int batch, double lx, double ly, double coef, double t, hipStream_t s) {
+  const int sop = op == FFTPDE_POISSON ? kSymPoisson : op == FFTPDE_DIFFUSION ? kSymDiffusion : kSymWave;
+  const SymParams sym = make_sym(sop, nx, ny, lx, ly, coef, t);
+  if (op != FFTPDE_WAVE || (!in2 && !out2))
+    return dtype == FFTPDE_C64 ? solve_real_symbol<float>(c, in, out, nx, ny, batch, sym, s)
+                               : solve_real_symbol<double>(c, in, out, nx, ny, batch, sym, s);
+  return dtype == FFTPDE_C64 ? solve_wave_two<float>(c, in, in2, out, out2, nx, ny, batch, sym, s)
+                             : solve_wave_two<double>(c, in, in2, out, out2, nx, ny, batch, sym, s);
+}
+
+template int row_pass<float>(Context*, const void*, void*, int, long long, bool, double, hipStream_t);
+template int row_pass<double>(Context*, const void*, void*, int, long long, bool, double, hipStream_t);
+template int col_pass<float>(Context*, const void*, const void*, void*, void*, int, int, long long, int,
+                             const SymParams&, int, hipStream_t);
+template int col_pass<double>(Context*, const void*, const void*, void*, void*, int, int, long long, int,
+                              const SymParams&, int, hipStream_t);
+
+}  // namespace fftpde

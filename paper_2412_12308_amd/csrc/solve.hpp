@@ -1,0 +1,34 @@
+// solve.hpp -- launch sequences shared by the C ABI, the autotuner, batches
+// and the request server.  Arguments are assumed valid (checked at the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "context.hpp"
+#include "kernels.hpp"
+
+namespace fftpde {
+
+SymParams make_sym(int op, int nx, int ny, double lx, double ly, double coef, double t);
+
+// One row pass over nrows rows of length 2^lognx (forward, or inverse by
+// conjugation with `scale`).
+template <typename T>
+int row_pass(Context* c, const void* in, void* out, int lognx, long long nrows, bool inverse, double scale,
+             hipStream_t s);
+
+// One column pass over `batch` fields of 2^lognx columns of length 2^logny.
+template <typename T>
+int col_pass(Context* c, const void* in0, const void* in1, void* out0, void* out1, int lognx, int logny,
+             long long batch, int mode, const SymParams& sym, int nf, hipStream_t s);
+
+// fft2d_forward / fft2d_inverse.
+int run_transform(Context* c, int dtype, bool inverse, const void* in, void* out, int nx, int ny, int batch,
+                  hipStream_t s);
+
+// A solve (op = FFTPDE_POISSON / DIFFUSION / WAVE; for the wave, in2 is the
+// initial velocity and out2 the velocity output, either may be null).
+int run_solve(Context* c, int dtype, int op, const void* in, const void* in2, void* out, void* out2, int nx, int ny,
+              int batch, double lx, double ly, double coef, double t, hipStream_t s);
+
+}  // namespace fftpde

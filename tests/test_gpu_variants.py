@@ -1,0 +1,95 @@
+"""Every compiled kernel variant (every plan the autotuner may choose) against
+the FP64 oracle: each row variant on a grid whose x side is its length, each
+column variant on a grid whose y side is its length, with a batch whose last
+tile is ragged where the tile holds several lines."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_helpers import as_oracle_input, say, to_dev, to_host, tol
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fp():
+    import paper_2412_12308_amd as fp
+    yield fp
+    fp.plan_select(None)
+
+
+def _variants():
+    import paper_2412_12308_amd as fp
+    try:
+        return fp.plan_variants()
+    except Exception:  # no GPU / library: the test body will report it
+        return []
+
+
+def _cases():
+    out = []
+    for v in _variants():
+        out.append(pytest.param(v, id=v["name"]))
+    return out
+
+
+@pytest.mark.parametrize("v", _cases())
+def test_variant_matches_oracle(fp, v):
+    dt = "c64" if v["dtype"] == 0 else "c128"
+    n = 1 << v["logn"]
+    if v["pass"] == "row":
+        nx, ny = n, 16 if n <= 1024 else 4
+    else:
+        nx, ny = 8 if n >= 1024 else 16, n
+    batch = 3
+    fp.plan_select(None)
+    fp.plan_select(v["name"])
+    say(f"variant {v['name']} nx={nx} ny={ny} batch={batch}")
+    try:
+        if v["fields"] == 1:
+            s = W.random_field((batch, ny, nx), seed=v["logn"] * 97 + v["dtype"])
+            u = to_host(fp.solve_poisson(to_dev(s, dt), 1.0, 2.0))
+            for b in range(batch):
+                ref = oracle.solve_poisson(as_oracle_input(s[b], dt), 1.0, 2.0)
+                assert oracle.rel_l2(u[b], ref) <= tol(dt, nx, ny, 2)
+            X = to_host(fp.fft2d_forward(to_dev(s, dt)))
+            assert oracle.rel_l2(X[batch - 1], oracle.fft2d(as_oracle_input(s[batch - 1], dt))) <= tol(dt, nx, ny, 1)
+        else:
+            u0 = W.random_field((batch, ny, nx), seed=11)
+            v0 = W.random_field((batch, ny, nx), seed=12)
+            u, vv = fp.solve_wave(to_dev(u0, dt), to_dev(v0, dt), 0.9, 0.3, 1.0, 1.0, want_v=True)
+            u, vv = to_host(u), to_host(vv)
+            for b in range(batch):
+                ru, rv = oracle.solve_wave(as_oracle_input(u0[b], dt), as_oracle_input(v0[b], dt), 1.0, 1.0,
+                                           0.9, 0.3, want_v=True)
+                assert oracle.rel_l2(u[b], ru) <= tol(dt, nx, ny, 2)
+                assert oracle.rel_l2(vv[b], rv) <= tol(dt, nx, ny, 2)
+    finally:
+        fp.plan_select(None)
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_autotune_picks_an_admitted_variant_and_round_trips(fp, dt, tmp_path):
+    say(f"autotune 256x512 {dt}")
+    fp.plan_select(None)
+    rep = fp.autotune(256, 512, batch=2, dtype=dt, op=fp.DIFFUSION, reps=2)
+    assert rep["nx"] == 256 and rep["ny"] == 512
+    names = {c["name"] for c in rep["candidates"] if c["ok"]}
+    assert rep["row"] in names and rep["col"] in names
+    assert all(c["err"] <= (1e-12 if dt == "c128" else 2 * 2e-6 * 9) for c in rep["candidates"] if c["ok"])
+    active = {v["name"] for v in fp.plan_variants() if v["active"]}
+    assert rep["row"] in active and rep["col"] in active
+    # results with the tuned plan still match the oracle
+    f = W.random_field((512, 256), seed=5)
+    u = to_host(fp.solve_diffusion(to_dev(f, dt), 0.2, 0.01, 1.0, 1.0))
+    ref = oracle.solve_diffusion(as_oracle_input(f, dt), 1.0, 1.0, 0.2, 0.01)
+    assert oracle.rel_l2(u, ref) <= tol(dt, 256, 512, 2)
+    # save, reset, load: the same variants become active again
+    path = str(tmp_path / "plan.txt")
+    fp.plan_save(path)
+    fp.plan_select(None)
+    fp.plan_load(path)
+    active2 = {v["name"] for v in fp.plan_variants() if v["active"]}
+    assert rep["row"] in active2 and rep["col"] in active2
+    fp.plan_select(None)
