@@ -51,6 +51,12 @@ def lib() -> ctypes.CDLL:
             if not os.path.exists(LIB_PATH):
                 raise ImportError(f"{LIB_PATH} is missing: build it with "
                                   "`python -m paper_2412_12308_amd.build`")
+            # PyTorch-ROCm carries its own HIP runtime and makes its symbols
+            # global.  Importing torch first makes libfftpde.so bind to that
+            # same runtime, so tensors, streams and kernels share one HIP
+            # instance (loading the library first would start a second runtime
+            # from /opt/rocm that torch cannot share the GPU with).
+            import torch  # noqa: F401
             L = ctypes.CDLL(LIB_PATH)
             _declare(L)
             _lib = L

@@ -500,25 +500,39 @@ struct Engine {
   }
 };
 
-// Persistent tile schedule: workgroup b of G walks tiles b0, b0 + step, ...
-// When G is a multiple of the 8 XCDs (workgroups are dealt to XCDs round
-// robin), each XCD gets one contiguous range of tiles, so neighbouring tiles
-// (which can share 128-byte lines) meet in the same L2.
+// Persistent tile schedule.  Tiles are taken in groups of GROUP consecutive
+// tiles, processed back to back by one workgroup (column tiles narrower than
+// 64 bytes come in pairs, so both halves of each 64-byte chunk are written
+// by the same workgroup while the first half is still in L2).  Workgroup b of
+// G walks groups b0, b0 + step, ...; when G is a multiple of the 8 XCDs
+// (workgroups are dealt to XCDs round robin), each XCD gets one contiguous
+// range of groups, so neighbouring tiles meet in the same L2.
+template <int GROUP>
 struct TileWalk {
-  long long next, end, step;
-  __device__ __forceinline__ TileWalk(long long ntiles) {
+  long long ntiles, end, step;
+  long long first = -1;
+  __device__ __forceinline__ explicit TileWalk(long long nt) : ntiles(nt) {
+    const long long ngroups = (nt + GROUP - 1) / GROUP;
     const int G = gridDim.x, b = blockIdx.x;
-    if ((G & 7) == 0 && ntiles >= G) {
+    long long g0;
+    if ((G & 7) == 0 && ngroups >= G) {
       const int x = b & 7, per = G >> 3;
-      const long long lo = ntiles * x / 8, hi = ntiles * (x + 1) / 8;
-      next = lo + (b >> 3);
+      const long long lo = ngroups * x / 8, hi = ngroups * (x + 1) / 8;
+      g0 = lo + (b >> 3);
       end = hi;
       step = per;
     } else {
-      next = b;
-      end = ntiles;
+      g0 = b;
+      end = ngroups;
       step = G;
     }
+    if (g0 < end) first = g0 * GROUP;
+  }
+  // the tile after `tile` in this workgroup's walk, or -1
+  __device__ __forceinline__ long long next(long long tile) const {
+    if (GROUP > 1 && (tile % GROUP) + 1 < GROUP && tile + 1 < ntiles) return tile + 1;
+    const long long g = tile / GROUP + step;
+    return g < end ? g * GROUP : -1;
   }
 };
 

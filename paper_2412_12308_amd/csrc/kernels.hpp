@@ -238,8 +238,8 @@ __global__ void __launch_bounds__(TH) row_kernel(RowArgs<T> a) {
 
   int tid = threadIdx.x;
   const long long ntiles = (a.nrows + LINES - 1) / LINES;
-  TileWalk walk(ntiles);
-  if (walk.next >= walk.end) return;
+  const TileWalk<1> walk(ntiles);
+  if (walk.first < 0) return;
   // raw loads; the inverse's conjugation is applied when the tile is consumed
   // so that a prefetch never waits for its own data
   auto load = [&](long long tile, cx<T>(&dst)[E]) {
@@ -257,12 +257,12 @@ __global__ void __launch_bounds__(TH) row_kernel(RowArgs<T> a) {
   const T sr = a.scale, si = sgn * a.scale;
   cx<T> x[E];
   cx<T> nxt[PF ? E : 1];
-  long long tile = walk.next;
+  long long tile = walk.first;
   load(tile, x);
   while (true) {
     tid = opaque(tid);
-    const long long nt = tile + walk.step;
-    const bool more = nt < walk.end;
+    const long long nt = walk.next(tile);
+    const bool more = nt >= 0;
     if constexpr (PF) {
       if (more) load(nt, nxt);
     }
@@ -311,8 +311,13 @@ __global__ void __launch_bounds__(TH) col_kernel(ColArgs<T> a) {
 
   int tid = threadIdx.x;
   const long long ntiles = (a.ncols + TT - 1) >> LOGT;
-  TileWalk walk(ntiles);
-  if (walk.next >= walk.end) return;
+  // One tile at a time: neighbouring tiles (which share 64-byte chunks when
+  // tiles are narrower) run concurrently on the same XCD, so their reads of a
+  // shared chunk meet in L2.  (Walking narrow tiles in pairs per workgroup
+  // merges the writes but reads the second half after its line has left L2:
+  // measured 1.8x the algorithmic traffic against 1.2x for this order.)
+  const TileWalk<1> walk(ntiles);
+  if (walk.first < 0) return;
   const int lognx = a.lognx;
   const long long fmask = (1ll << lognx) - 1;
   const int mode = a.mode;
@@ -389,12 +394,12 @@ __global__ void __launch_bounds__(TH) col_kernel(ColArgs<T> a) {
   cx<T> y[NF == 2 ? E : 1];
   cx<T> nx_[PF ? E : 1];
   cx<T> ny_[(PF && NF == 2) ? E : 1];
-  long long tile = walk.next;
+  long long tile = walk.first;
   load(tile, x, y);
   while (true) {
     tid = opaque(tid);
-    const long long nt = tile + walk.step;
-    const bool more = nt < walk.end;
+    const long long nt = walk.next(tile);
+    const bool more = nt >= 0;
     if constexpr (PF) {
       if (more) load(nt, nx_, ny_);
     }
