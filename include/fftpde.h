@@ -179,6 +179,34 @@ int solve_wave(fftpde_ctx *ctx, const void *u0, const void *v0, void *u, void *v
                int batch, double lx, double ly, double c, double t, int dtype,
                fftpde_stream stream);
 
+/* ---- time evolution with resident spectra -------------------------------
+ * The diffusion and wave solutions are closed forms in time
+ * (Eq. (solCalorFourier); Eq. (OmegaNonZero), (OmegaZero) with s = 0), so a
+ * time step is an evaluation at the absolute time t_n = n * dt (one FP64
+ * product; nothing accumulates over steps), as the paper's snapshots are.
+ *
+ * fftpde_evolve_create: kind = FFTPDE_DIFFUSION (coef = kappa >= 0; v0 must be
+ *   NULL) or FFTPDE_WAVE (coef = c >= 0; v0 = initial velocity or NULL for 0).
+ *   Computes and keeps on the device the forward spectra of u0 (and v0) for
+ *   `batch` fields: the library owns batch*nx*ny elements per spectrum until
+ *   fftpde_evolve_destroy.  u0/v0 are only read (stream-ordered) and may be
+ *   reused once the stream has passed this call.
+ * fftpde_evolve_step: state at t = n * dt.  u (may be NULL) receives u(t);
+ *   v (wave only, requires u, may be NULL) receives u_t(t).  diag (a DEVICE
+ *   array of 3*batch doubles, may be NULL) receives per field the mean of u(t)
+ *   (real, imaginary part: the k = 0 coefficient over nx*ny, conserved as in
+ *   the paper's Sec. III.B/III.C plots) and an energy computed from the
+ *   spectra in FP64 (Parseval): diffusion integral |u|^2 dx dy; wave
+ *   1/2 integral (|u_t|^2 + c^2 |grad u|^2) dx dy.  Diffusion requires t >= 0.
+ *   A step with u = NULL only reads the spectra (diagnostics).
+ * fftpde_evolve_destroy: waits for the device, frees the spectra; NULL ok. */
+int fftpde_evolve_create(fftpde_ctx *ctx, int kind, const void *u0, const void *v0, int nx, int ny,
+                         int batch, double lx, double ly, double coef, int dtype,
+                         fftpde_stream stream, fftpde_evolve **ev);
+int fftpde_evolve_step(fftpde_evolve *ev, long long n, double dt, void *u, void *v, double *diag,
+                       fftpde_stream stream);
+int fftpde_evolve_destroy(fftpde_evolve *ev);
+
 #ifdef __cplusplus
 }
 #endif

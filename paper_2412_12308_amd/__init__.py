@@ -86,7 +86,10 @@ def _declare(L):
                                   ctypes.POINTER(ctypes.c_size_t)]
     L.fftpde_plan_save.argtypes = [vp, ctypes.c_char_p]
     L.fftpde_plan_load.argtypes = [vp, ctypes.c_char_p]
-    for f in ("fftpde_autotune", "fftpde_plan_save", "fftpde_plan_load", "fftpde_plan_variants",
+    L.fftpde_evolve_create.argtypes = [vp, i, vp, vp, i, i, i, d, d, d, i, vp, ctypes.POINTER(vp)]
+    L.fftpde_evolve_step.argtypes = [vp, ctypes.c_longlong, d, vp, vp, vp, vp]
+    L.fftpde_evolve_destroy.argtypes = [vp]
+    for f in ("fftpde_evolve_create", "fftpde_evolve_step", "fftpde_evolve_destroy", "fftpde_autotune", "fftpde_plan_save", "fftpde_plan_load", "fftpde_plan_variants",
               "fftpde_plan_select", "fftpde_profile", "fftpde_profile_read", "fftpde_create", "fftpde_destroy", "fft2d_forward", "fft2d_inverse", "solve_poisson",
               "solve_diffusion", "solve_wave"):
         getattr(L, f).restype = i
@@ -294,3 +297,56 @@ def solve_wave(u0, v0=None, c: float = 1.0, t: float = 0.0, lx: float = 1.0, ly:
                             nx, ny, batch, float(lx), float(ly), float(c), float(t), dt,
                             _stream(u0)), "solve_wave")
     return out, v_out
+
+
+class Evolution:
+    """Time evolution of the diffusion or wave equation with the forward spectra
+    of the initial data resident on the device (fftpde_evolve_*).
+
+    step(n, dt) evaluates the exact solution at t = n * dt."""
+
+    def __init__(self, kind: int, u0, v0=None, coef: float = 1.0, lx: float = 1.0, ly: float = 1.0):
+        nx, ny, batch, dt = _field(u0, "u0")
+        if v0 is not None and (_field(v0, "v0") != (nx, ny, batch, dt) or v0.device != u0.device):
+            raise ValueError("v0 must match u0")
+        self.shape, self.dtype, self.device = tuple(u0.shape), u0.dtype, u0.device
+        self.kind, self.coef, self.lx, self.ly = kind, coef, lx, ly
+        self.batch = batch
+        h = ctypes.c_void_p()
+        _check(lib().fftpde_evolve_create(context(u0.device.index), int(kind), _ptr(u0), _ptr(v0), nx, ny, batch,
+                                          float(lx), float(ly), float(coef), dt, _stream(u0), ctypes.byref(h)),
+               "fftpde_evolve_create")
+        self._h = h.value
+
+    def step(self, n: int, dt: float, out=None, v_out=None, want_u: bool = True, want_v: bool = False,
+             diag: bool = False):
+        """(u(t), u_t(t) or None, diag or None) at t = n dt; diag is a float64
+        device tensor [batch, 3] = (mean re, mean im, energy)."""
+        torch = _torch()
+        if self._h is None:
+            raise RuntimeError("evolution destroyed")
+        if want_u or out is not None:
+            out = out if out is not None else torch.empty(self.shape, dtype=self.dtype, device=self.device)
+        if want_v or v_out is not None:
+            v_out = v_out if v_out is not None else torch.empty(self.shape, dtype=self.dtype, device=self.device)
+        d = torch.empty((self.batch, 3), dtype=torch.float64, device=self.device) if diag else None
+        _check(lib().fftpde_evolve_step(self._h, int(n), float(dt), _ptr(out), _ptr(v_out), _ptr(d),
+                                        torch.cuda.current_stream(self.device).cuda_stream), "fftpde_evolve_step")
+        return out, v_out, d
+
+    def close(self):
+        if self._h is not None and _lib is not None:
+            _lib.fftpde_evolve_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -14,6 +14,17 @@ def tol_fp32(nx: int, ny: int, transforms: int) -> float:
     return transforms * 2e-6 * math.log2(max(nx, ny))
 
 
+def rel_err_vs_input(y, ref, input_norm: float) -> float:
+    """||y - ref|| / max(||ref||, input_norm): the FP32 bound is per transform,
+    and a transform's rounding error scales with the norm of its input.  For
+    solves whose symbol has |M| <= 1 (diffusion, wave) a result much smaller
+    than the initial data (e.g. cos(w t) near 0) keeps the forward transform's
+    error floor, relative to ||u0||."""
+    y = np.asarray(y, dtype=np.complex128).ravel()
+    ref = np.asarray(ref, dtype=np.complex128).ravel()
+    return float(np.linalg.norm(y - ref) / max(np.linalg.norm(ref), input_norm))
+
+
 def tol(dtype_name: str, nx: int, ny: int, transforms: int) -> float:
     return TOL_FP64 if dtype_name == "c128" else tol_fp32(nx, ny, transforms)
 

@@ -117,3 +117,17 @@ def test_create_without_a_gpu_fails_cleanly():
     rc = L.fftpde_create(ctypes.byref(h), 0)
     assert rc != fp.OK and h.value is None
     assert L.fftpde_destroy(None) == fp.OK
+
+
+def test_evolve_rejects_bad_arguments():
+    fp, L = _lib()
+    h = ctypes.c_void_p(7)
+    # diffusion with a velocity field, unknown kind, bad sizes, negative coefficient
+    assert L.fftpde_evolve_create(DUMMY, fp.DIFFUSION, P, P, 4, 4, 1, 1.0, 1.0, 0.1, 0, None, ctypes.byref(h)) == fp.EINVAL
+    assert h.value is None
+    assert L.fftpde_evolve_create(DUMMY, 7, P, None, 4, 4, 1, 1.0, 1.0, 0.1, 0, None, ctypes.byref(h)) == fp.EINVAL
+    assert L.fftpde_evolve_create(DUMMY, fp.WAVE, P, None, 6, 4, 1, 1.0, 1.0, 0.1, 0, None, ctypes.byref(h)) == fp.EINVAL
+    assert L.fftpde_evolve_create(DUMMY, fp.WAVE, P, None, 4, 4, 1, 1.0, 1.0, -1.0, 0, None, ctypes.byref(h)) == fp.EINVAL
+    assert L.fftpde_evolve_create(None, fp.WAVE, P, None, 4, 4, 1, 1.0, 1.0, 1.0, 0, None, ctypes.byref(h)) == fp.EINVAL
+    assert L.fftpde_evolve_step(None, 1, 0.1, None, None, None, None) == fp.EINVAL
+    assert L.fftpde_evolve_destroy(None) == fp.OK
