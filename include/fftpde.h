@@ -115,6 +115,12 @@ int fftpde_profile_read(fftpde_ctx *ctx, char *buf, size_t cap, size_t *needed);
  *   in speed and in rounding order only. */
 int fftpde_plan_variants(fftpde_ctx *ctx, char *buf, size_t cap, size_t *needed);
 int fftpde_plan_select(fftpde_ctx *ctx, const char *name);
+/* fftpde_plan_small: enable (default) or disable the single-pass small-grid
+ *   path: for the grids it is compiled for (both sides in [32, 512] with at most
+ *   16384 points in C64, [32, 256] and 8192 points in C128) a transform or a
+ *   single-field solve is one launch, one workgroup per field holding the
+ *   field in LDS (one HBM read and one write). */
+int fftpde_plan_small(fftpde_ctx *ctx, int enable);
 
 /* fftpde_autotune: for an (nx, ny, batch, dtype, op) solve (op one of
  *   FFTPDE_POISSON / DIFFUSION / WAVE, zero initial velocity), time every

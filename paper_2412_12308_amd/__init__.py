@@ -82,6 +82,7 @@ def _declare(L):
     L.fftpde_plan_variants.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t,
                                        ctypes.POINTER(ctypes.c_size_t)]
     L.fftpde_plan_select.argtypes = [vp, ctypes.c_char_p]
+    L.fftpde_plan_small.argtypes = [vp, i]
     L.fftpde_autotune.argtypes = [vp, i, i, i, i, i, i, vp, ctypes.c_char_p, ctypes.c_size_t,
                                   ctypes.POINTER(ctypes.c_size_t)]
     L.fftpde_plan_save.argtypes = [vp, ctypes.c_char_p]
@@ -89,7 +90,7 @@ def _declare(L):
     L.fftpde_evolve_create.argtypes = [vp, i, vp, vp, i, i, i, d, d, d, i, vp, ctypes.POINTER(vp)]
     L.fftpde_evolve_step.argtypes = [vp, ctypes.c_longlong, d, vp, vp, vp, vp]
     L.fftpde_evolve_destroy.argtypes = [vp]
-    for f in ("fftpde_evolve_create", "fftpde_evolve_step", "fftpde_evolve_destroy", "fftpde_autotune", "fftpde_plan_save", "fftpde_plan_load", "fftpde_plan_variants",
+    for f in ("fftpde_plan_small", "fftpde_evolve_create", "fftpde_evolve_step", "fftpde_evolve_destroy", "fftpde_autotune", "fftpde_plan_save", "fftpde_plan_load", "fftpde_plan_variants",
               "fftpde_plan_select", "fftpde_profile", "fftpde_profile_read", "fftpde_create", "fftpde_destroy", "fft2d_forward", "fft2d_inverse", "solve_poisson",
               "solve_diffusion", "solve_wave"):
         getattr(L, f).restype = i
@@ -161,6 +162,11 @@ def plan_variants(device: int = 0):
     buf = ctypes.create_string_buffer(max(2, need.value))
     _check(lib().fftpde_plan_variants(context(device), buf, len(buf), None), "fftpde_plan_variants")
     return json.loads(buf.value.decode())
+
+
+def plan_small(enable: bool, device: int = 0):
+    """Use (default) or bypass the single-pass small-grid kernels."""
+    _check(lib().fftpde_plan_small(context(device), 1 if enable else 0), "fftpde_plan_small")
 
 
 def plan_select(name: Optional[str], device: int = 0):

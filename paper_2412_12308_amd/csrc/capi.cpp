@@ -114,6 +114,15 @@ const ColVariant* Context::col_variant(int dtype, int logn, int nf) const {
   return nullptr;
 }
 
+const SmallVariant* Context::small_variant(int dtype, int lognx, int logny) const {
+  if (!use_small) return nullptr;
+  int n = 0;
+  const SmallVariant* t = dtype == FFTPDE_C64 ? small_variants_f32(&n) : small_variants_f64(&n);
+  for (int i = 0; i < n; i++)
+    if (t[i].lx == lognx && t[i].ly == logny) return &t[i];
+  return nullptr;
+}
+
 int Context::workspace(size_t bytes, void** p) {
   if (bytes <= work_bytes) {
     *p = work;
@@ -342,8 +351,26 @@ int fftpde_plan_variants(fftpde_ctx* ctx, char* buf, size_t cap, size_t* needed)
     out += line;
     first = false;
   });
+  for (int d = 0; d < 2; d++) {
+    int cnt = 0;
+    const SmallVariant* t = d == 0 ? small_variants_f32(&cnt) : small_variants_f64(&cnt);
+    for (int i = 0; i < cnt; i++) {
+      char line[256];
+      std::snprintf(line, sizeof(line),
+                    ", {\"name\": \"%s\", \"dtype\": %d, \"pass\": \"small\", \"lognx\": %d, \"logny\": %d, "
+                    "\"threads\": %d, \"active\": %d}",
+                    t[i].name, d, t[i].lx, t[i].ly, t[i].th, c->use_small ? 1 : 0);
+      out += line;
+    }
+  }
   out += "]";
   return copy_out(out, buf, cap, needed);
+}
+
+int fftpde_plan_small(fftpde_ctx* ctx, int enable) {
+  if (!ctx) return FFTPDE_EINVAL;
+  reinterpret_cast<Context*>(ctx)->use_small = enable != 0;
+  return FFTPDE_OK;
 }
 
 int fftpde_plan_select(fftpde_ctx* ctx, const char* name) {

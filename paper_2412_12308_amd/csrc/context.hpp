@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "small.hpp"
 
 namespace fftpde {
 
@@ -44,6 +45,11 @@ struct Context {
   std::unordered_map<const void*, int> occupancy;  // variant -> resident workgroups per CU
   // Workgroup cap for a persistent (prefetching) launch: all resident at once.
   long long max_blocks(const void* variant, OccFn occ);
+
+  // Single-pass small-grid kernels: used whenever one is compiled for the
+  // shape, unless switched off (fftpde_plan_small).
+  bool use_small = true;
+  const SmallVariant* small_variant(int dtype, int lognx, int logny) const;
 
   const RowVariant* row_variant(int dtype, int logn) const;
   const ColVariant* col_variant(int dtype, int logn, int nf) const;

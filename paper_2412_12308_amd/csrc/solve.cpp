@@ -142,8 +142,30 @@ int solve_wave_two(Context* c, const void* u0, const void* v0, void* u, void* v,
 }
 
 
+// One launch for the whole transform or solve when a single-pass small-grid
+// kernel exists for the shape; returns -100 when there is none.
+template <typename T>
+int small_pass(Context* c, const void* in, void* out, int nx, int ny, int batch, int mode, const SymParams& sym,
+               hipStream_t s) {
+  const SmallVariant* v = c->small_variant(sizeof(T) == 4 ? FFTPDE_C64 : FFTPDE_C128, ilog2(nx), ilog2(ny));
+  if (!v) return -100;
+  SmallArgs<T> a{static_cast<const cx<T>*>(in), static_cast<cx<T>*>(out), twiddles<T>(c), batch, mode, sym};
+  const double bytes = 2.0 * sizeof(cx<T>) * (double)nx * ny * batch;
+  hipError_t e = timed_launch(c, v->name, bytes, s, [&] { return v->launch(&a, batch, 0, s); });
+  if (e != hipSuccess) {
+    set_last_error(v->name, e);
+    return FFTPDE_EDEVICE;
+  }
+  return FFTPDE_OK;
+}
+
 int run_transform(Context* c, int dtype, bool inverse, const void* in, void* out, int nx, int ny, int batch,
                   hipStream_t s) {
+  const SymParams sym = make_sym(kSymScale, nx, ny, 1.0, 1.0, 0.0, 0.0);
+  const int mode = inverse ? kColInverse : kColForward;
+  const int r = dtype == FFTPDE_C64 ? small_pass<float>(c, in, out, nx, ny, batch, mode, sym, s)
+                                    : small_pass<double>(c, in, out, nx, ny, batch, mode, sym, s);
+  if (r != -100) return r;
   return dtype == FFTPDE_C64 ? transform<float>(c, in, out, nx, ny, batch, inverse, s)
                              : transform<double>(c, in, out, nx, ny, batch, inverse, s);
 }
@@ -152,9 +174,13 @@ int run_solve(Context* c, int dtype, int op, const void* in, const void* in2, vo
               int batch, double lx, double ly, double coef, double t, hipStream_t s) {
   const int sop = op == FFTPDE_POISSON ? kSymPoisson : op == FFTPDE_DIFFUSION ? kSymDiffusion : kSymWave;
   const SymParams sym = make_sym(sop, nx, ny, lx, ly, coef, t);
-  if (op != FFTPDE_WAVE || (!in2 && !out2))
+  if (op != FFTPDE_WAVE || (!in2 && !out2)) {
+    const int r = dtype == FFTPDE_C64 ? small_pass<float>(c, in, out, nx, ny, batch, kColFwdMulInv, sym, s)
+                                      : small_pass<double>(c, in, out, nx, ny, batch, kColFwdMulInv, sym, s);
+    if (r != -100) return r;
     return dtype == FFTPDE_C64 ? solve_real_symbol<float>(c, in, out, nx, ny, batch, sym, s)
                                : solve_real_symbol<double>(c, in, out, nx, ny, batch, sym, s);
+  }
   return dtype == FFTPDE_C64 ? solve_wave_two<float>(c, in, in2, out, out2, nx, ny, batch, sym, s)
                              : solve_wave_two<double>(c, in, in2, out, out2, nx, ny, batch, sym, s);
 }

@@ -30,8 +30,45 @@ def _variants():
 def _cases():
     out = []
     for v in _variants():
-        out.append(pytest.param(v, id=v["name"]))
+        if v["pass"] in ("row", "col"):
+            out.append(pytest.param(v, id=v["name"]))
     return out
+
+
+def _small_cases():
+    return [pytest.param(v, id=v["name"]) for v in _variants() if v["pass"] == "small"]
+
+
+@pytest.mark.parametrize("v", _small_cases())
+def test_small_grid_kernel(fp, v):
+    """The single-pass kernel for each compiled shape: forward, inverse and
+    the three solves against the oracle, and the solve against the 3-pass path."""
+    dt = "c64" if v["dtype"] == 0 else "c128"
+    nx, ny, batch = 1 << v["lognx"], 1 << v["logny"], 5
+    say(f"small {v['name']} batch={batch}")
+    x = W.random_field((batch, ny, nx), seed=nx * 3 + ny)
+    xd = to_dev(x, dt)
+    X = to_host(fp.fft2d_forward(xd))
+    Y = to_host(fp.fft2d_inverse(xd))
+    for b in (0, batch - 1):
+        xb = as_oracle_input(x[b], dt)
+        assert oracle.rel_l2(X[b], oracle.fft2d(xb)) <= tol(dt, nx, ny, 1)
+        assert oracle.rel_l2(Y[b], oracle.ifft2d(xb)) <= tol(dt, nx, ny, 1)
+    u_p = to_host(fp.solve_poisson(xd, 1.0, 2.0))
+    u_d = to_host(fp.solve_diffusion(xd, 0.05, 0.02, 1.0, 2.0))
+    u_w, _ = fp.solve_wave(xd, None, 1.0, 0.37, 1.0, 2.0)
+    u_w = to_host(u_w)
+    for b in (0, batch - 1):
+        xb = as_oracle_input(x[b], dt)
+        assert oracle.rel_l2(u_p[b], oracle.solve_poisson(xb, 1.0, 2.0)) <= tol(dt, nx, ny, 2)
+        assert oracle.rel_l2(u_d[b], oracle.solve_diffusion(xb, 1.0, 2.0, 0.05, 0.02)) <= tol(dt, nx, ny, 2)
+        assert oracle.rel_l2(u_w[b], oracle.solve_wave(xb, None, 1.0, 2.0, 1.0, 0.37)[0]) <= tol(dt, nx, ny, 2)
+    fp.plan_small(False)
+    try:
+        u3 = to_host(fp.solve_poisson(xd, 1.0, 2.0))
+    finally:
+        fp.plan_small(True)
+    assert oracle.rel_l2(u_p, u3) <= tol(dt, nx, ny, 2)
 
 
 @pytest.mark.parametrize("v", _cases())
