@@ -213,6 +213,56 @@ int fftpde_evolve_step(fftpde_evolve *ev, long long n, double dt, void *u, void 
                        fftpde_stream stream);
 int fftpde_evolve_destroy(fftpde_evolve *ev);
 
+/* ---- batches of uneven solves ---------------------------------------------
+ * Many independent solves of different power-of-two shapes, operators, boxes
+ * and times (the per-field work of Sec. III, for many small and medium
+ * fields at once) as ONE persistent kernel: every job is a row pass, a fused
+ * column pass (forward y FFT, symbol, inverse y FFT) and an inverse row pass,
+ * cut into tiles of 8192 (FP32) / 4096 (FP64) points; workgroups take tiles
+ * from one queue and a job's column tiles start as soon as its own row tiles
+ * are done.  Each job is computed exactly as the single-field solves above
+ * define it (same symbols, same FP64 phases and exponents).
+ *
+ * fftpde_job: op = FFTPDE_POISSON (coef, t unused), FFTPDE_DIFFUSION
+ *   (coef = kappa >= 0, t >= 0) or FFTPDE_WAVE (coef = c >= 0, t finite,
+ *   initial velocity 0); nx, ny powers of two in [16, 4096]; lx, ly > 0;
+ *   in, out: device fields of nx*ny points (in == out allowed).  No job's
+ *   out may overlap another job's in or out.
+ * fftpde_batch_create: checks every job, builds the queue (largest jobs
+ *   first) in device memory owned by the batch, and captures the launch in a
+ *   HIP graph.  The job pointers are fixed here: a run reads the inputs and
+ *   writes the outputs the jobs named, so new data is written into the same
+ *   buffers between runs.  Errors: EINVAL (any bad job or overlap; nothing is
+ *   allocated), ENOMEM, EDEVICE.
+ * fftpde_batch_run: enqueues one run on `stream`: replays the captured graph
+ *   (use_graph != 0) or launches the same two kernels directly (use_graph = 0,
+ *   e.g. inside a caller's own capture).  Runs of one batch share its queue
+ *   and counters: runs on different streams must not overlap in time.
+ * fftpde_batch_status: waits for `stream`, then returns FFTPDE_OK, or
+ *   FFTPDE_ETIMEOUT if a tile's wait for its job's previous step gave up
+ *   (about a second; results of that run are then invalid).
+ * fftpde_batch_info: number of tiles in the queue, workgroups launched and
+ *   algorithmic HBM bytes of one run (6 field passes per job); NULL outputs
+ *   are skipped.
+ * fftpde_batch_destroy: frees the batch (waits for nothing: the caller
+ *   ensures no run is still in flight); NULL ok. */
+typedef struct fftpde_job {
+  int op;
+  int nx, ny;
+  double lx, ly;
+  double coef;
+  double t;
+  const void *in;
+  void *out;
+} fftpde_job;
+
+int fftpde_batch_create(fftpde_ctx *ctx, const fftpde_job *jobs, int njobs, int dtype,
+                        fftpde_batch **batch);
+int fftpde_batch_run(fftpde_batch *batch, int use_graph, fftpde_stream stream);
+int fftpde_batch_status(fftpde_batch *batch, fftpde_stream stream);
+int fftpde_batch_info(const fftpde_batch *batch, long long *items, int *grid, double *bytes);
+int fftpde_batch_destroy(fftpde_batch *batch);
+
 #ifdef __cplusplus
 }
 #endif

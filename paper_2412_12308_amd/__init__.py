@@ -63,6 +63,13 @@ def lib() -> ctypes.CDLL:
     return _lib
 
 
+class FftpdeJob(ctypes.Structure):
+    """struct fftpde_job of the C ABI."""
+    _fields_ = [("op", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+                ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("coef", ctypes.c_double),
+                ("t", ctypes.c_double), ("inp", ctypes.c_void_p), ("out", ctypes.c_void_p)]
+
+
 def _declare(L):
     vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
     L.fftpde_create.argtypes = [ctypes.POINTER(vp), i]
@@ -90,7 +97,14 @@ def _declare(L):
     L.fftpde_evolve_create.argtypes = [vp, i, vp, vp, i, i, i, d, d, d, i, vp, ctypes.POINTER(vp)]
     L.fftpde_evolve_step.argtypes = [vp, ctypes.c_longlong, d, vp, vp, vp, vp]
     L.fftpde_evolve_destroy.argtypes = [vp]
-    for f in ("fftpde_plan_small", "fftpde_evolve_create", "fftpde_evolve_step", "fftpde_evolve_destroy", "fftpde_autotune", "fftpde_plan_save", "fftpde_plan_load", "fftpde_plan_variants",
+    L.fftpde_batch_create.argtypes = [vp, ctypes.POINTER(FftpdeJob), i, i, ctypes.POINTER(vp)]
+    L.fftpde_batch_run.argtypes = [vp, i, vp]
+    L.fftpde_batch_status.argtypes = [vp, vp]
+    L.fftpde_batch_info.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(i),
+                                    ctypes.POINTER(d)]
+    L.fftpde_batch_destroy.argtypes = [vp]
+    for f in ("fftpde_batch_create", "fftpde_batch_run", "fftpde_batch_status", "fftpde_batch_info",
+              "fftpde_batch_destroy", "fftpde_plan_small", "fftpde_evolve_create", "fftpde_evolve_step", "fftpde_evolve_destroy", "fftpde_autotune", "fftpde_plan_save", "fftpde_plan_load", "fftpde_plan_variants",
               "fftpde_plan_select", "fftpde_profile", "fftpde_profile_read", "fftpde_create", "fftpde_destroy", "fft2d_forward", "fft2d_inverse", "solve_poisson",
               "solve_diffusion", "solve_wave"):
         getattr(L, f).restype = i
@@ -343,6 +357,87 @@ class Evolution:
     def close(self):
         if self._h is not None and _lib is not None:
             _lib.fftpde_evolve_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Batch:
+    """Many independent solves of uneven power-of-two shapes run by one
+    persistent kernel (fftpde_batch_*), replayed from a captured HIP graph.
+
+    jobs: sequence of dicts with keys op (POISSON / DIFFUSION / WAVE), inp (a
+    [ny, nx] complex device tensor), and optionally out (default: a new
+    tensor; inp itself for in place), lx, ly (default 1.0), coef (kappa or c)
+    and t.  The tensors are kept alive by the batch; run() recomputes every
+    out from the current contents of every inp."""
+
+    def __init__(self, jobs):
+        torch = _torch()
+        jobs = list(jobs)
+        if not jobs:
+            raise ValueError("a batch needs at least one job")
+        first = jobs[0]["inp"]
+        self.device, self.dtype = first.device, first.dtype
+        self.inputs, self.outputs = [], []
+        arr = (FftpdeJob * len(jobs))()
+        dt = None
+        for k, j in enumerate(jobs):
+            inp = j["inp"]
+            nx, ny, b, code = _field(inp, f"jobs[{k}].inp")
+            if b != 1 or inp.dim() != 2:
+                raise ValueError("each job is one [ny, nx] field")
+            if inp.device != self.device or inp.dtype != self.dtype:
+                raise ValueError("all jobs must share one device and dtype")
+            out = j.get("out")
+            if out is None:
+                out = torch.empty_like(inp)
+            elif tuple(out.shape) != tuple(inp.shape) or out.dtype != inp.dtype or not out.is_contiguous():
+                raise ValueError(f"jobs[{k}].out must match jobs[{k}].inp")
+            dt = code
+            self.inputs.append(inp)
+            self.outputs.append(out)
+            arr[k] = FftpdeJob(int(j["op"]), nx, ny, float(j.get("lx", 1.0)), float(j.get("ly", 1.0)),
+                               float(j.get("coef", 0.0)), float(j.get("t", 0.0)), inp.data_ptr(),
+                               out.data_ptr())
+        # the plan's copies are synchronous: order them after pending work
+        torch.cuda.current_stream(self.device).synchronize()
+        h = ctypes.c_void_p()
+        _check(lib().fftpde_batch_create(context(self.device.index), arr, len(jobs), dt, ctypes.byref(h)),
+               "fftpde_batch_create")
+        self._h = h.value
+        items, grid, nbytes = ctypes.c_longlong(), ctypes.c_int(), ctypes.c_double()
+        _check(lib().fftpde_batch_info(self._h, ctypes.byref(items), ctypes.byref(grid), ctypes.byref(nbytes)),
+               "fftpde_batch_info")
+        self.items, self.grid, self.bytes = items.value, grid.value, nbytes.value
+
+    def run(self, use_graph: bool = True):
+        """Enqueue one run on the current stream; returns the output tensors."""
+        if self._h is None:
+            raise RuntimeError("batch destroyed")
+        s = _torch().cuda.current_stream(self.device).cuda_stream
+        _check(lib().fftpde_batch_run(self._h, 1 if use_graph else 0, s), "fftpde_batch_run")
+        return self.outputs
+
+    def status(self):
+        """Wait for the current stream; raise if a dependency wait timed out."""
+        s = _torch().cuda.current_stream(self.device).cuda_stream
+        _check(lib().fftpde_batch_status(self._h, s), "fftpde_batch_status")
+
+    def close(self):
+        if self._h is not None and _lib is not None:
+            _torch().cuda.current_stream(self.device).synchronize()
+            _lib.fftpde_batch_destroy(self._h)
         self._h = None
 
     def __del__(self):

@@ -1,0 +1,188 @@
+// batch.hip -- the persistent batch kernel: queue, per-job dependencies and
+// the row / column tiles for every side 16..4096 (one workgroup of 512).
+#include "batch.hpp"
+
+namespace fftpde {
+namespace {
+
+// Row tile: LINES rows of length 2^LOGN, forward (or inverse by conjugation).
+template <typename T, int LOGN>
+__device__ __forceinline__ void row_tile(const cx<T>* __restrict__ in, cx<T>* out, int nrows, int tile,
+                                         bool inverse, const cx<T>* __restrict__ tw, cx<T>* lds, int tid) {
+  constexpr int E = BatchCfg<T>::E;
+  constexpr int N = 1 << LOGN;
+  constexpr int LINES = BatchCfg<T>::kTile / N;
+  using Map = RowMap<LOGN, LINES, plan_pad(LOGN, 3, false)>;
+  using Eng = Engine<T, LOGN, E, kBatchTH, 3, false, Map, false>;
+  static_assert(Map::kLdsElems <= BatchCfg<T>::kLdsElems, "row tile exceeds the batch LDS buffer");
+  const T sgn = inverse ? T(-1) : T(1);
+  const int row0 = tile * LINES;
+  cx<T> x[E];
+  // rows past the field reread the last row and are never stored
+  Eng::for_each_input(tid, [&](int i, int line, int n) {
+    const int row = min(row0 + line, nrows - 1);
+    const cx<T> v = in[((long long)row << LOGN) + n];
+    x[i] = {v.re, sgn * v.im};
+  });
+  Eng::run(x, lds, tw, tid);
+  Eng::for_each_output(tid, [&](int i, int line, int n) {
+    const int row = row0 + line;
+    if (row < nrows) out[((long long)row << LOGN) + n] = {x[i].re, sgn * x[i].im};
+  });
+}
+
+// Column tile of one job: 2^LOGT columns of length 2^LOGN; forward y
+// transform, the real symbol (1/(nx ny) folded in), inverse y transform.
+template <typename T, int LOGN>
+__device__ __forceinline__ void col_tile(cx<T>* data, int lognx, int tile, const SymParams& sym,
+                                         const cx<T>* __restrict__ tw, cx<T>* lds, int tid) {
+  constexpr int E = BatchCfg<T>::E;
+  constexpr int LOGT = BatchCfg<T>::kLogTile - LOGN;
+  constexpr int TT = 1 << LOGT;
+  static_assert(TT << LOGN == BatchCfg<T>::kTile, "tile holds whole columns");
+  static_assert(kBatchTH % TT == 0, "every thread stays on one column of the tile");
+  using FMap = ColMap<LOGN, LOGT, plan_pad(LOGN, 3, false)>;
+  using IMap = ColMap<LOGN, LOGT, plan_pad(LOGN, 3, true)>;
+  using Fwd = Engine<T, LOGN, E, kBatchTH, 3, false, FMap, false>;
+  using Inv = Engine<T, LOGN, E, kBatchTH, 3, true, IMap, false>;
+  static_assert(FMap::kLdsElems <= BatchCfg<T>::kLdsElems && IMap::kLdsElems <= BatchCfg<T>::kLdsElems,
+                "column tile exceeds the batch LDS buffer");
+  const int ncols = 1 << lognx;
+  // this thread's column; columns past the field reread the last column and
+  // are never stored, so the loads carry no branches
+  const int C = (tile << LOGT) + (tid & (TT - 1));
+  const int Cl = min(C, ncols - 1);
+  const cx<T>* src = data + Cl;
+  cx<T> x[E];
+  Fwd::for_each_input(tid, [&](int i, int, int n) { x[i] = src[(long long)n << lognx]; });
+  Fwd::run(x, lds, tw, tid);
+  auto mul = [&](auto tag) {
+    constexpr int OP = decltype(tag)::value;
+    const Symbol<T, OP> s(sym, Cl);
+    Inv::for_each_input(tid, [&](int i, int, int n) {
+      const T m = s(n);
+      x[i] = {x[i].re * m, -x[i].im * m};
+    });
+  };
+  switch (sym.op) {
+    case kSymPoisson: mul(std::integral_constant<int, kSymPoisson>()); break;
+    case kSymDiffusion: mul(std::integral_constant<int, kSymDiffusion>()); break;
+    case kSymWave: mul(std::integral_constant<int, kSymWave>()); break;
+    default: mul(std::integral_constant<int, kSymScale>()); break;
+  }
+  Inv::run(x, lds, tw, tid);
+  if (C < ncols) {
+    cx<T>* dst = data + C;
+    Inv::for_each_output(tid, [&](int i, int, int n) { dst[(long long)n << lognx] = conjg(x[i]); });
+  }
+}
+
+template <typename T, int L = kBatchMinLog>
+__device__ __forceinline__ void dispatch_row(int logn, const cx<T>* in, cx<T>* out, int nrows, int tile,
+                                             bool inverse, const cx<T>* tw, cx<T>* lds, int tid) {
+  if constexpr (L <= kBatchMaxLog) {
+    if (logn == L) row_tile<T, L>(in, out, nrows, tile, inverse, tw, lds, tid);
+    else dispatch_row<T, L + 1>(logn, in, out, nrows, tile, inverse, tw, lds, tid);
+  }
+}
+
+template <typename T, int L = kBatchMinLog>
+__device__ __forceinline__ void dispatch_col(int logn, cx<T>* data, int lognx, int tile, const SymParams& sym,
+                                             const cx<T>* tw, cx<T>* lds, int tid) {
+  if constexpr (L <= kBatchMaxLog) {
+    if (logn == L) col_tile<T, L>(data, lognx, tile, sym, tw, lds, tid);
+    else dispatch_col<T, L + 1>(logn, data, lognx, tile, sym, tw, lds, tid);
+  }
+}
+
+// about a second of polling
+constexpr long kSpinLimit = 1l << 22;
+
+template <typename T>
+__global__ void __launch_bounds__(kBatchTH) batch_kernel(BatchArgs a) {
+  __shared__ cx<T> lds[BatchCfg<T>::kLdsElems];
+  __shared__ long long s_item;
+  int tid = threadIdx.x;
+  const cx<T>* tw = static_cast<const cx<T>*>(a.tw);
+  while (true) {
+    // keeps per-stage addresses from being hoisted out of the item loop
+    // (they would all stay live in registers across items)
+    tid = opaque(tid);
+    if (tid == 0)
+      s_item = (long long)__hip_atomic_fetch_add(&a.ctl->head, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const long long it = s_item;
+    __syncthreads();
+    if (it >= a.nitems) break;
+    const BatchItem item = a.items[it];
+    const BatchJobDesc& job = a.jobs[item.job];
+    if (item.step > 0) {
+      // wait for the job's previous step (acquire); a timeout is reported,
+      // never waited out
+      if (tid == 0) {
+        const unsigned* cnt = &a.done[2 * item.job + item.step - 1];
+        long spins = 0;
+        while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < (unsigned)item.need) {
+          __builtin_amdgcn_s_sleep(8);
+          if (++spins > kSpinLimit) {
+            __hip_atomic_store(&a.ctl->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+          }
+        }
+      }
+      __syncthreads();
+      // every wave drops cached lines another XCD may have rewritten
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    const int lognx = job.sym.lognx, logny = job.sym.logny;
+    cx<T>* out = static_cast<cx<T>*>(job.out);
+    if (item.step == 1) {
+      dispatch_col<T>(logny, out, lognx, item.tile, job.sym, tw, lds, tid);
+    } else {
+      const cx<T>* src = item.step == 0 ? static_cast<const cx<T>*>(job.in) : out;
+      dispatch_row<T>(lognx, src, out, 1 << logny, item.tile, item.step == 2, tw, lds, tid);
+    }
+    if (item.step < 2) {
+      // publish this tile (release by every wave, then one count)
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __syncthreads();
+      if (tid == 0)
+        __hip_atomic_fetch_add(&a.done[2 * item.job + item.step], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+__global__ void batch_reset_kernel(BatchCtl* ctl, unsigned* done, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    ctl->head = 0;
+    ctl->error = 0;
+  }
+  if (i < n) done[i] = 0;
+}
+
+template <typename T>
+int occ() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel<T>, kBatchTH, 0) != hipSuccess) return 0;
+  return n;
+}
+
+}  // namespace
+
+hipError_t batch_launch(int fp64, const BatchArgs& a, int grid, hipStream_t s) {
+  if (fp64) hipLaunchKernelGGL(batch_kernel<double>, dim3(grid), dim3(kBatchTH), 0, s, a);
+  else hipLaunchKernelGGL(batch_kernel<float>, dim3(grid), dim3(kBatchTH), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t batch_reset(BatchCtl* ctl, unsigned* done, int njobs, hipStream_t s) {
+  const int n = 2 * njobs;
+  const int blocks = n / 256 + 1;
+  hipLaunchKernelGGL(batch_reset_kernel, dim3(blocks), dim3(256), 0, s, ctl, done, n);
+  return hipGetLastError();
+}
+
+int batch_occupancy(int fp64) { return fp64 ? occ<double>() : occ<float>(); }
+
+}  // namespace fftpde

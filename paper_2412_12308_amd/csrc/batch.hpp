@@ -1,0 +1,74 @@
+// batch.hpp -- one persistent kernel for a batch of independent solves of
+// uneven power-of-two shapes (many small and medium fields at once, each with
+// its own box, operator and time).
+//
+// Every job is three steps of tiles: row tiles of x forward transforms
+// (in -> out), column tiles that run the y forward transform, multiply by the
+// job's symbol and run the y inverse (out -> out), and row tiles of x inverse
+// transforms (out -> out).  All tiles of all jobs sit in one queue, first
+// every row-forward tile, then every column tile, then every row-inverse
+// tile, largest jobs first.  Workgroups pop items with an atomic counter; an
+// item of step s waits until its job's step s-1 tiles are all done (a per-job
+// counter).  An item only ever waits on items earlier in the queue, which are
+// held by running workgroups, so the queue drains whatever the number of
+// resident workgroups.  Each wait is still bounded and reports a timeout
+// through an error flag instead of spinning forever.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace fftpde {
+
+constexpr int kBatchTH = 512;
+constexpr int kBatchMinLog = 4;   // sides 16 ..
+constexpr int kBatchMaxLog = 12;  // .. 4096
+
+template <typename T>
+struct BatchCfg {
+  // points per tile: 8192 FP32 / 4096 FP64 (16 / 8 per thread)
+  static constexpr int E = sizeof(T) == 4 ? 16 : 8;
+  static constexpr int kLogTile = sizeof(T) == 4 ? 13 : 12;
+  static constexpr int kTile = E * kBatchTH;
+  static constexpr int kLdsElems = kTile + kTile / 8;  // the engines pad by at most 1 in 8
+};
+
+constexpr int batch_log_tile(int dtype_fp64) { return dtype_fp64 ? 12 : 13; }
+
+struct BatchJobDesc {
+  const void* in;
+  void* out;
+  SymParams sym;  // op, lognx, logny, wavenumber scales, 1/(nx ny)
+};
+
+struct BatchItem {
+  int job;
+  int step;   // 0: row forward, 1: column, 2: row inverse
+  int tile;
+  int need;   // tiles of the job's previous step (0 for step 0)
+};
+
+struct BatchCtl {
+  unsigned long long head;  // next item
+  int error;                // 1: a dependency wait timed out
+  int pad;
+};
+
+struct BatchArgs {
+  const BatchJobDesc* jobs;
+  const BatchItem* items;
+  long long nitems;
+  BatchCtl* ctl;
+  unsigned* done;  // per job: [row-forward tiles done, column tiles done]
+  int njobs;
+  const void* tw;
+};
+
+hipError_t batch_launch(int fp64, const BatchArgs& a, int grid, hipStream_t s);
+// Clears the queue head, the error flag and the per-job counters (a kernel,
+// so the reset may be captured in a graph).
+hipError_t batch_reset(BatchCtl* ctl, unsigned* done, int njobs, hipStream_t s);
+int batch_occupancy(int fp64);
+
+}  // namespace fftpde

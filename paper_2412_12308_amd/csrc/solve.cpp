@@ -18,22 +18,7 @@ int ilog2(int n) {
   return l;
 }
 
-// Launch through `fn`, bracketed by events when profiling is on.
-template <class F>
-hipError_t timed_launch(Context* c, const char* name, double bytes, hipStream_t s, F&& fn) {
-  if (!c->profiling) return fn();
-  hipEvent_t a = c->take_event(), b = c->take_event();
-  if (!a || !b) return fn();
-  (void)hipEventRecord(a, s);
-  hipError_t e = fn();
-  (void)hipEventRecord(b, s);
-  c->timed.push_back({name, bytes, a, b});
-  return e;
-}
-
-
 }  // namespace
-
 
 template <typename T>
 static const cx<T>* twiddles(const Context* c) {

@@ -131,3 +131,70 @@ def test_evolve_rejects_bad_arguments():
     assert L.fftpde_evolve_create(None, fp.WAVE, P, None, 4, 4, 1, 1.0, 1.0, 1.0, 0, None, ctypes.byref(h)) == fp.EINVAL
     assert L.fftpde_evolve_step(None, 1, 0.1, None, None, None, None) == fp.EINVAL
     assert L.fftpde_evolve_destroy(None) == fp.OK
+
+
+def _jobs(*specs):
+    """fftpde_job array from (op, nx, ny, lx, ly, coef, t, in, out) tuples."""
+    import paper_2412_12308_amd as fp
+    arr = (fp.FftpdeJob * len(specs))()
+    for k, s in enumerate(specs):
+        arr[k] = fp.FftpdeJob(*s)
+    return arr
+
+
+# Fake device addresses: batch planning checks every job (shape, box,
+# coefficients, alignment, overlaps) before touching the context or device.
+A = 1 << 32
+FIELD = 64 * 64 * 8  # a 64x64 FP32 field
+
+
+@pytest.mark.parametrize("job", [
+    (3, 64, 64, 1.0, 1.0, 0.0, 0.0, A, A + FIELD),          # unknown operator
+    (0, 8, 64, 1.0, 1.0, 0.0, 0.0, A, A + FIELD),           # side below 16
+    (0, 64, 8192, 1.0, 1.0, 0.0, 0.0, A, A + (1 << 24)),    # side above 4096
+    (0, 48, 64, 1.0, 1.0, 0.0, 0.0, A, A + FIELD),          # not a power of two
+    (0, 64, 64, 0.0, 1.0, 0.0, 0.0, A, A + FIELD),          # empty box
+    (1, 64, 64, 1.0, 1.0, -0.1, 0.1, A, A + FIELD),         # negative diffusivity
+    (1, 64, 64, 1.0, 1.0, 0.1, -0.1, A, A + FIELD),         # backward heat equation
+    (2, 64, 64, 1.0, 1.0, -1.0, 0.1, A, A + FIELD),         # negative wave speed
+    (2, 64, 64, 1.0, 1.0, 1.0, math.inf, A, A + FIELD),     # non-finite time
+    (0, 64, 64, 1.0, 1.0, 0.0, 0.0, None, A + FIELD),       # null input
+    (0, 64, 64, 1.0, 1.0, 0.0, 0.0, A + 4, A + FIELD),      # misaligned input
+    (0, 64, 64, 1.0, 1.0, 0.0, 0.0, A, A + FIELD // 2),     # in and out partly overlap
+])
+def test_batch_rejects_bad_jobs(job):
+    fp, L = _lib()
+    h = ctypes.c_void_p(9)
+    good = (0, 64, 64, 1.0, 1.0, 0.0, 0.0, A + 8 * FIELD, A + 9 * FIELD)
+    assert L.fftpde_batch_create(DUMMY, _jobs(good, job), 2, fp.C64, ctypes.byref(h)) == fp.EINVAL
+    assert h.value is None
+
+
+def test_batch_rejects_overlapping_outputs_and_bad_arguments():
+    fp, L = _lib()
+    h = ctypes.c_void_p()
+    j1 = (0, 64, 64, 1.0, 1.0, 0.0, 0.0, A, A + 4 * FIELD)
+    j2 = (1, 64, 64, 1.0, 1.0, 0.1, 0.1, A + FIELD, A + 4 * FIELD + FIELD // 2)   # outputs overlap
+    j3 = (0, 64, 64, 1.0, 1.0, 0.0, 0.0, A + 4 * FIELD, A + 6 * FIELD)           # reads j1's output
+    assert L.fftpde_batch_create(DUMMY, _jobs(j1, j2), 2, fp.C64, ctypes.byref(h)) == fp.EINVAL
+    assert L.fftpde_batch_create(DUMMY, _jobs(j1, j3), 2, fp.C64, ctypes.byref(h)) == fp.EINVAL
+    assert L.fftpde_batch_create(None, _jobs(j1), 1, fp.C64, ctypes.byref(h)) == fp.EINVAL
+    assert L.fftpde_batch_create(DUMMY, _jobs(j1), 0, fp.C64, ctypes.byref(h)) == fp.EINVAL
+    assert L.fftpde_batch_create(DUMMY, _jobs(j1), 1, 2, ctypes.byref(h)) == fp.EINVAL
+    assert L.fftpde_batch_create(DUMMY, _jobs(j1), 1, fp.C64, None) == fp.EINVAL
+    # FP64 needs 16-byte alignment
+    j4 = (0, 64, 64, 1.0, 1.0, 0.0, 0.0, A + 8, A + 8 * FIELD)
+    assert L.fftpde_batch_create(DUMMY, _jobs(j4), 1, fp.C128, ctypes.byref(h)) == fp.EINVAL
+    assert L.fftpde_batch_run(None, 1, None) == fp.EINVAL
+    assert L.fftpde_batch_status(None, None) == fp.EINVAL
+    assert L.fftpde_batch_info(None, None, None, None) == fp.EINVAL
+    assert L.fftpde_batch_destroy(None) == fp.OK
+
+
+def test_job_struct_layout_matches_the_header():
+    """ctypes' fftpde_job must have the C layout (int, int, int, 4 doubles,
+    2 pointers, natural alignment)."""
+    import paper_2412_12308_amd as fp
+    J = fp.FftpdeJob
+    assert J.lx.offset == 16 and J.t.offset == 40 and J.inp.offset == 48 and J.out.offset == 56
+    assert ctypes.sizeof(J) == 64
