@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <climits>
 #include <numeric>
 #include <vector>
 
@@ -139,6 +140,8 @@ int fftpde_batch_create(fftpde_ctx* ctx, const fftpde_job* jobs, int njobs, int 
     for (int i : order)
       for (int t = 0; t < ntile[s][i]; t++) items.push_back({i, s, t, s > 0 ? ntile[s - 1][i] : 0});
 
+  if (items.size() > (size_t)0x7fffffff) return FFTPDE_EINVAL;  // 32-bit tile counters
+
   auto* b = new fftpde_batch();
   b->ctx = c;
   b->dtype = dtype;
@@ -168,6 +171,11 @@ int fftpde_batch_create(fftpde_ctx* ctx, const fftpde_job* jobs, int njobs, int 
   b->args.items = reinterpret_cast<const BatchItem*>(base + o_items);
   b->args.nitems = b->nitems;
   b->args.njobs = njobs;
+  for (int s = 0; s < 2; s++) {
+    long long n = 0;
+    for (int i = 0; i < njobs; i++) n += ntile[s][i];
+    b->args.step_items[s] = (unsigned)n;
+  }
   b->args.tw = fp64 ? static_cast<const void*>(c->tw64) : static_cast<const void*>(c->tw32);
   e = hipMemcpy(base + o_jobs, desc.data(), sizeof(BatchJobDesc) * desc.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess)

@@ -97,13 +97,48 @@ __device__ __forceinline__ void dispatch_col(int logn, cx<T>* data, int lognx, i
 
 // about a second of polling
 constexpr long kSpinLimit = 1l << 22;
+// completions a workgroup may hold before it publishes them
+constexpr int kMaxPending = 64;
 
+// Publication.  A finished row-forward or column tile is not announced at
+// once: the workgroup notes it (job counter index) in LDS and publishes its
+// notes together -- every wave drains its stores, one agent-scope release
+// (an L2 write-back) covers the workgroup, then relaxed counter increments --
+// before it takes an item of a later step (the only items that may wait),
+// when the notes are full, and when the queue is empty.  A workgroup holding
+// unpublished notes is thus always working on an item that does not wait, so
+// every note is eventually published and no wait can be circular.
+//
+// Acquisition.  A waiting item spins on its job's counter, then one wave
+// performs an agent-scope acquire (invalidating this CU's and XCD's cached
+// lines) before any wave reads.  Once a workgroup has done that after the
+// whole batch's previous step was published (the step counters), its later
+// items of that step need neither the wait nor the invalidation.
 template <typename T>
 __global__ void __launch_bounds__(kBatchTH) batch_kernel(BatchArgs a) {
   __shared__ cx<T> lds[BatchCfg<T>::kLdsElems];
   __shared__ long long s_item;
+  __shared__ int s_note[kMaxPending];
+  __shared__ int s_flag;
   int tid = threadIdx.x;
   const cx<T>* tw = static_cast<const cx<T>*>(a.tw);
+  int nnote = 0, note_step = 0;  // uniform across the workgroup
+  int acquired = 0;              // bit s: step s items need no wait
+
+  auto publish = [&]() {
+    if (nnote == 0) return;
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have reached its L2
+    __syncthreads();
+    if (tid == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      for (int k = 0; k < nnote; k++)
+        __hip_atomic_fetch_add(&a.done[s_note[k]], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&a.ctl->step_done[note_step], (unsigned)nnote, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    }
+    nnote = 0;
+  };
+
   while (true) {
     // keeps per-stage addresses from being hoisted out of the item loop
     // (they would all stay live in registers across items)
@@ -115,25 +150,27 @@ __global__ void __launch_bounds__(kBatchTH) batch_kernel(BatchArgs a) {
     __syncthreads();
     if (it >= a.nitems) break;
     const BatchItem item = a.items[it];
-    const BatchJobDesc& job = a.jobs[item.job];
-    if (item.step > 0) {
-      // wait for the job's previous step (acquire); a timeout is reported,
-      // never waited out
+    if (nnote > 0 && (item.step != note_step || nnote == kMaxPending)) publish();
+    if (item.step > 0 && !((acquired >> item.step) & 1)) {
       if (tid == 0) {
         const unsigned* cnt = &a.done[2 * item.job + item.step - 1];
         long spins = 0;
-        while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < (unsigned)item.need) {
+        while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (unsigned)item.need) {
           __builtin_amdgcn_s_sleep(8);
           if (++spins > kSpinLimit) {
             __hip_atomic_store(&a.ctl->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             break;
           }
         }
+        const unsigned all = __hip_atomic_load(&a.ctl->step_done[item.step - 1], __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        s_flag = all >= a.step_items[item.step - 1];
       }
       __syncthreads();
-      // every wave drops cached lines another XCD may have rewritten
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      if (s_flag) acquired |= 1 << item.step;
     }
+    const BatchJobDesc& job = a.jobs[item.job];
     const int lognx = job.sym.lognx, logny = job.sym.logny;
     cx<T>* out = static_cast<cx<T>*>(job.out);
     if (item.step == 1) {
@@ -143,19 +180,20 @@ __global__ void __launch_bounds__(kBatchTH) batch_kernel(BatchArgs a) {
       dispatch_row<T>(lognx, src, out, 1 << logny, item.tile, item.step == 2, tw, lds, tid);
     }
     if (item.step < 2) {
-      // publish this tile (release by every wave, then one count)
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      __syncthreads();
-      if (tid == 0)
-        __hip_atomic_fetch_add(&a.done[2 * item.job + item.step], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      if (tid == 0) s_note[nnote] = 2 * item.job + item.step;
+      note_step = item.step;
+      nnote++;
     }
   }
+  publish();
 }
 
 __global__ void batch_reset_kernel(BatchCtl* ctl, unsigned* done, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) {
     ctl->head = 0;
+    ctl->step_done[0] = 0;
+    ctl->step_done[1] = 0;
     ctl->error = 0;
   }
   if (i < n) done[i] = 0;

@@ -8,11 +8,11 @@
 // transforms (out -> out).  All tiles of all jobs sit in one queue, first
 // every row-forward tile, then every column tile, then every row-inverse
 // tile, largest jobs first.  Workgroups pop items with an atomic counter; an
-// item of step s waits until its job's step s-1 tiles are all done (a per-job
-// counter).  An item only ever waits on items earlier in the queue, which are
-// held by running workgroups, so the queue drains whatever the number of
-// resident workgroups.  Each wait is still bounded and reports a timeout
-// through an error flag instead of spinning forever.
+// item of step s waits until its job's step s-1 tiles are all published (a
+// per-job counter).  An item only ever waits on items earlier in the queue, so
+// the queue drains whatever the number of resident workgroups (see the
+// publication rule in batch.hip).  Each wait is still bounded and reports a
+// timeout through an error flag instead of spinning forever.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -51,6 +51,7 @@ struct BatchItem {
 
 struct BatchCtl {
   unsigned long long head;  // next item
+  unsigned step_done[2];    // published tiles of steps 0 and 1, whole batch
   int error;                // 1: a dependency wait timed out
   int pad;
 };
@@ -62,6 +63,7 @@ struct BatchArgs {
   BatchCtl* ctl;
   unsigned* done;  // per job: [row-forward tiles done, column tiles done]
   int njobs;
+  unsigned step_items[2];  // tiles of steps 0 and 1, whole batch
   const void* tw;
 };
 
