@@ -263,6 +263,125 @@ int fftpde_batch_status(fftpde_batch *batch, fftpde_stream stream);
 int fftpde_batch_info(const fftpde_batch *batch, long long *items, int *grid, double *bytes);
 int fftpde_batch_destroy(fftpde_batch *batch);
 
+/* ---- request server ------------------------------------------------------
+ * A server runs submitted solves and time evolutions on one GPU with
+ * continuous batching: a host thread repeatedly admits queued requests
+ * (first come, first served) while the HBM budget and the slots allow, then
+ * runs one iteration over the running requests -- each gets its next piece of
+ * work (the whole Poisson solve; the forward transforms of an evolution; up
+ * to 16 steps of diagnostics; the final field) -- on one of a few streams, so
+ * requests overlap on the device and new requests join at the next
+ * iteration.  An evolving request keeps the spectra of its initial data on
+ * the device between steps (Eq. (solCalorFourier); Eq. (OmegaNonZero),
+ * (OmegaZero) with s = 0): a step is the closed form at the absolute time
+ * t_n = n dt.  At most two iterations are in flight.
+ *
+ * fftpde_request: op = FFTPDE_POISSON (steps must be 1), FFTPDE_DIFFUSION
+ *   (coef = kappa >= 0, dt >= 0) or FFTPDE_WAVE (coef = c >= 0, dt finite);
+ *   dtype; nx, ny powers of two in [2, 4096]; lx, ly > 0; steps >= 1.
+ *   in: device field (source s, or u0); v0: wave initial velocity or NULL.
+ *   out: device field that receives u at t = steps*dt (Poisson: the
+ *   solution), or NULL: the server then owns the output (charged to the
+ *   budget) until fftpde_server_release.  diag: NULL, or a device array of
+ *   3*steps doubles that receives (mean re, mean im, energy) at t_1..t_steps
+ *   (as fftpde_evolve_step); Poisson requests take no diag.  deadline: seconds
+ *   after submission (<= 0: none); a request not done by then ends with
+ *   FFTPDE_ETIMEOUT.  flags: FFTPDE_REQ_AUTORELEASE forgets the request (and
+ *   frees a server-owned output) as soon as it ends, for callers that only
+ *   want the statistics.  stream: the request's work starts after the work
+ *   enqueued on this stream before submission (e.g. what produced `in`);
+ *   NULL: the inputs are ready at submission.  The caller keeps in, v0, out
+ *   and diag valid until the request has ended.
+ * Budget.  A request is charged its footprint while it runs: the bytes of its
+ *   fields (in, v0, out) plus what the server allocates for it (the resident
+ *   spectra, a reduction scratch, a server-owned output) from a pool of
+ *   `hbm_budget` bytes reserved at creation.  A request whose footprint
+ *   exceeds the whole budget is rejected at submission (FFTPDE_EBUDGET); one
+ *   that does not fit now waits, and so do all requests behind it.
+ * fftpde_server_create: ctx names the device (the server keeps its own
+ *   context and streams); max_slots >= 1 requests run at once; nstreams in
+ *   [1, 8].
+ * fftpde_server_create_host: the same scheduler with a host backend for
+ *   testing it without a GPU: two worker threads stand for the streams, and
+ *   every piece of work calls exec(user, id, req, out, phase, n0, nt) on the
+ *   request's worker, in order (phase 0: start; 1: steps n0..n0+nt-1; 2: the
+ *   final field into out, host memory); a nonzero return fails the request
+ *   and skips its remaining work.  The pool is host memory (budget <= 1 GiB).
+ * fftpde_server_submit: checks the request (EINVAL, EBUDGET) and queues it;
+ *   *id identifies it until released.
+ * fftpde_server_poll: FFTPDE_PENDING while queued or running, else the final
+ *   status (OK, EDEVICE, ECANCELED, ETIMEOUT, or the host backend's error);
+ *   fills *res when res != NULL.  ENOTFOUND for unknown or released ids.
+ * fftpde_server_wait: as poll, blocking up to timeout seconds (< 0: forever).
+ * fftpde_server_cancel: a queued request ends at once with ECANCELED; a
+ *   running one issues no further work and ends with ECANCELED once its work
+ *   in flight is done; an ended one is left as it is.
+ * fftpde_server_copy_out: enqueues a copy of a successfully ended request's
+ *   output (nx*ny points) to dst (device memory, or host memory for the host
+ *   backend) on `stream`; EINVAL unless the request ended with FFTPDE_OK.
+ * fftpde_server_release: forgets an ended request and frees a server-owned
+ *   output; EINVAL if it has not ended.
+ * fftpde_server_stats: counters, HBM in use and high-water mark, and the
+ *   p50/p99 latency (end - submission, ms) over requests completed OK since
+ *   the last reset (reset != 0 resets the latency record and the high-water
+ *   mark after reading).
+ * fftpde_server_destroy: cancels queued requests, waits for running ones,
+ *   stops the thread and frees everything; NULL ok. */
+#define FFTPDE_REQ_AUTORELEASE 1
+
+typedef struct fftpde_request {
+  int op;
+  int dtype;
+  int nx, ny;
+  double lx, ly;
+  double coef;
+  double dt;
+  long long steps;
+  const void *in;
+  const void *v0;
+  void *out;
+  double *diag;
+  double deadline;
+  int flags;
+  fftpde_stream stream;
+} fftpde_request;
+
+typedef struct fftpde_result {
+  int status;               /* FFTPDE_PENDING, or the final status */
+  int state;                /* 0 queued, 1 running, 2 ended */
+  double t_submit;          /* seconds on the server clock */
+  double t_admit;           /* -1 until admitted */
+  double t_done;            /* -1 until ended */
+  void *out;                /* where u is (the request's out, or server-owned) */
+  long long footprint;      /* bytes charged to the budget */
+} fftpde_result;
+
+typedef struct fftpde_stats {
+  long long submitted, rejected, admitted, completed, failed, canceled, timed_out;
+  long long queued, running;
+  long long hbm_budget, hbm_in_use, hbm_high_water;
+  long long iterations;
+  long long latency_count;  /* completions behind p50 / p99 */
+  double p50_ms, p99_ms, mean_ms, max_ms;
+  double now;               /* server clock, seconds */
+} fftpde_stats;
+
+typedef int (*fftpde_host_exec)(void *user, unsigned long long id, const fftpde_request *req, void *out,
+                                int phase, long long n0, int nt);
+
+int fftpde_server_create(fftpde_ctx *ctx, long long hbm_budget, int max_slots, int nstreams,
+                         fftpde_server **server);
+int fftpde_server_create_host(long long hbm_budget, int max_slots, fftpde_host_exec exec, void *user,
+                              fftpde_server **server);
+int fftpde_server_submit(fftpde_server *server, const fftpde_request *req, unsigned long long *id);
+int fftpde_server_poll(fftpde_server *server, unsigned long long id, fftpde_result *res);
+int fftpde_server_wait(fftpde_server *server, unsigned long long id, double timeout, fftpde_result *res);
+int fftpde_server_cancel(fftpde_server *server, unsigned long long id);
+int fftpde_server_copy_out(fftpde_server *server, unsigned long long id, void *dst, fftpde_stream stream);
+int fftpde_server_release(fftpde_server *server, unsigned long long id);
+int fftpde_server_stats(fftpde_server *server, int reset, fftpde_stats *stats);
+int fftpde_server_destroy(fftpde_server *server);
+
 #ifdef __cplusplus
 }
 #endif

@@ -70,6 +70,34 @@ class FftpdeJob(ctypes.Structure):
                 ("t", ctypes.c_double), ("inp", ctypes.c_void_p), ("out", ctypes.c_void_p)]
 
 
+class FftpdeRequest(ctypes.Structure):
+    """struct fftpde_request of the C ABI."""
+    _fields_ = [("op", ctypes.c_int), ("dtype", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+                ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("coef", ctypes.c_double),
+                ("dt", ctypes.c_double), ("steps", ctypes.c_longlong), ("inp", ctypes.c_void_p),
+                ("v0", ctypes.c_void_p), ("out", ctypes.c_void_p), ("diag", ctypes.c_void_p),
+                ("deadline", ctypes.c_double), ("flags", ctypes.c_int), ("stream", ctypes.c_void_p)]
+
+
+class FftpdeResult(ctypes.Structure):
+    """struct fftpde_result of the C ABI."""
+    _fields_ = [("status", ctypes.c_int), ("state", ctypes.c_int), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double), ("out", ctypes.c_void_p),
+                ("footprint", ctypes.c_longlong)]
+
+
+class FftpdeStats(ctypes.Structure):
+    """struct fftpde_stats of the C ABI."""
+    _fields_ = [(n, ctypes.c_longlong) for n in (
+        "submitted", "rejected", "admitted", "completed", "failed", "canceled", "timed_out", "queued", "running",
+        "hbm_budget", "hbm_in_use", "hbm_high_water", "iterations", "latency_count")] + \
+        [(n, ctypes.c_double) for n in ("p50_ms", "p99_ms", "mean_ms", "max_ms", "now")]
+
+
+HOST_EXEC = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_ulonglong, ctypes.POINTER(FftpdeRequest),
+                             ctypes.c_void_p, ctypes.c_int, ctypes.c_longlong, ctypes.c_int)
+
+
 def _declare(L):
     vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
     L.fftpde_create.argtypes = [ctypes.POINTER(vp), i]
@@ -103,7 +131,21 @@ def _declare(L):
     L.fftpde_batch_info.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(i),
                                     ctypes.POINTER(d)]
     L.fftpde_batch_destroy.argtypes = [vp]
-    for f in ("fftpde_batch_create", "fftpde_batch_run", "fftpde_batch_status", "fftpde_batch_info",
+    ull, ll = ctypes.c_ulonglong, ctypes.c_longlong
+    L.fftpde_server_create.argtypes = [vp, ll, i, i, ctypes.POINTER(vp)]
+    L.fftpde_server_create_host.argtypes = [ll, i, HOST_EXEC, vp, ctypes.POINTER(vp)]
+    L.fftpde_server_submit.argtypes = [vp, ctypes.POINTER(FftpdeRequest), ctypes.POINTER(ull)]
+    L.fftpde_server_poll.argtypes = [vp, ull, ctypes.POINTER(FftpdeResult)]
+    L.fftpde_server_wait.argtypes = [vp, ull, d, ctypes.POINTER(FftpdeResult)]
+    L.fftpde_server_cancel.argtypes = [vp, ull]
+    L.fftpde_server_copy_out.argtypes = [vp, ull, vp, vp]
+    L.fftpde_server_release.argtypes = [vp, ull]
+    L.fftpde_server_stats.argtypes = [vp, i, ctypes.POINTER(FftpdeStats)]
+    L.fftpde_server_destroy.argtypes = [vp]
+    for f in ("fftpde_server_create", "fftpde_server_create_host", "fftpde_server_submit", "fftpde_server_poll",
+              "fftpde_server_wait", "fftpde_server_cancel", "fftpde_server_copy_out", "fftpde_server_release",
+              "fftpde_server_stats", "fftpde_server_destroy",
+              "fftpde_batch_create", "fftpde_batch_run", "fftpde_batch_status", "fftpde_batch_info",
               "fftpde_batch_destroy", "fftpde_plan_small", "fftpde_evolve_create", "fftpde_evolve_step", "fftpde_evolve_destroy", "fftpde_autotune", "fftpde_plan_save", "fftpde_plan_load", "fftpde_plan_variants",
               "fftpde_plan_select", "fftpde_profile", "fftpde_profile_read", "fftpde_create", "fftpde_destroy", "fft2d_forward", "fft2d_inverse", "solve_poisson",
               "solve_diffusion", "solve_wave"):
@@ -439,6 +481,127 @@ class Batch:
             _torch().cuda.current_stream(self.device).synchronize()
             _lib.fftpde_batch_destroy(self._h)
         self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+AUTORELEASE = 1
+STATE_QUEUED, STATE_RUNNING, STATE_ENDED = 0, 1, 2
+
+
+class Server:
+    """Request server (fftpde_server_*): continuous batching of Poisson solves
+    and diffusion / wave evolutions on one GPU, admission by an HBM budget.
+
+    Server(budget_bytes, max_slots, streams, device) runs on the GPU;
+    Server.host(budget_bytes, max_slots, exec_fn) runs the same scheduler with
+    a host backend that calls exec_fn(id, request, out_address, phase, n0, nt)
+    for every piece of work (phase 0 start, 1 steps n0..n0+nt-1, 2 final
+    field) -- for testing the scheduler without a GPU."""
+
+    def __init__(self, budget: int, max_slots: int = 16, streams: int = 4, device: int = 0, _host=None):
+        self._h = None
+        self._keep = {}
+        h = ctypes.c_void_p()
+        if _host is None:
+            self.device = device
+            _check(lib().fftpde_server_create(context(device), int(budget), int(max_slots), int(streams),
+                                              ctypes.byref(h)), "fftpde_server_create")
+        else:
+            self.device = None
+            self._cb = _host
+            _check(lib().fftpde_server_create_host(int(budget), int(max_slots), _host, None, ctypes.byref(h)),
+                   "fftpde_server_create_host")
+        self._h = h.value
+
+    @classmethod
+    def host(cls, budget: int, max_slots: int, exec_fn):
+        def tramp(user, rid, req, out, phase, n0, nt):
+            try:
+                rc = exec_fn(int(rid), req.contents, out, int(phase), int(n0), int(nt))
+                return int(rc or 0)
+            except Exception:  # a failing callback fails its request
+                import traceback
+                traceback.print_exc()
+                return -3
+        return cls(budget, max_slots, _host=HOST_EXEC(tramp))
+
+    def submit_raw(self, req: FftpdeRequest, keep=()) -> int:
+        rid = ctypes.c_ulonglong()
+        _check(lib().fftpde_server_submit(self._h, ctypes.byref(req), ctypes.byref(rid)), "fftpde_server_submit")
+        if keep:
+            self._keep[rid.value] = keep
+        return rid.value
+
+    def submit(self, op: int, inp, *, out=None, v0=None, diag=None, steps: int = 1, dt: float = 0.0,
+               coef: float = 0.0, lx: float = 1.0, ly: float = 1.0, deadline: float = 0.0,
+               autorelease: bool = False) -> int:
+        """Submit a request on device tensors ([ny, nx] complex inp, optional
+        out / v0 of the same shape, optional float64 diag of 3*steps)."""
+        nx, ny, b, code = _field(inp, "inp")
+        if b != 1 or inp.dim() != 2:
+            raise ValueError("a request is one [ny, nx] field")
+        for t, name in ((out, "out"), (v0, "v0")):
+            if t is not None and (tuple(t.shape) != tuple(inp.shape) or t.dtype != inp.dtype or not t.is_contiguous()):
+                raise ValueError(f"{name} must match inp")
+        if diag is not None and (diag.dtype != _torch().float64 or diag.numel() < 3 * steps or not diag.is_contiguous()):
+            raise ValueError("diag must be a contiguous float64 tensor of 3*steps values")
+        req = FftpdeRequest(int(op), code, nx, ny, float(lx), float(ly), float(coef), float(dt), int(steps),
+                            inp.data_ptr(), _ptr(v0), _ptr(out), _ptr(diag), float(deadline),
+                            AUTORELEASE if autorelease else 0, _stream(inp))
+        return self.submit_raw(req, keep=(inp, out, v0, diag))
+
+    def _result(self, rc, res, rid):
+        if rc == ENOTFOUND:
+            raise FftpdeError(rc, "fftpde_server_poll", f"unknown request {rid}")
+        return dict(status=res.status, state=res.state, t_submit=res.t_submit, t_admit=res.t_admit,
+                    t_done=res.t_done, out=res.out, footprint=res.footprint)
+
+    def poll(self, rid: int) -> dict:
+        res = FftpdeResult()
+        return self._result(lib().fftpde_server_poll(self._h, rid, ctypes.byref(res)), res, rid)
+
+    def wait(self, rid: int, timeout: float = -1.0) -> dict:
+        res = FftpdeResult()
+        return self._result(lib().fftpde_server_wait(self._h, rid, float(timeout), ctypes.byref(res)), res, rid)
+
+    def cancel(self, rid: int):
+        _check(lib().fftpde_server_cancel(self._h, rid), "fftpde_server_cancel")
+
+    def copy_out(self, rid: int, dst):
+        """Copy an ended request's output into dst (a device tensor, or for the
+        host backend a numpy array)."""
+        if hasattr(dst, "data_ptr"):
+            s = _torch().cuda.current_stream(dst.device).cuda_stream
+            _check(lib().fftpde_server_copy_out(self._h, rid, dst.data_ptr(), s), "fftpde_server_copy_out")
+        else:
+            _check(lib().fftpde_server_copy_out(self._h, rid, dst.ctypes.data, None), "fftpde_server_copy_out")
+        return dst
+
+    def release(self, rid: int):
+        _check(lib().fftpde_server_release(self._h, rid), "fftpde_server_release")
+        self._keep.pop(rid, None)
+
+    def stats(self, reset: bool = False) -> dict:
+        st = FftpdeStats()
+        _check(lib().fftpde_server_stats(self._h, 1 if reset else 0, ctypes.byref(st)), "fftpde_server_stats")
+        return {n: getattr(st, n) for n, _ in FftpdeStats._fields_}
+
+    def close(self):
+        if self._h is not None and _lib is not None:
+            _lib.fftpde_server_destroy(self._h)
+        self._h = None
+        self._keep.clear()
 
     def __del__(self):
         try:

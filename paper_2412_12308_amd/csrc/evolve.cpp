@@ -60,37 +60,14 @@ struct DevGuard {
   }
 };
 
-template <typename T>
-int step_impl(fftpde_evolve* e, double t, void* u, void* v, double* diag, hipStream_t s) {
-  Context* c = e->ctx;
-  const int lx = ilog2e(e->nx), ly = ilog2e(e->ny);
-  const long long nrows = (long long)e->ny * e->batch;
+int step_impl(fftpde_evolve* e, long long n, double dt, void* u, void* v, double* diag, hipStream_t s) {
   int rc = FFTPDE_OK;
-  if (u) {
-    if (e->kind == FFTPDE_DIFFUSION) {
-      const SymParams sym = make_sym(kSymDiffusion, e->nx, e->ny, e->lx, e->ly, e->coef, t);
-      rc = col_pass<T>(c, e->F, nullptr, u, nullptr, lx, ly, e->batch, kColMulInv, sym, 1, s);
-    } else {
-      const SymParams sym = make_sym(kSymWave, e->nx, e->ny, e->lx, e->ly, e->coef, t);
-      if (!e->G && !v)
-        rc = col_pass<T>(c, e->F, nullptr, u, nullptr, lx, ly, e->batch, kColMulInv, sym, 1, s);
-      else
-        rc = col_pass<T>(c, e->F, e->G, u, v, lx, ly, e->batch, kColMulInv, sym, 2, s);
-    }
-    if (rc == FFTPDE_OK) rc = row_pass<T>(c, u, u, lx, nrows, true, 1.0, s);
-    if (rc == FFTPDE_OK && v) rc = row_pass<T>(c, v, v, lx, nrows, true, 1.0, s);
-  }
-  if (rc == FFTPDE_OK && diag) {
-    DiagArgs<T> a{static_cast<const cx<T>*>(e->F), static_cast<const cx<T>*>(e->G),
-                  e->kind == FFTPDE_DIFFUSION ? 0 : 1, lx, ly,
-                  2.0 * 3.14159265358979323846 / e->lx, 2.0 * 3.14159265358979323846 / e->ly, e->coef, t,
-                  (e->lx / e->nx) * (e->ly / e->ny)};
-    hipError_t he = launch_diag<T>(a, e->batch, e->scratch, diag, s);
-    if (he != hipSuccess) {
-      set_last_error("diagnostics", he);
-      rc = FFTPDE_EDEVICE;
-    }
-  }
+  if (u)
+    rc = run_materialize(e->ctx, e->dtype, e->kind, e->F, e->G, u, v, e->nx, e->ny, e->batch, e->lx, e->ly, e->coef,
+                         (double)n * dt, s);
+  if (rc == FFTPDE_OK && diag)
+    rc = run_diag(e->ctx, e->dtype, e->kind, e->F, e->G, e->nx, e->ny, e->batch, e->lx, e->ly, e->coef, n, dt, 1,
+                  e->scratch, diag, s);
   return rc;
 }
 
@@ -156,7 +133,7 @@ int fftpde_evolve_step(fftpde_evolve* e, long long n, double dt, void* u, void* 
     return FFTPDE_EINVAL;
   DevGuard g(e->ctx->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  return e->dtype == FFTPDE_C64 ? step_impl<float>(e, t, u, v, diag, s) : step_impl<double>(e, t, u, v, diag, s);
+  return step_impl(e, n, dt, u, v, diag, s);
 }
 
 int fftpde_evolve_destroy(fftpde_evolve* e) {

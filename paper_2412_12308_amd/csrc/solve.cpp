@@ -3,6 +3,8 @@
 // transforms, with the symbol between forward and inverse), row pass.
 #include "solve.hpp"
 
+#include "diag.hpp"
+
 #include <cmath>
 
 #include "../../include/fftpde.h"
@@ -168,6 +170,53 @@ int run_solve(Context* c, int dtype, int op, const void* in, const void* in2, vo
   }
   return dtype == FFTPDE_C64 ? solve_wave_two<float>(c, in, in2, out, out2, nx, ny, batch, sym, s)
                              : solve_wave_two<double>(c, in, in2, out, out2, nx, ny, batch, sym, s);
+}
+
+template <typename T>
+static int materialize(Context* c, int kind, const void* F, const void* G, void* u, void* v, int nx, int ny, int batch,
+                       double lx, double ly, double coef, double t, hipStream_t s) {
+  const int lgx = ilog2(nx), lgy = ilog2(ny);
+  const long long nrows = (long long)ny * batch;
+  int rc;
+  if (kind == FFTPDE_DIFFUSION) {
+    const SymParams sym = make_sym(kSymDiffusion, nx, ny, lx, ly, coef, t);
+    rc = col_pass<T>(c, F, nullptr, u, nullptr, lgx, lgy, batch, kColMulInv, sym, 1, s);
+  } else {
+    const SymParams sym = make_sym(kSymWave, nx, ny, lx, ly, coef, t);
+    if (!G && !v) rc = col_pass<T>(c, F, nullptr, u, nullptr, lgx, lgy, batch, kColMulInv, sym, 1, s);
+    else rc = col_pass<T>(c, F, G, u, v, lgx, lgy, batch, kColMulInv, sym, 2, s);
+  }
+  if (rc == FFTPDE_OK) rc = row_pass<T>(c, u, u, lgx, nrows, true, 1.0, s);
+  if (rc == FFTPDE_OK && v) rc = row_pass<T>(c, v, v, lgx, nrows, true, 1.0, s);
+  return rc;
+}
+
+int run_materialize(Context* c, int dtype, int kind, const void* F, const void* G, void* u, void* v, int nx, int ny,
+                    int batch, double lx, double ly, double coef, double t, hipStream_t s) {
+  return dtype == FFTPDE_C64 ? materialize<float>(c, kind, F, G, u, v, nx, ny, batch, lx, ly, coef, t, s)
+                             : materialize<double>(c, kind, F, G, u, v, nx, ny, batch, lx, ly, coef, t, s);
+}
+
+template <typename T>
+static hipError_t diag_t(int kind, const void* F, const void* G, int nx, int ny, int batch, double lx, double ly,
+                         double coef, long long n0, double dt, int nt, double* scratch, double* out, hipStream_t s) {
+  DiagArgs<T> a{static_cast<const cx<T>*>(F), static_cast<const cx<T>*>(G), kind == FFTPDE_DIFFUSION ? 0 : 1,
+                ilog2(nx), ilog2(ny), 2.0 * kPi / lx, 2.0 * kPi / ly, coef, n0, dt, nt, (lx / nx) * (ly / ny)};
+  return launch_diag<T>(a, batch, scratch, out, s);
+}
+
+int run_diag(Context* c, int dtype, int kind, const void* F, const void* G, int nx, int ny, int batch, double lx,
+             double ly, double coef, long long n0, double dt, int nt, double* scratch, double* out, hipStream_t s) {
+  const double bytes = (double)(dtype == FFTPDE_C64 ? 8 : 16) * nx * ny * batch * (G ? 2 : 1);
+  hipError_t e = timed_launch(c, dtype == FFTPDE_C64 ? "diag_float" : "diag_double", bytes, s, [&] {
+    return dtype == FFTPDE_C64 ? diag_t<float>(kind, F, G, nx, ny, batch, lx, ly, coef, n0, dt, nt, scratch, out, s)
+                               : diag_t<double>(kind, F, G, nx, ny, batch, lx, ly, coef, n0, dt, nt, scratch, out, s);
+  });
+  if (e != hipSuccess) {
+    set_last_error("diagnostics", e);
+    return FFTPDE_EDEVICE;
+  }
+  return FFTPDE_OK;
 }
 
 template int row_pass<float>(Context*, const void*, void*, int, long long, bool, double, hipStream_t);

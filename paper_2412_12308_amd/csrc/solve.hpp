@@ -44,4 +44,15 @@ int run_transform(Context* c, int dtype, bool inverse, const void* in, void* out
 int run_solve(Context* c, int dtype, int op, const void* in, const void* in2, void* out, void* out2, int nx, int ny,
               int batch, double lx, double ly, double coef, double t, hipStream_t s);
 
+// u(t) (and u_t(t)) of an evolving field from its resident spectra F (and G):
+// the inverse column pass with the propagator at time t applied on load, then
+// the inverse row pass (kind = FFTPDE_DIFFUSION or FFTPDE_WAVE).
+int run_materialize(Context* c, int dtype, int kind, const void* F, const void* G, void* u, void* v, int nx, int ny,
+                    int batch, double lx, double ly, double coef, double t, hipStream_t s);
+
+// Mean and energy at t_j = (n0 + j) dt, j < nt <= 16, from the spectra (one
+// read); out[3 (j batch + f) + {0, 1, 2}].  scratch: diag_scratch_doubles.
+int run_diag(Context* c, int dtype, int kind, const void* F, const void* G, int nx, int ny, int batch, double lx,
+             double ly, double coef, long long n0, double dt, int nt, double* scratch, double* out, hipStream_t s);
+
 }  // namespace fftpde

@@ -198,3 +198,35 @@ def test_job_struct_layout_matches_the_header():
     J = fp.FftpdeJob
     assert J.lx.offset == 16 and J.t.offset == 40 and J.inp.offset == 48 and J.out.offset == 56
     assert ctypes.sizeof(J) == 64
+
+
+def test_server_rejects_bad_arguments():
+    fp, L = _lib()
+    h = ctypes.c_void_p(5)
+    assert L.fftpde_server_create(None, 1 << 20, 4, 2, ctypes.byref(h)) == fp.EINVAL and h.value is None
+    assert L.fftpde_server_create(DUMMY, 1 << 20, 0, 2, ctypes.byref(h)) == fp.EINVAL
+    assert L.fftpde_server_create(DUMMY, 1 << 20, 4, 9, ctypes.byref(h)) == fp.EINVAL
+    assert L.fftpde_server_create(DUMMY, 16, 4, 2, ctypes.byref(h)) == fp.EINVAL
+    cb = fp.HOST_EXEC(lambda *a: 0)
+    assert L.fftpde_server_create_host(1 << 40, 4, cb, None, ctypes.byref(h)) == fp.EINVAL  # host pool <= 1 GiB
+    assert L.fftpde_server_create_host(1 << 20, 0, cb, None, ctypes.byref(h)) == fp.EINVAL
+    r = fp.FftpdeResult()
+    st = fp.FftpdeStats()
+    rid = ctypes.c_ulonglong()
+    req = fp.FftpdeRequest()
+    assert L.fftpde_server_submit(None, ctypes.byref(req), ctypes.byref(rid)) == fp.EINVAL
+    assert L.fftpde_server_poll(None, 1, ctypes.byref(r)) == fp.EINVAL
+    assert L.fftpde_server_wait(None, 1, 0.0, ctypes.byref(r)) == fp.EINVAL
+    assert L.fftpde_server_cancel(None, 1) == fp.EINVAL
+    assert L.fftpde_server_release(None, 1) == fp.EINVAL
+    assert L.fftpde_server_copy_out(None, 1, P, None) == fp.EINVAL
+    assert L.fftpde_server_stats(None, 0, ctypes.byref(st)) == fp.EINVAL
+    assert L.fftpde_server_destroy(None) == fp.OK
+
+
+def test_request_structs_match_the_header():
+    import paper_2412_12308_amd as fp
+    R = fp.FftpdeRequest
+    assert (R.lx.offset, R.steps.offset, R.inp.offset, R.deadline.offset, R.flags.offset) == (16, 48, 56, 88, 96)
+    assert R.stream.offset == 104 and ctypes.sizeof(R) == 112 and ctypes.sizeof(fp.FftpdeResult) == 48
+    assert ctypes.sizeof(fp.FftpdeStats) == 14 * 8 + 5 * 8
