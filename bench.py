@@ -11,6 +11,14 @@ keeps the working set (2 x 512 MiB at B = 16) well above the 256 MiB
 Infinity Cache, so the passes run from HBM.  The same workload in FP64
 (B = 8) is reported beside it.
 
+Beside it: the batched uneven launch (1024 Poisson solves, sides drawn from
+32..1024, one persistent kernel replayed from a HIP graph, FP32 and FP64,
+and the FP64 solves one at a time), and the request server under an open
+loop of Poisson arrivals at 2000 requests/s (50 % Poisson, 30 % diffusion
+with 10..200 steps, 20 % wave with 10..500 steps, sides log-uniform in
+2^6..2^12, 64 GiB budget, per-step diagnostics from resident spectra):
+p50 / p99 latency over 10 s after 1 s of warm-up.
+
 Prints one JSON line.  Inputs are resident in HBM before timing starts.
 """
 from __future__ import annotations
@@ -120,6 +128,154 @@ def cpu_baseline(host_field, seconds: float = 10.0):
                       f"inverse 2D FFT), {el:.1f} s on {threads} threads"}
 
 
+def batch_leg(fp, torch, reps: int, warmup: int, check: bool):
+    """1024 uneven Poisson solves per launch (graph replay), FP32 and FP64;
+    the FP64 solves also one at a time through the single-field path."""
+    import numpy as np
+
+    import oracle
+    import workloads as W
+    shapes = W.batch_shapes()
+    srcs = W.batch_sources(shapes)
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    out = {"workload": "poisson_uneven_batch_1024", "jobs": len(srcs),
+           "sides": "nx, ny independently uniform in {32..1024}"}
+    for name, tdt in (("fp32", torch.complex64), ("fp64", torch.complex128)):
+        ins = [torch.from_numpy(ms.field).to(tdt).cuda() for ms in srcs]
+        b = fp.Batch([dict(op=0, inp=x, lx=ms.lx, ly=ms.ly) for x, ms in zip(ins, srcs)])
+        for _ in range(warmup):
+            b.run()
+        torch.cuda.synchronize()
+        e0, e1 = ev(), ev()
+        e0.record()
+        for _ in range(reps):
+            b.run()
+        e1.record()
+        torch.cuda.synchronize()
+        b.status()
+        ms = e0.elapsed_time(e1) / reps
+        leg = {"ms_per_launch": round(ms, 4), "solves_per_s": round(len(srcs) / (ms * 1e-3), 1),
+               "alg_gbs": round(b.bytes / (ms * 1e-3) / 1e9, 1),
+               "alg_frac": round(b.bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+               "tiles": b.items, "workgroups": b.grid, "alg_bytes": b.bytes}
+        if check:
+            errs = []
+            for i in (int(np.argmax([m.nx * m.ny for m in srcs])), 0, 511):
+                x = srcs[i].field
+                x = x.astype(np.complex64).astype(np.complex128) if name == "fp32" else x
+                ref = oracle.solve_poisson(x, srcs[i].lx, srcs[i].ly, threads=oracle.default_threads())
+                errs.append(oracle.rel_l2(b.outputs[i].cpu().numpy().astype(np.complex128), ref))
+            leg["err_vs_oracle_max"] = max(errs)
+        if name == "fp64":
+            solo = [torch.empty_like(x) for x in ins]
+            for _ in range(2):
+                for x, o, m in zip(ins, solo, srcs):
+                    fp.solve_poisson(x, m.lx, m.ly, out=o)
+            torch.cuda.synchronize()
+            e0, e1 = ev(), ev()
+            e0.record()
+            for x, o, m in zip(ins, solo, srcs):
+                fp.solve_poisson(x, m.lx, m.ly, out=o)
+            e1.record()
+            torch.cuda.synchronize()
+            ms1 = e0.elapsed_time(e1)
+            out["fp64_one_at_a_time"] = {"ms": round(ms1, 3), "solves_per_s": round(len(srcs) / (ms1 * 1e-3), 1)}
+        out[name] = leg
+        b.close()
+        del ins
+    return out
+
+
+def serving_leg(fp, torch, duration: float = 11.0, warm: float = 1.0, budget_gib: int = 64,
+                slots: int = 64, streams: int = 4):
+    """Open-loop serving: requests are submitted at their arrival times from
+    a client thread; the main thread waits for each, records its latency and
+    releases it.  Latency = completion (device timestamp) - submission."""
+    import threading
+
+    import numpy as np
+
+    import workloads as W
+    trace = W.serving_trace(seed=5, rate=2000.0, duration=duration)
+    dev = torch.device("cuda:0")
+    inputs = {}
+    for t in trace:
+        key = (t.kind, t.nx, t.ny)
+        if key not in inputs:
+            f, lx, ly = W.serving_input(t.kind, t.nx, t.ny)
+            inputs[key] = (torch.from_numpy(f).to(torch.complex64).to(dev), lx, ly)
+    max_steps = max(t.steps for t in trace)
+    ring = 4096  # diagnostics slots: far more than requests in flight
+    diag = torch.zeros((ring, 3 * max_steps), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    srv = fp.Server(budget_gib << 30, slots, streams)
+    reqs = []
+    for i, t in enumerate(trace):
+        x, lx, ly = inputs[(t.kind, t.nx, t.ny)]
+        d = diag[i % ring].data_ptr() if t.kind != 0 else None
+        reqs.append(fp.FftpdeRequest(t.kind, 0, t.nx, t.ny, lx, ly, t.coef, t.dt, t.steps, x.data_ptr(), None,
+                                     None, d, 0.0, 0, None))
+    ids = [None] * len(trace)
+    lag = [0.0] * len(trace)
+    started = threading.Event()
+    t0_box = []
+
+    def client():
+        t0 = time.perf_counter()
+        t0_box.append(t0)
+        started.set()
+        for i, (t, r) in enumerate(zip(trace, reqs)):
+            while True:
+                now = time.perf_counter() - t0
+                if now >= t.arrival:
+                    break
+                if t.arrival - now > 2e-4:
+                    time.sleep(min(t.arrival - now - 1e-4, 1e-3))
+            lag[i] = time.perf_counter() - t0 - t.arrival
+            ids[i] = srv.submit_raw(r)
+
+    th = threading.Thread(target=client, daemon=True)
+    th.start()
+    started.wait()
+    lat, kinds, arr = [], [], []
+    failed = 0
+    for i, t in enumerate(trace):
+        while ids[i] is None:
+            time.sleep(1e-4)
+        res = srv.wait(ids[i], 120.0)
+        if res["status"] != 0:
+            failed += 1
+        else:
+            lat.append((res["t_done"] - res["t_submit"]) * 1e3 + lag[i] * 1e3)
+            kinds.append(t.kind)
+            arr.append(t.arrival)
+        srv.release(ids[i])
+    th.join()
+    st = srv.stats()
+    srv.close()
+    lat, kinds, arr = np.array(lat), np.array(kinds), np.array(arr)
+    m = arr >= warm
+    window = duration - warm
+
+    def q(v, p):
+        return float(np.percentile(v, p, method="inverted_cdf")) if len(v) else None
+    per_kind = {name: {"p50_ms": q(lat[m & (kinds == k)], 50), "p99_ms": q(lat[m & (kinds == k)], 99),
+                       "count": int((m & (kinds == k)).sum())}
+                for k, name in ((0, "poisson"), (1, "diffusion"), (2, "wave"))}
+    return {"workload": "serving_mix_poisson_arrivals_2000rps", "requests": len(trace),
+            "measured_requests": int(m.sum()), "failed": failed,
+            "offered_rps": round(sum(1 for t in trace if t.arrival >= warm) / window, 1),
+            "achieved_rps": round(int(m.sum()) / window, 1),
+            "p50_ms": q(lat[m], 50), "p99_ms": q(lat[m], 99), "mean_ms": float(lat[m].mean()),
+            "max_ms": float(lat[m].max()), "per_kind": per_kind,
+            "submit_lag_p99_ms": round(float(np.percentile(np.array(lag), 99)) * 1e3, 3),
+            "hbm_budget_gib": budget_gib, "hbm_high_water_gib": round(st["hbm_high_water"] / 2 ** 30, 3),
+            "max_slots": slots, "streams": streams, "iterations": st["iterations"],
+            "latency": "device completion - submission + client submit lag",
+            "steps": "diagnostics (mean, energy) at every step from the resident spectra, "
+                     "u materialised at the final step"}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,6 +289,9 @@ def main(argv=None):
                     help="also run a plain elementwise copy of the FP32 batch (512 MiB at B = 16), "
                          "the known-size reference for hardware byte counters")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-seconds", type=float, default=11.0)
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported "
@@ -166,6 +325,14 @@ def main(argv=None):
         f64 = fields[: max(1, a.batch // 2)]
         r64 = run_leg(fp, torch, f64, "c128", a.steps, a.warmup)
         err64 = None if a.no_check else oracle_check(r64["last_out"][0], f64[0], "c128", r64["last_t"])
+    batch = None
+    if not a.no_batch:
+        print("# uneven batch leg", file=sys.stderr, flush=True)
+        batch = batch_leg(fp, torch, 20, 3, not a.no_check)
+    serve = None
+    if not a.no_serve:
+        print("# serving leg", file=sys.stderr, flush=True)
+        serve = serving_leg(fp, torch, duration=a.serve_seconds)
     cpu = None
     if not a.no_cpu:
         print("# cpu baseline", file=sys.stderr, flush=True)
@@ -210,6 +377,10 @@ def main(argv=None):
                         "kernels": [{"kernel": k["kernel"], "launches": k["launches"],
                                      "avg_us": round(k["avg_us"], 2), "gbs": round(k["gbs"], 1)}
                                     for k in r64["kernels"]]}
+    if batch:
+        line["batch"] = batch
+    if serve:
+        line["serving"] = serve
     print(json.dumps(line), flush=True)
     return 0
 

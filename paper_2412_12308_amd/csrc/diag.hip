@@ -16,94 +16,160 @@
 namespace fftpde {
 namespace {
 
-constexpr int kDiagThreads = 256;
+constexpr int kDiagThreads = 1024;
 
 __device__ __forceinline__ int sidx(int a, int logn) { return a < (1 << (logn - 1)) ? a : a - (1 << logn); }
 
-// per-field partial sums: block (bx, field) writes one double per time
+// sum over the 64 lanes of a wave, xor butterfly (the same order in every lane)
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Per-block partial sums for nt <= NT times t_j = (n0 + j) dt.  Each
+// element's propagator is evaluated directly at t_0 and advanced to t_j by an
+// FP64 rotation through w dt (wave) or a product with exp(-2 kappa |k|^2 dt)
+// (diffusion): two transcendental evaluations per element per launch, one
+// rounding per further time.  partial[(field * nt + j) * nblocks + block].
+// A second kernel sums the partials; the kernel boundary makes them visible
+// (no fences, no atomics, a fixed order).
 template <typename T, int NT>
 __global__ void __launch_bounds__(kDiagThreads) diag_partial(DiagArgs<T> a, double* partial) {
   const int field = blockIdx.y;
+  const int nb = gridDim.x;
   const long long P = 1ll << (a.lognx + a.logny);
   const cx<T>* F = a.F + field * P;
   const cx<T>* G = a.G ? a.G + field * P : nullptr;
+  const int nt = a.nt;
+  const double t0 = double(a.n0) * a.dt;
   double acc[NT];
 #pragma unroll
   for (int j = 0; j < NT; j++) acc[j] = 0.0;
-  for (long long i = blockIdx.x * (long long)kDiagThreads + threadIdx.x; i < P; i += (long long)gridDim.x * kDiagThreads) {
+  for (long long i = blockIdx.x * (long long)kDiagThreads + threadIdx.x; i < P; i += (long long)nb * kDiagThreads) {
     const int ai = sidx(int(i & ((1ll << a.lognx) - 1)), a.lognx);
     const int bi = sidx(int(i >> a.lognx), a.logny);
     const double kx = a.kxs * ai, ky = a.kys * bi;
     const double k2 = kx * kx + ky * ky;
     const double fr = double(F[i].re), fi = double(F[i].im);
-    const double gr = G ? double(G[i].re) : 0.0, gi = G ? double(G[i].im) : 0.0;
-    const double w = a.coef * sqrt(k2);
+    if (a.kind == 0) {
+      const double f2 = fr * fr + fi * fi;
+      double e = exp(-2.0 * a.coef * k2 * t0);
+      const double ed = NT > 1 ? exp(-2.0 * a.coef * k2 * a.dt) : 1.0;
 #pragma unroll
-    for (int j = 0; j < NT; j++) {
-      if (j < a.nt) {
-        const double t = double(a.n0 + j) * a.dt;
-        if (a.kind == 0) {
-          acc[j] += (fr * fr + fi * fi) * exp(-2.0 * a.coef * k2 * t);
-        } else {
-          double s, c;
-          sincos(w * t, &s, &c);
-          double ur, ui, vr, vi;
-          if (w == 0.0) {
-            ur = fr + gr * t;
-            ui = fi + gi * t;
-            vr = gr;
-            vi = gi;
-          } else {
-            ur = fr * c + gr * s / w;
-            ui = fi * c + gi * s / w;
-            vr = -w * fr * s + gr * c;
-            vi = -w * fi * s + gi * c;
+      for (int j = 0; j < NT; j++) {
+        if (j < nt) acc[j] += f2 * e;
+        e *= ed;
+      }
+    } else {
+      const double w = a.coef * sqrt(k2);
+      double s, c, sd = 0.0, cd = 1.0;
+      sincos(w * t0, &s, &c);
+      if (NT > 1) sincos(w * a.dt, &sd, &cd);
+      if (!G) {
+        // v0 = 0: U = F cos, V = -w F sin, so |V|^2 + w^2 |U|^2 = w^2 |F|^2 (cos^2 + sin^2)
+        const double e = w * w * (fr * fr + fi * fi);
+#pragma unroll
+        for (int j = 0; j < NT; j++) {
+          if (j < nt) acc[j] += e * (c * c + s * s);
+          const double c2 = c * cd - s * sd;
+          s = s * cd + c * sd;
+          c = c2;
+        }
+      } else if (w == 0.0) {
+        // U = F + G t, V = G: the energy density is |G|^2 at every time
+        const double gr = double(G[i].re), gi = double(G[i].im);
+#pragma unroll
+        for (int j = 0; j < NT; j++)
+          if (j < nt) acc[j] += gr * gr + gi * gi;
+      } else {
+        const double gr = double(G[i].re), gi = double(G[i].im);
+        const double iw = 1.0 / w;
+#pragma unroll
+        for (int j = 0; j < NT; j++) {
+          if (j < nt) {
+            const double ur = fr * c + gr * s * iw, ui = fi * c + gi * s * iw;
+            const double vr = -w * fr * s + gr * c, vi = -w * fi * s + gi * c;
+            acc[j] += vr * vr + vi * vi + w * w * (ur * ur + ui * ui);
           }
-          acc[j] += vr * vr + vi * vi + w * w * (ur * ur + ui * ui);
+          const double c2 = c * cd - s * sd;
+          s = s * cd + c * sd;
+          c = c2;
         }
       }
     }
   }
-  __shared__ double sh[kDiagThreads];
-  for (int j = 0; j < a.nt && j < NT; j++) {
-    sh[threadIdx.x] = acc[j];
-    __syncthreads();
-    for (int s = kDiagThreads / 2; s > 0; s >>= 1) {
-      if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-      __syncthreads();
+  // Block sums in a fixed order: an xor butterfly within each wave, then the
+  // waves' values in wave order.
+  constexpr int kWaves = kDiagThreads / 64;
+  __shared__ double sh[NT * kWaves];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < NT; j++) {
+    if (j < nt) {
+      const double v = wave_sum(acc[j]);
+      if (lane == 0) sh[j * kWaves + wave] = v;
     }
-    if (threadIdx.x == 0) partial[(field * a.nt + j) * gridDim.x + blockIdx.x] = sh[0];
-    __syncthreads();
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nt) {
+    double v = 0.0;
+    for (int w = 0; w < kWaves; w++) v += sh[threadIdx.x * kWaves + w];
+    partial[(field * nt + threadIdx.x) * nb + blockIdx.x] = v;
   }
 }
 
-// one thread per (field, time): ordered sum of the partials, mean from the
-// k = 0 mode
-template <typename T>
-__global__ void diag_final(DiagArgs<T> a, const double* partial, int nblocks, int batch, double* out) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= batch * a.nt) return;
-  const int field = idx / a.nt, j = idx % a.nt;
-  const double t = double(a.n0 + j) * a.dt;
-  double e = 0.0;
-  for (int b = 0; b < nblocks; b++) e += partial[(field * a.nt + j) * nblocks + b];
+// One block per field: the partials of every time summed in block order
+// (thread k takes blocks k, k + kDiagThreads, ...; then the xor butterfly and
+// the waves in order), the mean from the k = 0 mode.
+template <typename T, int NT>
+__global__ void __launch_bounds__(kDiagThreads) diag_final(DiagArgs<T> a, const double* partial, int nb, int batch,
+                                                           double* out) {
+  constexpr int kWaves = kDiagThreads / 64;
+  __shared__ double sh[NT * kWaves];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int f = blockIdx.x;
+  const int nt = a.nt;
   const long long P = 1ll << (a.lognx + a.logny);
-  const cx<T> F0 = a.F[field * P];
-  double mr = double(F0.re), mi = double(F0.im);
-  if (a.kind == 1 && a.G) {
-    const cx<T> G0 = a.G[field * P];
-    mr += double(G0.re) * t;
-    mi += double(G0.im) * t;
+  // all loads first (independent), then the reductions
+  double e[NT];
+#pragma unroll
+  for (int j = 0; j < NT; j++) e[j] = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kDiagThreads) {
+#pragma unroll
+    for (int j = 0; j < NT; j++)
+      if (j < nt) e[j] += partial[(f * nt + j) * nb + b];
   }
-  const double scale = a.dxdy / double(P);
-  double* o = out + 3 * ((long long)j * batch + field);
-  o[0] = mr / double(P);
-  o[1] = mi / double(P);
-  o[2] = (a.kind == 0 ? 1.0 : 0.5) * scale * e;
+#pragma unroll
+  for (int j = 0; j < NT; j++) {
+    if (j < nt) {
+      const double v = wave_sum(e[j]);
+      if (lane == 0) sh[j * kWaves + wave] = v;
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nt) {
+    const int j = threadIdx.x;
+    double en = 0.0;
+    for (int w = 0; w < kWaves; w++) en += sh[j * kWaves + w];
+    const double t = double(a.n0 + j) * a.dt;
+    const cx<T> F0 = a.F[f * P];
+    double mr = double(F0.re), mi = double(F0.im);
+    if (a.kind == 1 && a.G) {
+      const cx<T> G0 = a.G[f * P];
+      mr += double(G0.re) * t;
+      mi += double(G0.im) * t;
+    }
+    const double scale = a.dxdy / double(P);
+    double* o = out + 3 * ((long long)j * batch + f);
+    o[0] = mr / double(P);
+    o[1] = mi / double(P);
+    o[2] = (a.kind == 0 ? 1.0 : 0.5) * scale * en;
+  }
 }
 
 int diag_blocks(long long P) {
-  long long b = (P + kDiagThreads * 8 - 1) / (kDiagThreads * 8);
+  long long b = (P + kDiagThreads * 4 - 1) / (kDiagThreads * 4);
   return int(b < 1 ? 1 : (b > 256 ? 256 : b));
 }
 
@@ -115,14 +181,16 @@ size_t diag_scratch_doubles(int lognx, int logny, int batch) {
 
 template <typename T>
 hipError_t launch_diag(const DiagArgs<T>& a, int batch, double* scratch, double* out, hipStream_t s) {
-  if (a.nt < 1 || a.nt > kDiagMaxTimes) return hipErrorInvalidValue;
+  if (a.nt < 1 || a.nt > kDiagMaxTimes || batch < 1 || batch > 65535) return hipErrorInvalidValue;
   const int nb = diag_blocks(1ll << (a.lognx + a.logny));
-  if (a.nt == 1) hipLaunchKernelGGL((diag_partial<T, 1>), dim3(nb, batch), dim3(kDiagThreads), 0, s, a, scratch);
-  else hipLaunchKernelGGL((diag_partial<T, kDiagMaxTimes>), dim3(nb, batch), dim3(kDiagThreads), 0, s, a, scratch);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const int n = batch * a.nt;
-  hipLaunchKernelGGL(diag_final<T>, dim3((n + 63) / 64), dim3(64), 0, s, a, scratch, nb, batch, out);
+  if (a.nt == 1) {
+    hipLaunchKernelGGL((diag_partial<T, 1>), dim3(nb, batch), dim3(kDiagThreads), 0, s, a, scratch);
+    hipLaunchKernelGGL((diag_final<T, 1>), dim3(batch), dim3(kDiagThreads), 0, s, a, scratch, nb, batch, out);
+  } else {
+    hipLaunchKernelGGL((diag_partial<T, kDiagMaxTimes>), dim3(nb, batch), dim3(kDiagThreads), 0, s, a, scratch);
+    hipLaunchKernelGGL((diag_final<T, kDiagMaxTimes>), dim3(batch), dim3(kDiagThreads), 0, s, a, scratch, nb, batch,
+                       out);
+  }
   return hipGetLastError();
 }
 

@@ -26,7 +26,8 @@ struct DiagArgs {
 // Times one launch evaluates (one read of the spectra for all of them).
 constexpr int kDiagMaxTimes = 16;
 
-// Doubles of scratch the reduction needs (for up to kDiagMaxTimes times).
+// Doubles of scratch the reduction needs (for up to kDiagMaxTimes times);
+// launches sharing a scratch must be ordered (one stream).
 size_t diag_scratch_doubles(int lognx, int logny, int batch);
 
 // out[3 (j batch + f) + {0, 1, 2}] = mean (re, im) and energy of field f at t_j.

@@ -31,7 +31,7 @@ using namespace fftpde;
 namespace {
 
 enum { kQueued = 0, kRunning = 1, kEnded = 2 };
-constexpr int kChunk = kDiagMaxTimes;  // steps of diagnostics per iteration
+constexpr int kChunk = kDiagMaxTimes;  // steps of diagnostics per iteration (one launch)
 constexpr long long kHostPoolMax = 1ll << 30;
 constexpr int kHostStreams = 2;
 

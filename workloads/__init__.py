@@ -199,6 +199,29 @@ def wave_ic(n: int = 2048, seed: int = 3, *, sigma: float = 0.02,
     return ic
 
 
+def serving_input(kind: int, nx: int, ny: int, seed: int = 5) -> Tuple[np.ndarray, float, float]:
+    """(field, lx, ly) of a serving request: the recipe of the kind's single
+    case at an nx-by-ny grid -- Poisson: a 16-mode mean-zero source on [0,1)^2
+    (no sine term); diffusion: Gaussian (sigma 0.05) plus N(0, 1e-3^2) noise on
+    [-1,1)^2; wave: a Gaussian pulse (sigma 0.02) at a seeded centre plus the
+    standing mode sin(2 pi 3 x) sin(2 pi 5 y) on [0,1)^2."""
+    rng = np.random.default_rng(_child_seed(seed, kind * 10007 + nx * 13 + ny))
+    if kind == POISSON:
+        k = max(1, min(8, nx // 2 - 1, ny // 2 - 1))
+        ms = poisson_source(nx, ny, seed=int(rng.integers(1 << 31)), kmax=k, with_sine=False)
+        return ms.field, 1.0, 1.0
+    if kind == DIFFUSION:
+        x, y = grid(nx, 2.0, -1.0), grid(ny, 2.0, -1.0)
+        g = np.outer(np.exp(-y ** 2 / (2 * 0.05 ** 2)), np.exp(-x ** 2 / (2 * 0.05 ** 2)))
+        return (g + rng.normal(0.0, 1e-3, size=(ny, nx))).astype(np.complex128), 2.0, 2.0
+    cx_, cy_ = (float(v) for v in rng.uniform(0.0, 1.0, size=2))
+    x, y = grid(nx, 1.0), grid(ny, 1.0)
+    dx, dy = _periodic_offset(x, cx_, 1.0), _periodic_offset(y, cy_, 1.0)
+    f = np.outer(np.exp(-dy ** 2 / (2 * 0.02 ** 2)), np.exp(-dx ** 2 / (2 * 0.02 ** 2)))
+    f = f + np.outer(np.sin(TWO_PI * 5 * y), np.sin(TWO_PI * 3 * x))
+    return f.astype(np.complex128), 1.0, 1.0
+
+
 def random_field(shape: Tuple[int, ...], seed: int) -> np.ndarray:
     """Complex128 field with i.i.d. N(0,1) real and imaginary parts."""
     rng = np.random.default_rng(seed)
