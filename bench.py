@@ -24,9 +24,11 @@ Prints one JSON line.  Inputs are resident in HBM before timing starts.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -39,6 +41,44 @@ HBM_PEAK_GBS = 8000.0
 N_SIDE = 2048
 DT = 1e-4
 C_SPEED = 1.0
+
+
+# Counter traffic comes from the committed rocprofv3 summary, valid only for
+# the kernel sources it was measured on.
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "wave2d_2048_hbm_traffic.md")
+KERNEL_SOURCES = ("fft_engine.hpp", "kernels.hpp", "rows_f32.hip", "rows_f64.hip", "cols_f32_nf1.hip",
+                  "cols_f64_nf1.hip", "cols_f32_nf2.hip", "cols_f64_nf2.hip")
+
+
+def kernel_sources_hash() -> str:
+    """sha256 over the row / column kernel sources (name and contents)."""
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(f.encode())
+        with open(os.path.join(ROOT, "paper_2412_12308_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_for(kernel: str):
+    """HBM bytes per launch of `kernel` (a plan variant name) from the counter
+    summary; None if the summary is missing, lacks the kernel, or was taken on
+    other kernel sources."""
+    try:
+        with open(TRAFFIC_PROFILE) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    m = re.search(r"kernel sources sha256: ([0-9a-f]{64})", text)
+    if not m or m.group(1) != kernel_sources_hash():
+        return None
+    for line in text.splitlines():
+        if line.startswith(f"| `{kernel}` |"):
+            try:
+                return float(line.strip().strip("|").split("|")[-1])
+            except ValueError:
+                return None
+    return None
 
 
 def make_inputs(n: int, batch: int, seed: int = 3):
@@ -363,8 +403,8 @@ def main(argv=None):
         "err_tol": tol32,
         "roofline": {"bound": "hbm", "achieved": round(dom["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(dom["achieved_gbs"] / HBM_PEAK_GBS, 4),
-                     "traffic": None, "kernel": dom["kernel"], "avg_us": round(dom["avg_us"], 2),
-                     "bytes_per_launch": dom["bytes_per_launch"]},
+                     "traffic": traffic_for(dom["kernel"]), "kernel": dom["kernel"],
+                     "avg_us": round(dom["avg_us"], 2), "bytes_per_launch": dom["bytes_per_launch"]},
         "kernels": [{"kernel": k["kernel"], "launches": k["launches"], "avg_us": round(k["avg_us"], 2),
                      "gbs": round(k["gbs"], 1)} for k in r32["kernels"]],
         "cpu_baseline": cpu,

@@ -194,3 +194,20 @@ def test_wave_matches_second_order_ode_per_mode():
     w2 = kx[:, None] ** 2 + kx[None, :] ** 2
     acc = (Up - 2 * U0 + Um) / h ** 2
     assert oracle.rel_l2(acc, -w2 * U0) <= 1e-5
+
+
+def test_spectral_diagnostics_match_grid_sums_and_closed_forms():
+    """mean_from_spectrum and l2_from_spectrum against sums over the grid
+    (Parseval), and the L2 norm of a narrow Gaussian exp(-r^2/(2 s^2)) against
+    its closed form: the integral of exp(-r^2/s^2) over the plane is pi s^2."""
+    n, length, s = 256, 2.0, 0.05
+    x = W.grid(n, length, -1.0)
+    g = np.outer(np.exp(-x ** 2 / (2 * s * s)), np.exp(-x ** 2 / (2 * s * s))).astype(np.complex128)
+    f = g + 0.3 + 0.1j
+    F = oracle.fft2d(f)
+    dx = length / n
+    assert abs(oracle.mean_from_spectrum(F) - f.mean()) <= 1e-14
+    direct = float(np.sum(np.abs(f) ** 2)) * dx * dx
+    assert abs(oracle.l2_from_spectrum(F, length, length) / direct - 1) <= 1e-13
+    # the Gaussian alone: its tails at the box edge are exp(-200), far below rounding
+    assert abs(oracle.l2_from_spectrum(oracle.fft2d(g), length, length) / (math.pi * s * s) - 1) <= 1e-12
