@@ -121,6 +121,16 @@ int fftpde_plan_select(fftpde_ctx *ctx, const char *name);
  *   single-field solve is one launch, one workgroup per field holding the
  *   field in LDS (one HBM read and one write). */
 int fftpde_plan_small(fftpde_ctx *ctx, int enable);
+/* fftpde_plan_tiled: the layout of the spectrum between the passes of the
+ *   3-pass solves without an initial velocity.  block_bytes > 0 (default
+ *   1024): the forward row pass writes it into a scratch field of the context
+ *   (one per stream, grown on demand, freed by fftpde_destroy) in column
+ *   blocks of block_bytes per row (at least one column tile wide) x ny rows,
+ *   the column pass reads and writes within contiguous blocks, and the
+ *   inverse row pass writes the row-major result; 0: row-major in the output
+ *   field.  Results are bit-identical for every block size; only the memory
+ *   access pattern changes.  EINVAL unless 0 or a power of two <= 65536. */
+int fftpde_plan_tiled(fftpde_ctx *ctx, int block_bytes);
 
 /* fftpde_autotune: for an (nx, ny, batch, dtype, op) solve (op one of
  *   FFTPDE_POISSON / DIFFUSION / WAVE, zero initial velocity), time every

@@ -123,26 +123,27 @@ const SmallVariant* Context::small_variant(int dtype, int lognx, int logny) cons
   return nullptr;
 }
 
-int Context::workspace(size_t bytes, void** p) {
-  if (bytes <= work_bytes) {
-    *p = work;
+int Context::workspace(size_t bytes, hipStream_t s, void** p) {
+  Work& w = work[static_cast<void*>(s)];
+  if (bytes <= w.bytes) {
+    *p = w.p;
     return FFTPDE_OK;
   }
-  if (work) {
-    // stream-ordered users may still read the old buffer
-    (void)hipDeviceSynchronize();
-    (void)hipFree(work);
-    work = nullptr;
-    work_bytes = 0;
+  if (w.p) {
+    // work already enqueued on this stream may still use the old buffer
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(w.p);
+    w.p = nullptr;
+    w.bytes = 0;
   }
-  hipError_t e = hipMalloc(&work, bytes);
+  hipError_t e = hipMalloc(&w.p, bytes);
   if (e != hipSuccess) {
     set_error("hipMalloc(workspace)", e);
-    work = nullptr;
+    w.p = nullptr;
     return FFTPDE_ENOMEM;
   }
-  work_bytes = bytes;
-  *p = work;
+  w.bytes = bytes;
+  *p = w.p;
   return FFTPDE_OK;
 }
 
@@ -373,6 +374,12 @@ int fftpde_plan_small(fftpde_ctx* ctx, int enable) {
   return FFTPDE_OK;
 }
 
+int fftpde_plan_tiled(fftpde_ctx* ctx, int block_bytes) {
+  if (!ctx || block_bytes < 0 || block_bytes > 65536 || (block_bytes & (block_bytes - 1))) return FFTPDE_EINVAL;
+  reinterpret_cast<Context*>(ctx)->tiled_bytes = block_bytes;
+  return FFTPDE_OK;
+}
+
 int fftpde_plan_select(fftpde_ctx* ctx, const char* name) {
   if (!ctx) return FFTPDE_EINVAL;
   Context* c = reinterpret_cast<Context*>(ctx);
@@ -401,7 +408,8 @@ int fftpde_destroy(fftpde_ctx* ctx) {
   (void)hipDeviceSynchronize();
   if (c->tw64) (void)hipFree(c->tw64);
   if (c->tw32) (void)hipFree(c->tw32);
-  if (c->work) (void)hipFree(c->work);
+  for (auto& w : c->work)
+    if (w.second.p) (void)hipFree(w.second.p);
   for (auto& t : c->timed) {
     (void)hipEventDestroy(t.start);
     (void)hipEventDestroy(t.stop);

@@ -24,8 +24,13 @@ struct Context {
   int device = 0;
   cx<float>* tw32 = nullptr;   // exp(-2 pi i e/4096), FP64-generated, rounded once
   cx<double>* tw64 = nullptr;  // the same in FP64
-  void* work = nullptr;        // scratch field for solves that need one
-  size_t work_bytes = 0;
+  // Scratch fields for solves that need one, one per stream so that calls on
+  // different streams never share it (grown on demand, freed at destroy).
+  struct Work {
+    void* p = nullptr;
+    size_t bytes = 0;
+  };
+  std::unordered_map<void*, Work> work;
   // Kernel choice per plan slot; null = the first compiled variant of that length.
   const RowVariant* row_choice[kPlanSlots] = {};
   const ColVariant* col_choice[kPlanSlots] = {};
@@ -51,9 +56,16 @@ struct Context {
   bool use_small = true;
   const SmallVariant* small_variant(int dtype, int lognx, int logny) const;
 
+  // Solves keep their spectrum between the passes in column blocks of
+  // tiled_bytes per row (at least the column plan's tile) x ny rows; 0:
+  // row-major in the output field.  Set with fftpde_plan_tiled.  1024 bytes
+  // measured best at 2048^2 (FP32 and FP64): wide enough for full-line row
+  // writes, narrow enough that the column tiles of a block stay close.
+  int tiled_bytes = 1024;
+
   const RowVariant* row_variant(int dtype, int logn) const;
   const ColVariant* col_variant(int dtype, int logn, int nf) const;
-  int workspace(size_t bytes, void** p);
+  int workspace(size_t bytes, hipStream_t s, void** p);
 };
 
 void set_last_error(const char* what, hipError_t e);

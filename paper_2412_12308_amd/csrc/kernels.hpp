@@ -56,6 +56,11 @@ struct RowArgs {
   long long nrows;  // ny * batch
   int inverse;      // 0: forward; 1: inverse (conjugate in and out), times scale
   T scale;
+  // Layouts of in and out: a field is stored in blocks of 2^t columns x ny
+  // rows, element (y, x) at block (x >> t), offset y * 2^t + (x & (2^t - 1))
+  // within it; t = log2 of the row length is the plain row-major layout.
+  int logny;
+  int in_t, out_t;
 };
 
 template <typename T>
@@ -69,6 +74,7 @@ struct ColArgs {
   int lognx;
   int mode;           // ColMode
   SymParams sym;
+  int layout_t;       // fields stored in blocks of 2^layout_t >= 2^LOGT columns (see RowArgs); -1 row-major
 };
 
 // signed frequency index a' of slot a on a 2^logn axis
@@ -240,6 +246,13 @@ __global__ void __launch_bounds__(TH) row_kernel(RowArgs<T> a) {
   const long long ntiles = (a.nrows + LINES - 1) / LINES;
   const TileWalk<1> walk(ntiles);
   if (walk.first < 0) return;
+  const int logny = a.logny;
+  const long long ymask = (1ll << logny) - 1;
+  // element offset of (row, n) in a layout of 2^t-column blocks (t = LOGN: row-major)
+  auto offset = [&](long long row, int n, int t) -> long long {
+    const long long f = row >> logny, yy = row & ymask;
+    return (f << (logny + LOGN)) + ((long long)(n >> t) << (logny + t)) + (yy << t) + (n & ((1 << t) - 1));
+  };
   // raw loads; the inverse's conjugation is applied when the tile is consumed
   // so that a prefetch never waits for its own data
   auto load = [&](long long tile, cx<T>(&dst)[E]) {
@@ -248,7 +261,7 @@ __global__ void __launch_bounds__(TH) row_kernel(RowArgs<T> a) {
       // clamped, unconditional loads (padding rows reread the last row and are
       // never stored) keep the loads free of branches
       const long long row = min(row0 + line, a.nrows - 1);
-      dst[i] = a.in[row * N + n];
+      dst[i] = a.in[offset(row, n, a.in_t)];
     });
   };
   cx<T> wall[TWM == kTwRegs ? Eng::kTwRegs : 1];
@@ -273,7 +286,7 @@ __global__ void __launch_bounds__(TH) row_kernel(RowArgs<T> a) {
     const long long row0 = tile * LINES;
     Eng::for_each_output(tid, [&](int i, int line, int n) {
       const long long row = row0 + line;
-      if (row < a.nrows) a.out[row * N + n] = {x[i].re * sr, x[i].im * si};
+      if (row < a.nrows) a.out[offset(row, n, a.out_t)] = {x[i].re * sr, x[i].im * si};
     });
     if (!more) break;
     if constexpr (PF) {
@@ -325,9 +338,14 @@ __global__ void __launch_bounds__(TH) col_kernel(ColArgs<T> a) {
   const T sgn = mode == kColInverse ? T(-1) : T(1);
   const bool has_in1 = a.in1 != nullptr;
 
-  // Element offset of (column C, row 0) of the batch; row n adds n * nx.
+  // Row stride 2^ts: nx for row-major fields, the block width for fields
+  // stored in column blocks (a block holds whole tiles).
+  const int ts = a.layout_t >= 0 ? a.layout_t : lognx;
+  const long long tmask = (1ll << ts) - 1;
+  // Element offset of (column C, row 0) of the batch; row n adds n << ts.
   auto col_base = [&](long long C) -> long long {
-    return ((C >> lognx) << (lognx + LOGN)) + (C & fmask);
+    const long long xa = C & fmask;
+    return ((C >> lognx) << (lognx + LOGN)) + ((xa >> ts) << (LOGN + ts)) + (xa & tmask);
   };
   // Loads are clamped to the last column (padding columns are reread and never
   // stored), so loads carry no branches and prefetches stay in flight.
@@ -337,8 +355,8 @@ __global__ void __launch_bounds__(TH) col_kernel(ColArgs<T> a) {
     if constexpr (kOneCol) cb = col_base(min(col0 + (tid & (TT - 1)), a.ncols - 1));
     auto f = [&](int i, int line, int n) {
       long long p;
-      if constexpr (kOneCol) p = cb + ((long long)n << lognx);
-      else p = col_base(min(col0 + line, a.ncols - 1)) + ((long long)n << lognx);
+      if constexpr (kOneCol) p = cb + ((long long)n << ts);
+      else p = col_base(min(col0 + line, a.ncols - 1)) + ((long long)n << ts);
       dx[i] = a.in0[p];
       if constexpr (NF == 2) dy[i] = has_in1 ? a.in1[p] : cx<T>{T(0), T(0)};
     };
@@ -351,11 +369,11 @@ __global__ void __launch_bounds__(TH) col_kernel(ColArgs<T> a) {
       const long long C = col0 + (tid & (TT - 1));
       if (C >= a.ncols) return;
       cx<T>* o = out + col_base(C);
-      Inv::for_each_output(tid, [&](int i, int, int n) { o[(long long)n << lognx] = value(i); });
+      Inv::for_each_output(tid, [&](int i, int, int n) { o[(long long)n << ts] = value(i); });
     } else {
       Inv::for_each_output(tid, [&](int i, int line, int n) {
         const long long C = col0 + line;
-        if (C < a.ncols) out[col_base(C) + ((long long)n << lognx)] = value(i);
+        if (C < a.ncols) out[col_base(C) + ((long long)n << ts)] = value(i);
       });
     }
   };
@@ -416,13 +434,13 @@ __global__ void __launch_bounds__(TH) col_kernel(ColArgs<T> a) {
         if (C < a.ncols) {
           cx<T>* o = a.out0 + col_base(C);
           Fwd::for_each_output(tid, [&](int i, int, int n) {
-            o[(long long)n << lognx] = {x[i].re * sc, x[i].im * si};
+            o[(long long)n << ts] = {x[i].re * sc, x[i].im * si};
           });
         }
       } else {
         Fwd::for_each_output(tid, [&](int i, int line, int n) {
           const long long C = col0 + line;
-          if (C < a.ncols) a.out0[col_base(C) + ((long long)n << lognx)] = {x[i].re * sc, x[i].im * si};
+          if (C < a.ncols) a.out0[col_base(C) + ((long long)n << ts)] = {x[i].re * sc, x[i].im * si};
         });
       }
     } else {

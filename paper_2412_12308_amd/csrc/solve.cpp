@@ -29,12 +29,12 @@ static const cx<T>* twiddles(const Context* c) {
 }
 
 template <typename T>
-int row_pass(Context* c, const void* in, void* out, int lognx, long long nrows, bool inverse, double scale,
-             hipStream_t s) {
+int row_pass(Context* c, const void* in, void* out, int lognx, int logny, long long nrows, bool inverse,
+             double scale, hipStream_t s, int in_t, int out_t) {
   const RowVariant* v = c->row_variant(sizeof(T) == 4 ? FFTPDE_C64 : FFTPDE_C128, lognx);
   if (!v) return FFTPDE_EINVAL;
   RowArgs<T> a{static_cast<const cx<T>*>(in), static_cast<cx<T>*>(out), twiddles<T>(c), nrows, inverse ? 1 : 0,
-               T(scale)};
+               T(scale), logny, in_t < 0 ? lognx : in_t, out_t < 0 ? lognx : out_t};
   const double bytes = 2.0 * sizeof(cx<T>) * (double)nrows * (double)(1 << lognx);
   const long long maxb = v->pf ? c->max_blocks(v, v->occupancy) : 0;
   hipError_t e = timed_launch(c, v->name, bytes, s, [&] { return v->launch(&a, nrows, maxb, s); });
@@ -47,11 +47,13 @@ int row_pass(Context* c, const void* in, void* out, int lognx, long long nrows, 
 
 template <typename T>
 int col_pass(Context* c, const void* in0, const void* in1, void* out0, void* out1, int lognx, int logny,
-             long long batch, int mode, const SymParams& sym, int nf, hipStream_t s) {
+             long long batch, int mode, const SymParams& sym, int nf, hipStream_t s, int layout_t) {
   const ColVariant* v = c->col_variant(sizeof(T) == 4 ? FFTPDE_C64 : FFTPDE_C128, logny, nf);
   if (!v) return FFTPDE_EINVAL;
+  // a block holds whole tiles and never spans fields
+  if (layout_t >= 0 && (layout_t < v->logt || layout_t > lognx)) return FFTPDE_EINVAL;
   ColArgs<T> a{static_cast<const cx<T>*>(in0), static_cast<const cx<T>*>(in1), static_cast<cx<T>*>(out0),
-               static_cast<cx<T>*>(out1), twiddles<T>(c), batch << lognx, lognx, mode, sym};
+               static_cast<cx<T>*>(out1), twiddles<T>(c), batch << lognx, lognx, mode, sym, layout_t};
   const double field = sizeof(cx<T>) * (double)batch * (double)(1ll << (lognx + logny));
   const double bytes = field * ((in0 ? 1 : 0) + (in1 ? 1 : 0) + (out0 ? 1 : 0) + (out1 ? 1 : 0));
   const long long maxb = v->pf ? c->max_blocks(v, v->occupancy) : 0;
@@ -87,11 +89,11 @@ int transform(Context* c, const void* in, void* out, int nx, int ny, int batch, 
   SymParams sym = make_sym(kSymScale, nx, ny, 1.0, 1.0, 0.0, 0.0);
   int rc;
   if (!inverse) {
-    rc = row_pass<T>(c, in, out, lx, (long long)ny * batch, false, 1.0, s);
+    rc = row_pass<T>(c, in, out, lx, ly, (long long)ny * batch, false, 1.0, s);
     if (rc == FFTPDE_OK) rc = col_pass<T>(c, out, nullptr, out, nullptr, lx, ly, batch, kColForward, sym, 1, s);
   } else {
     rc = col_pass<T>(c, in, nullptr, out, nullptr, lx, ly, batch, kColInverse, sym, 1, s);
-    if (rc == FFTPDE_OK) rc = row_pass<T>(c, out, out, lx, (long long)ny * batch, true, 1.0, s);
+    if (rc == FFTPDE_OK) rc = row_pass<T>(c, out, out, lx, ly, (long long)ny * batch, true, 1.0, s);
   }
   return rc;
 }
@@ -102,9 +104,28 @@ int solve_real_symbol(Context* c, const void* in, void* out, int nx, int ny, int
                       hipStream_t s) {
   const int lx = ilog2(nx), ly = ilog2(ny);
   const long long nrows = (long long)ny * batch;
-  int rc = row_pass<T>(c, in, out, lx, nrows, false, 1.0, s);
+  // Tiled intermediate in a per-stream scratch field: column blocks of
+  // tiled_bytes per row (whole cache lines for the row passes; the column
+  // tiles of a block share its lines), at least one column tile wide.
+  const ColVariant* cv = c->col_variant(sizeof(T) == 4 ? FFTPDE_C64 : FFTPDE_C128, ly, 1);
+  if (c->tiled_bytes > 0 && cv) {
+    int bt = 0;  // log2 of the block width in columns
+    while ((int)sizeof(cx<T>) << (bt + 1) <= c->tiled_bytes) bt++;
+    const int lt = bt > cv->logt ? bt : cv->logt;
+    if (lt < lx) {
+      void* w = nullptr;
+      const int rcw = c->workspace(sizeof(cx<T>) * (size_t)nx * ny * batch, s, &w);
+      if (rcw != FFTPDE_OK) return rcw;
+      int rc = row_pass<T>(c, in, w, lx, ly, nrows, false, 1.0, s, -1, lt);
+      if (rc == FFTPDE_OK)
+        rc = col_pass<T>(c, w, nullptr, w, nullptr, lx, ly, batch, kColFwdMulInv, sym, 1, s, lt);
+      if (rc == FFTPDE_OK) rc = row_pass<T>(c, w, out, lx, ly, nrows, true, 1.0, s, lt, -1);
+      return rc;
+    }
+  }
+  int rc = row_pass<T>(c, in, out, lx, ly, nrows, false, 1.0, s);
   if (rc == FFTPDE_OK) rc = col_pass<T>(c, out, nullptr, out, nullptr, lx, ly, batch, kColFwdMulInv, sym, 1, s);
-  if (rc == FFTPDE_OK) rc = row_pass<T>(c, out, out, lx, nrows, true, 1.0, s);
+  if (rc == FFTPDE_OK) rc = row_pass<T>(c, out, out, lx, ly, nrows, true, 1.0, s);
   return rc;
 }
 
@@ -116,15 +137,15 @@ int solve_wave_two(Context* c, const void* u0, const void* v0, void* u, void* v,
   void* vbuf = v;
   if (v0 && !v) {
     const size_t bytes = sizeof(cx<T>) * (size_t)nx * ny * batch;
-    int rc = c->workspace(bytes, &vbuf);
+    int rc = c->workspace(bytes, s, &vbuf);
     if (rc != FFTPDE_OK) return rc;
   }
-  int rc = row_pass<T>(c, u0, u, lx, nrows, false, 1.0, s);
-  if (rc == FFTPDE_OK && v0) rc = row_pass<T>(c, v0, vbuf, lx, nrows, false, 1.0, s);
+  int rc = row_pass<T>(c, u0, u, lx, ly, nrows, false, 1.0, s);
+  if (rc == FFTPDE_OK && v0) rc = row_pass<T>(c, v0, vbuf, lx, ly, nrows, false, 1.0, s);
   if (rc == FFTPDE_OK)
     rc = col_pass<T>(c, u, v0 ? vbuf : nullptr, u, v, lx, ly, batch, kColFwdMulInv, sym, 2, s);
-  if (rc == FFTPDE_OK) rc = row_pass<T>(c, u, u, lx, nrows, true, 1.0, s);
-  if (rc == FFTPDE_OK && v) rc = row_pass<T>(c, v, v, lx, nrows, true, 1.0, s);
+  if (rc == FFTPDE_OK) rc = row_pass<T>(c, u, u, lx, ly, nrows, true, 1.0, s);
+  if (rc == FFTPDE_OK && v) rc = row_pass<T>(c, v, v, lx, ly, nrows, true, 1.0, s);
   return rc;
 }
 
@@ -186,8 +207,8 @@ static int materialize(Context* c, int kind, const void* F, const void* G, void*
     if (!G && !v) rc = col_pass<T>(c, F, nullptr, u, nullptr, lgx, lgy, batch, kColMulInv, sym, 1, s);
     else rc = col_pass<T>(c, F, G, u, v, lgx, lgy, batch, kColMulInv, sym, 2, s);
   }
-  if (rc == FFTPDE_OK) rc = row_pass<T>(c, u, u, lgx, nrows, true, 1.0, s);
-  if (rc == FFTPDE_OK && v) rc = row_pass<T>(c, v, v, lgx, nrows, true, 1.0, s);
+  if (rc == FFTPDE_OK) rc = row_pass<T>(c, u, u, lgx, lgy, nrows, true, 1.0, s);
+  if (rc == FFTPDE_OK && v) rc = row_pass<T>(c, v, v, lgx, lgy, nrows, true, 1.0, s);
   return rc;
 }
 
@@ -219,11 +240,12 @@ int run_diag(Context* c, int dtype, int kind, const void* F, const void* G, int 
   return FFTPDE_OK;
 }
 
-template int row_pass<float>(Context*, const void*, void*, int, long long, bool, double, hipStream_t);
-template int row_pass<double>(Context*, const void*, void*, int, long long, bool, double, hipStream_t);
+template int row_pass<float>(Context*, const void*, void*, int, int, long long, bool, double, hipStream_t, int, int);
+template int row_pass<double>(Context*, const void*, void*, int, int, long long, bool, double, hipStream_t, int,
+                              int);
 template int col_pass<float>(Context*, const void*, const void*, void*, void*, int, int, long long, int,
-                             const SymParams&, int, hipStream_t);
+                             const SymParams&, int, hipStream_t, int);
 template int col_pass<double>(Context*, const void*, const void*, void*, void*, int, int, long long, int,
-                              const SymParams&, int, hipStream_t);
+                              const SymParams&, int, hipStream_t, int);
 
 }  // namespace fftpde

@@ -24,16 +24,19 @@ hipError_t timed_launch(Context* c, const char* name, double bytes, hipStream_t 
 
 SymParams make_sym(int op, int nx, int ny, double lx, double ly, double coef, double t);
 
-// One row pass over nrows rows of length 2^lognx (forward, or inverse by
-// conjugation with `scale`).
+// One row pass over nrows = batch * 2^logny rows of length 2^lognx (forward,
+// or inverse by conjugation with `scale`).  in_t / out_t: log2 of the column
+// block width of the input / output layout (see RowArgs), -1 = row-major.
 template <typename T>
-int row_pass(Context* c, const void* in, void* out, int lognx, long long nrows, bool inverse, double scale,
-             hipStream_t s);
+int row_pass(Context* c, const void* in, void* out, int lognx, int logny, long long nrows, bool inverse,
+             double scale, hipStream_t s, int in_t = -1, int out_t = -1);
 
-// One column pass over `batch` fields of 2^lognx columns of length 2^logny.
+// One column pass over `batch` fields of 2^lognx columns of length 2^logny;
+// layout_t >= 0: the fields are stored in blocks of 2^layout_t columns
+// (at least the variant's tile width), -1: row-major.
 template <typename T>
 int col_pass(Context* c, const void* in0, const void* in1, void* out0, void* out1, int lognx, int logny,
-             long long batch, int mode, const SymParams& sym, int nf, hipStream_t s);
+             long long batch, int mode, const SymParams& sym, int nf, hipStream_t s, int layout_t = -1);
 
 // fft2d_forward / fft2d_inverse.
 int run_transform(Context* c, int dtype, bool inverse, const void* in, void* out, int nx, int ny, int batch,

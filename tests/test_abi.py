@@ -230,3 +230,10 @@ def test_request_structs_match_the_header():
     assert (R.lx.offset, R.steps.offset, R.inp.offset, R.deadline.offset, R.flags.offset) == (16, 48, 56, 88, 96)
     assert R.stream.offset == 104 and ctypes.sizeof(R) == 112 and ctypes.sizeof(fp.FftpdeResult) == 48
     assert ctypes.sizeof(fp.FftpdeStats) == 14 * 8 + 5 * 8
+
+
+def test_plan_tiled_rejects_bad_block_sizes():
+    fp, L = _lib()
+    for bad in (-1, 3, 100, 1 << 17):
+        assert L.fftpde_plan_tiled(DUMMY, bad) == fp.EINVAL
+    assert L.fftpde_plan_tiled(None, 128) == fp.EINVAL

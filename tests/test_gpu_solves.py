@@ -166,3 +166,29 @@ def test_solves_in_place(fp, dt):
     fp.solve_diffusion(t, 0.1, 0.05, 1.0, 1.0, out=t)
     ref = oracle.solve_diffusion(as_oracle_input(f, dt), 1.0, 1.0, 0.1, 0.05)
     assert oracle.rel_l2(to_host(t), ref) <= tol(dt, 128, 256, 2)
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+@pytest.mark.parametrize("nx,ny,batch", [(2048, 2048, 2), (1024, 512, 3), (4096, 64, 2), (64, 4096, 1),
+                                         (8, 2048, 5), (4, 1024, 3)])
+def test_tiled_intermediate_is_bit_identical(fp, dt, nx, ny, batch):
+    """The solve's spectrum between passes in column blocks (default) or
+    row-major: the same arithmetic, so the same bits, for every operator;
+    and the tiled result against the oracle."""
+    import torch
+    say(f"tiled vs row-major {nx}x{ny}x{batch} {dt}")
+    x = to_dev(W.random_field((batch, ny, nx), seed=nx + 3 * ny), dt)
+    outs = {}
+    try:
+        for mode in (128, 8, 1024, 0):
+            fp.plan_tiled(mode)
+            outs[mode] = (fp.solve_poisson(x, 1.0, 2.0), fp.solve_diffusion(x, 0.01, 0.3, 1.0, 2.0),
+                          fp.solve_wave(x, None, 1.0, 0.37, 1.0, 2.0)[0])
+    finally:
+        fp.plan_tiled(1024)
+    for mode in (128, 8, 1024):
+        for a, b in zip(outs[mode], outs[0]):
+            assert torch.equal(a, b)
+    ref = oracle.solve_poisson(as_oracle_input(W.random_field((batch, ny, nx), seed=nx + 3 * ny)[-1], dt), 1.0, 2.0,
+                               threads=THREADS)
+    assert oracle.rel_l2(to_host(outs[128][0])[-1], ref) <= tol(dt, nx, ny, 2)
