@@ -139,14 +139,21 @@ int fftpde_plan_tiled(fftpde_ctx *ctx, int block_bytes);
  *   `reps` timed solves each (HIP events on `stream`).  A variant is admitted
  *   only if its result matches the plan in use at the call to relative L2
  *   <= 1e-12 (C128) or 2 * 2e-6 * log2(max(nx, ny)) (C64); the fastest admitted
- *   variant becomes this context's plan for its slot.  A JSON report
- *   ({"candidates": [{"name", "pass", "us", "err", "ok"}], "row", "col"}) is
- *   written like fftpde_profile_read (report may be NULL).  Synchronises the
- *   stream; allocates and frees 3 * batch * nx * ny elements of scratch.
- * fftpde_plan_save / fftpde_plan_load: write / apply the variants chosen on
- *   this context as a text file, one variant name per line ('#' comments).
- *   Loading a name that is not compiled in gives FFTPDE_ENOTFOUND (the other
- *   lines still apply). */
+ *   variant becomes this context's plan for its slot.  Then, for shapes that
+ *   take the 3-pass path, the layout of the spectrum between the passes
+ *   (fftpde_plan_tiled block sizes 0, 256, 1024, 4096) is timed the same way
+ *   and the fastest admitted one is kept for this shape and dtype.  A JSON
+ *   report ({"candidates": [{"name", "pass", "us", "err", "ok"}],
+ *   "tiled_bytes" (-1 if not tuned), "row", "col"}) is written like
+ *   fftpde_profile_read (report may be NULL).  Synchronises the stream;
+ *   allocates and frees 3 * batch * nx * ny elements of scratch.
+ * fftpde_plan_save / fftpde_plan_load: write / apply the plan of this
+ *   context as a text file: one variant name per line, and one line
+ *   "tiled <dtype> <log2 nx> <log2 ny> <block bytes>" per tuned layout ('#'
+ *   comments).  Loading a name that is not compiled in gives
+ *   FFTPDE_ENOTFOUND, a malformed layout line FFTPDE_EINVAL (the other lines
+ *   still apply).  fftpde_plan_select(ctx, NULL) and fftpde_plan_tiled also
+ *   drop tuned layouts. */
 int fftpde_autotune(fftpde_ctx *ctx, int nx, int ny, int batch, int dtype, int op, int reps,
                     fftpde_stream stream, char *report, size_t cap, size_t *needed);
 int fftpde_plan_save(fftpde_ctx *ctx, const char *path);

@@ -1,10 +1,12 @@
-// autotune.cpp -- per-shape kernel selection.  For a (nx, ny, batch, dtype,
+// autotune.cpp -- per-shape plan selection.  For a (nx, ny, batch, dtype,
 // operator) problem every compiled variant of the row pass for nx and of the
-// column pass for ny is timed on scratch fields with HIP events; a variant is
-// admitted only if its result matches the current plan's result to the
-// dtype's tolerance; the fastest admitted variant becomes the context's plan
-// for that slot.  Plans can be written to and read from a text file (one
-// variant name per line).
+// column pass for ny is timed on scratch fields with HIP events, then the
+// layout of the spectrum between the passes (row-major or column blocks of
+// several widths); a candidate is admitted only if its result matches the
+// current plan's result to the dtype's tolerance; the fastest admitted one
+// becomes the context's plan.  Plans can be written to and read from a text
+// file (one variant name per line, and "tiled <dtype> <log2 nx> <log2 ny>
+// <bytes>" lines for layouts).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -163,7 +165,37 @@ extern "C" int fftpde_autotune(fftpde_ctx* ctx, int nx, int ny, int batch, int d
     }
     c->col_choice[k] = best;
   }
-  out += "], \"row\": \"";
+  // layout of the spectrum between the passes (3-pass solves only)
+  int tiled = -1;
+  if (!(c->use_small && c->small_variant(dtype, lgx, lgy))) {
+    const int key = Context::tiled_key(dtype, lgx, lgy);
+    auto it = c->tiled_for.find(key);
+    const bool had = it != c->tiled_for.end();
+    const int keep = had ? it->second : 0;
+    int best = c->tiled_bytes_for(dtype, lgx, lgy);
+    double best_us = 1e30;
+    for (const int bytes : {0, 256, 1024, 4096}) {
+      c->tiled_for[key] = bytes;
+      double us = 0, err = 0;
+      rc = time_solve(&us, &err);
+      if (rc != FFTPDE_OK) {
+        if (had) c->tiled_for[key] = keep;
+        else c->tiled_for.erase(key);
+        return fail(rc);
+      }
+      const bool ok = err <= tol;
+      char name[32];
+      std::snprintf(name, sizeof(name), "tiled_%d", bytes);
+      note(name, "layout", us, err, ok);
+      if (ok && us < best_us) {
+        best_us = us;
+        best = bytes;
+      }
+    }
+    c->tiled_for[key] = best;
+    tiled = best;
+  }
+  out += "], \"tiled_bytes\": " + std::to_string(tiled) + ", \"row\": \"";
   out += c->row_variant(dtype, lgx)->name;
   out += "\", \"col\": \"";
   out += c->col_variant(dtype, lgy, 1)->name;
@@ -180,11 +212,13 @@ extern "C" int fftpde_plan_save(fftpde_ctx* ctx, const char* path) {
   Context* c = reinterpret_cast<Context*>(ctx);
   std::ofstream f(path);
   if (!f) return FFTPDE_EINVAL;
-  f << "# fftpde plan: one kernel variant per line\n";
+  f << "# fftpde plan: one kernel variant per line; tiled <dtype> <log2 nx> <log2 ny> <block bytes>\n";
   for (int k = 0; k < kPlanSlots; k++) {
     if (c->row_choice[k]) f << c->row_choice[k]->name << "\n";
     if (c->col_choice[k]) f << c->col_choice[k]->name << "\n";
   }
+  for (const auto& t : c->tiled_for)
+    f << "tiled " << t.first / 256 << " " << (t.first / 16) % 16 << " " << t.first % 16 << " " << t.second << "\n";
   return f.good() ? FFTPDE_OK : FFTPDE_EINVAL;
 }
 
@@ -197,6 +231,16 @@ extern "C" int fftpde_plan_load(fftpde_ctx* ctx, const char* path) {
   while (std::getline(f, line)) {
     while (!line.empty() && (line.back() == '\r' || line.back() == ' ')) line.pop_back();
     if (line.empty() || line[0] == '#') continue;
+    if (line.compare(0, 6, "tiled ") == 0) {
+      int dt = -1, lx = -1, ly = -1, bytes = -1;
+      if (std::sscanf(line.c_str() + 6, "%d %d %d %d", &dt, &lx, &ly, &bytes) != 4 || dt < 0 || dt > 1 || lx < 1 ||
+          lx > 12 || ly < 1 || ly > 12 || bytes < 0 || bytes > 65536 || (bytes & (bytes - 1))) {
+        rc = FFTPDE_EINVAL;
+        continue;
+      }
+      reinterpret_cast<Context*>(ctx)->tiled_for[Context::tiled_key(dt, lx, ly)] = bytes;
+      continue;
+    }
     const int r = fftpde_plan_select(ctx, line.c_str());
     if (r != FFTPDE_OK) rc = r;
   }

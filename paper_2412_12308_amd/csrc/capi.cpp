@@ -376,7 +376,9 @@ int fftpde_plan_small(fftpde_ctx* ctx, int enable) {
 
 int fftpde_plan_tiled(fftpde_ctx* ctx, int block_bytes) {
   if (!ctx || block_bytes < 0 || block_bytes > 65536 || (block_bytes & (block_bytes - 1))) return FFTPDE_EINVAL;
-  reinterpret_cast<Context*>(ctx)->tiled_bytes = block_bytes;
+  Context* c = reinterpret_cast<Context*>(ctx);
+  c->tiled_bytes = block_bytes;
+  c->tiled_for.clear();  // an explicit setting overrides tuned ones
   return FFTPDE_OK;
 }
 
@@ -384,6 +386,7 @@ int fftpde_plan_select(fftpde_ctx* ctx, const char* name) {
   if (!ctx) return FFTPDE_EINVAL;
   Context* c = reinterpret_cast<Context*>(ctx);
   if (!name || !*name) {
+    c->tiled_for.clear();
     for (int k = 0; k < kPlanSlots; k++) {
       c->row_choice[k] = nullptr;
       c->col_choice[k] = nullptr;

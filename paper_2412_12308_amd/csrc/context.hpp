@@ -62,6 +62,13 @@ struct Context {
   // measured best at 2048^2 (FP32 and FP64): wide enough for full-line row
   // writes, narrow enough that the column tiles of a block stay close.
   int tiled_bytes = 1024;
+  // per-shape block size chosen by the autotuner (key: tiled_key)
+  std::unordered_map<int, int> tiled_for;
+  static int tiled_key(int dtype, int lognx, int logny) { return (dtype * 16 + lognx) * 16 + logny; }
+  int tiled_bytes_for(int dtype, int lognx, int logny) const {
+    auto it = tiled_for.find(tiled_key(dtype, lognx, logny));
+    return it == tiled_for.end() ? tiled_bytes : it->second;
+  }
 
   const RowVariant* row_variant(int dtype, int logn) const;
   const ColVariant* col_variant(int dtype, int logn, int nf) const;

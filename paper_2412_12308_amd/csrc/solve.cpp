@@ -108,9 +108,10 @@ int solve_real_symbol(Context* c, const void* in, void* out, int nx, int ny, int
   // tiled_bytes per row (whole cache lines for the row passes; the column
   // tiles of a block share its lines), at least one column tile wide.
   const ColVariant* cv = c->col_variant(sizeof(T) == 4 ? FFTPDE_C64 : FFTPDE_C128, ly, 1);
-  if (c->tiled_bytes > 0 && cv) {
+  const int tiled_bytes = c->tiled_bytes_for(sizeof(T) == 4 ? FFTPDE_C64 : FFTPDE_C128, lx, ly);
+  if (tiled_bytes > 0 && cv) {
     int bt = 0;  // log2 of the block width in columns
-    while ((int)sizeof(cx<T>) << (bt + 1) <= c->tiled_bytes) bt++;
+    while ((int)sizeof(cx<T>) << (bt + 1) <= tiled_bytes) bt++;
     const int lt = bt > cv->logt ? bt : cv->logt;
     if (lt < lx) {
       void* w = nullptr;

@@ -117,6 +117,10 @@ def test_autotune_picks_an_admitted_variant_and_round_trips(fp, dt, tmp_path):
     assert all(c["err"] <= (1e-12 if dt == "c128" else 2 * 2e-6 * 9) for c in rep["candidates"] if c["ok"])
     active = {v["name"] for v in fp.plan_variants() if v["active"]}
     assert rep["row"] in active and rep["col"] in active
+    # the layout stage: every block size timed, the chosen one among the admitted
+    layouts = {c["name"]: c for c in rep["candidates"] if c["pass"] == "layout"}
+    assert set(layouts) == {"tiled_0", "tiled_256", "tiled_1024", "tiled_4096"}
+    assert layouts[f"tiled_{rep['tiled_bytes']}"]["ok"]
     # results with the tuned plan still match the oracle
     f = W.random_field((512, 256), seed=5)
     u = to_host(fp.solve_diffusion(to_dev(f, dt), 0.2, 0.01, 1.0, 1.0))
@@ -129,4 +133,6 @@ def test_autotune_picks_an_admitted_variant_and_round_trips(fp, dt, tmp_path):
     fp.plan_load(path)
     active2 = {v["name"] for v in fp.plan_variants() if v["active"]}
     assert rep["row"] in active2 and rep["col"] in active2
+    code = 0 if dt == "c64" else 1
+    assert f"tiled {code} 8 9 {rep['tiled_bytes']}" in open(path).read()
     fp.plan_select(None)
