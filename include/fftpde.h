@@ -131,6 +131,13 @@ int fftpde_plan_small(fftpde_ctx *ctx, int enable);
  *   field.  Results are bit-identical for every block size; only the memory
  *   access pattern changes.  EINVAL unless 0 or a power of two <= 65536. */
 int fftpde_plan_tiled(fftpde_ctx *ctx, int block_bytes);
+/* fftpde_plan_chunk: a batch of 3-pass solves without an initial velocity
+ *   runs in chunks of about `bytes` of field data (at least one field), all
+ *   three passes of a chunk before the next, so that the spectrum one pass
+ *   writes is still in the GPU's 256 MiB Infinity Cache when the next pass
+ *   reads it.  Default 256 MiB; 0 = the whole batch at once.  Results are
+ *   bit-identical for every chunk size.  EINVAL for negative sizes. */
+int fftpde_plan_chunk(fftpde_ctx *ctx, long long bytes);
 
 /* fftpde_autotune: for an (nx, ny, batch, dtype, op) solve (op one of
  *   FFTPDE_POISSON / DIFFUSION / WAVE, zero initial velocity), time every
@@ -142,18 +149,22 @@ int fftpde_plan_tiled(fftpde_ctx *ctx, int block_bytes);
  *   variant becomes this context's plan for its slot.  Then, for shapes that
  *   take the 3-pass path, the layout of the spectrum between the passes
  *   (fftpde_plan_tiled block sizes 0, 256, 1024, 4096) is timed the same way
- *   and the fastest admitted one is kept for this shape and dtype.  A JSON
- *   report ({"candidates": [{"name", "pass", "us", "err", "ok"}],
- *   "tiled_bytes" (-1 if not tuned), "row", "col"}) is written like
+ *   and the fastest admitted one is kept for this shape and dtype, and so is
+ *   the chunk size of the batch (fftpde_plan_chunk: 0, 64, 128, 256, 512
+ *   MiB).  A JSON report ({"candidates": [{"name", "pass", "us", "err",
+ *   "ok"}], "tiled_bytes", "chunk_bytes" (-1 if not tuned), "row", "col"})
+ *   is written like
  *   fftpde_profile_read (report may be NULL).  Synchronises the stream;
  *   allocates and frees 3 * batch * nx * ny elements of scratch.
  * fftpde_plan_save / fftpde_plan_load: write / apply the plan of this
  *   context as a text file: one variant name per line, and one line
- *   "tiled <dtype> <log2 nx> <log2 ny> <block bytes>" per tuned layout ('#'
+ *   "tiled <dtype> <log2 nx> <log2 ny> <block bytes>" / "chunk <dtype>
+ *   <log2 nx> <log2 ny> <bytes>" per tuned layout / chunk size ('#'
  *   comments).  Loading a name that is not compiled in gives
- *   FFTPDE_ENOTFOUND, a malformed layout line FFTPDE_EINVAL (the other lines
- *   still apply).  fftpde_plan_select(ctx, NULL) and fftpde_plan_tiled also
- *   drop tuned layouts. */
+ *   FFTPDE_ENOTFOUND, a malformed layout or chunk line FFTPDE_EINVAL (the
+ *   other lines still apply).  fftpde_plan_select(ctx, NULL) drops tuned
+ *   layouts and chunk sizes; fftpde_plan_tiled / fftpde_plan_chunk drop the
+ *   tuned ones of their kind. */
 int fftpde_autotune(fftpde_ctx *ctx, int nx, int ny, int batch, int dtype, int op, int reps,
                     fftpde_stream stream, char *report, size_t cap, size_t *needed);
 int fftpde_plan_save(fftpde_ctx *ctx, const char *path);

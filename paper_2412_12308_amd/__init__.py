@@ -119,6 +119,7 @@ def _declare(L):
     L.fftpde_plan_select.argtypes = [vp, ctypes.c_char_p]
     L.fftpde_plan_small.argtypes = [vp, i]
     L.fftpde_plan_tiled.argtypes = [vp, i]
+    L.fftpde_plan_chunk.argtypes = [vp, ctypes.c_longlong]
     L.fftpde_autotune.argtypes = [vp, i, i, i, i, i, i, vp, ctypes.c_char_p, ctypes.c_size_t,
                                   ctypes.POINTER(ctypes.c_size_t)]
     L.fftpde_plan_save.argtypes = [vp, ctypes.c_char_p]
@@ -147,7 +148,7 @@ def _declare(L):
               "fftpde_server_wait", "fftpde_server_cancel", "fftpde_server_copy_out", "fftpde_server_release",
               "fftpde_server_stats", "fftpde_server_destroy",
               "fftpde_batch_create", "fftpde_batch_run", "fftpde_batch_status", "fftpde_batch_info",
-              "fftpde_batch_destroy", "fftpde_plan_small", "fftpde_plan_tiled", "fftpde_evolve_create", "fftpde_evolve_step", "fftpde_evolve_destroy", "fftpde_autotune", "fftpde_plan_save", "fftpde_plan_load", "fftpde_plan_variants",
+              "fftpde_batch_destroy", "fftpde_plan_small", "fftpde_plan_tiled", "fftpde_plan_chunk", "fftpde_evolve_create", "fftpde_evolve_step", "fftpde_evolve_destroy", "fftpde_autotune", "fftpde_plan_save", "fftpde_plan_load", "fftpde_plan_variants",
               "fftpde_plan_select", "fftpde_profile", "fftpde_profile_read", "fftpde_create", "fftpde_destroy", "fft2d_forward", "fft2d_inverse", "solve_poisson",
               "solve_diffusion", "solve_wave"):
         getattr(L, f).restype = i
@@ -224,6 +225,12 @@ def plan_variants(device: int = 0):
 def plan_small(enable: bool, device: int = 0):
     """Use (default) or bypass the single-pass small-grid kernels."""
     _check(lib().fftpde_plan_small(context(device), 1 if enable else 0), "fftpde_plan_small")
+
+
+def plan_chunk(nbytes: int = 256 << 20, device: int = 0):
+    """Run batches of 3-pass solves in chunks of about `nbytes` of field data
+    (fftpde_plan_chunk; 0 = whole batch).  Results are bit-identical."""
+    _check(lib().fftpde_plan_chunk(context(device), int(nbytes)), "fftpde_plan_chunk")
 
 
 def plan_tiled(block_bytes: int = 1024, device: int = 0):

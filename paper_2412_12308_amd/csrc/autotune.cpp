@@ -2,11 +2,11 @@
 // operator) problem every compiled variant of the row pass for nx and of the
 // column pass for ny is timed on scratch fields with HIP events, then the
 // layout of the spectrum between the passes (row-major or column blocks of
-// several widths); a candidate is admitted only if its result matches the
-// current plan's result to the dtype's tolerance; the fastest admitted one
-// becomes the context's plan.  Plans can be written to and read from a text
-// file (one variant name per line, and "tiled <dtype> <log2 nx> <log2 ny>
-// <bytes>" lines for layouts).
+// several widths), then the chunking of the batch; a candidate is admitted
+// only if its result matches the current plan's result to the dtype's
+// tolerance; the fastest admitted one becomes the context's plan.  Plans can
+// be written to and read from a text file (one variant name per line, and
+// "tiled|chunk <dtype> <log2 nx> <log2 ny> <bytes>" lines).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -195,7 +195,34 @@ extern "C" int fftpde_autotune(fftpde_ctx* ctx, int nx, int ny, int batch, int d
     c->tiled_for[key] = best;
     tiled = best;
   }
-  out += "], \"tiled_bytes\": " + std::to_string(tiled) + ", \"row\": \"";
+  // chunking of the batch (3-pass solves only)
+  long long chunk = -1;
+  if (tiled >= 0) {
+    const int key = Context::tiled_key(dtype, lgx, lgy);
+    long long best = c->chunk_bytes_for(dtype, lgx, lgy);
+    double best_us = 1e30;
+    for (const long long cb : {0ll, 64ll << 20, 128ll << 20, 256ll << 20, 512ll << 20}) {
+      c->chunk_for[key] = cb;
+      double us = 0, err = 0;
+      rc = time_solve(&us, &err);
+      if (rc != FFTPDE_OK) {
+        c->chunk_for.erase(key);
+        return fail(rc);
+      }
+      const bool ok = err <= tol;
+      char name[40];
+      std::snprintf(name, sizeof(name), "chunk_%lld", cb);
+      note(name, "chunk", us, err, ok);
+      if (ok && us < best_us) {
+        best_us = us;
+        best = cb;
+      }
+    }
+    c->chunk_for[key] = best;
+    chunk = best;
+  }
+  out += "], \"tiled_bytes\": " + std::to_string(tiled) + ", \"chunk_bytes\": " + std::to_string(chunk) +
+         ", \"row\": \"";
   out += c->row_variant(dtype, lgx)->name;
   out += "\", \"col\": \"";
   out += c->col_variant(dtype, lgy, 1)->name;
@@ -219,6 +246,8 @@ extern "C" int fftpde_plan_save(fftpde_ctx* ctx, const char* path) {
   }
   for (const auto& t : c->tiled_for)
     f << "tiled " << t.first / 256 << " " << (t.first / 16) % 16 << " " << t.first % 16 << " " << t.second << "\n";
+  for (const auto& t : c->chunk_for)
+    f << "chunk " << t.first / 256 << " " << (t.first / 16) % 16 << " " << t.first % 16 << " " << t.second << "\n";
   return f.good() ? FFTPDE_OK : FFTPDE_EINVAL;
 }
 
@@ -239,6 +268,17 @@ extern "C" int fftpde_plan_load(fftpde_ctx* ctx, const char* path) {
         continue;
       }
       reinterpret_cast<Context*>(ctx)->tiled_for[Context::tiled_key(dt, lx, ly)] = bytes;
+      continue;
+    }
+    if (line.compare(0, 6, "chunk ") == 0) {
+      int dt = -1, lx = -1, ly = -1;
+      long long bytes = -1;
+      if (std::sscanf(line.c_str() + 6, "%d %d %d %lld", &dt, &lx, &ly, &bytes) != 4 || dt < 0 || dt > 1 || lx < 1 ||
+          lx > 12 || ly < 1 || ly > 12 || bytes < 0) {
+        rc = FFTPDE_EINVAL;
+        continue;
+      }
+      reinterpret_cast<Context*>(ctx)->chunk_for[Context::tiled_key(dt, lx, ly)] = bytes;
       continue;
     }
     const int r = fftpde_plan_select(ctx, line.c_str());

@@ -382,11 +382,20 @@ int fftpde_plan_tiled(fftpde_ctx* ctx, int block_bytes) {
   return FFTPDE_OK;
 }
 
+int fftpde_plan_chunk(fftpde_ctx* ctx, long long bytes) {
+  if (!ctx || bytes < 0) return FFTPDE_EINVAL;
+  Context* c = reinterpret_cast<Context*>(ctx);
+  c->chunk_bytes = bytes;
+  c->chunk_for.clear();  // an explicit setting overrides tuned ones
+  return FFTPDE_OK;
+}
+
 int fftpde_plan_select(fftpde_ctx* ctx, const char* name) {
   if (!ctx) return FFTPDE_EINVAL;
   Context* c = reinterpret_cast<Context*>(ctx);
   if (!name || !*name) {
     c->tiled_for.clear();
+    c->chunk_for.clear();
     for (int k = 0; k < kPlanSlots; k++) {
       c->row_choice[k] = nullptr;
       c->col_choice[k] = nullptr;

@@ -62,8 +62,18 @@ struct Context {
   // measured best at 2048^2 (FP32 and FP64): wide enough for full-line row
   // writes, narrow enough that the column tiles of a block stay close.
   int tiled_bytes = 1024;
-  // per-shape block size chosen by the autotuner (key: tiled_key)
+  // Batches of 3-pass solves run in chunks of about chunk_bytes of field
+  // data, all three passes per chunk, so that the spectrum a pass writes is
+  // still in the 256 MiB Infinity Cache when the next pass reads it (0: the
+  // whole batch at once).  Set with fftpde_plan_chunk.
+  long long chunk_bytes = 256ll << 20;
+  // per-shape block size and chunk size chosen by the autotuner (key: tiled_key)
   std::unordered_map<int, int> tiled_for;
+  std::unordered_map<int, long long> chunk_for;
+  long long chunk_bytes_for(int dtype, int lognx, int logny) const {
+    auto it = chunk_for.find(tiled_key(dtype, lognx, logny));
+    return it == chunk_for.end() ? chunk_bytes : it->second;
+  }
   static int tiled_key(int dtype, int lognx, int logny) { return (dtype * 16 + lognx) * 16 + logny; }
   int tiled_bytes_for(int dtype, int lognx, int logny) const {
     auto it = tiled_for.find(tiled_key(dtype, lognx, logny));

@@ -5,6 +5,7 @@
 
 #include "diag.hpp"
 
+#include <algorithm>
 #include <cmath>
 
 #include "../../include/fftpde.h"
@@ -98,36 +99,47 @@ int transform(Context* c, const void* in, void* out, int nx, int ny, int batch, 
   return rc;
 }
 
-// forward rows -> fused column pass -> inverse rows, for one real symbol
+// forward rows -> fused column pass -> inverse rows, for one real symbol;
+// batches run in chunks (Context::chunk_bytes), every pass of a chunk before
+// the next chunk
 template <typename T>
 int solve_real_symbol(Context* c, const void* in, void* out, int nx, int ny, int batch, const SymParams& sym,
                       hipStream_t s) {
+  const int dt = sizeof(T) == 4 ? FFTPDE_C64 : FFTPDE_C128;
   const int lx = ilog2(nx), ly = ilog2(ny);
-  const long long nrows = (long long)ny * batch;
+  const size_t field = sizeof(cx<T>) * (size_t)nx * ny;
+  const long long cb = c->chunk_bytes_for(dt, lx, ly);
+  long long chunk = cb > 0 ? std::max<long long>(1, cb / (long long)field) : batch;
+  chunk = std::min<long long>(chunk, batch);
   // Tiled intermediate in a per-stream scratch field: column blocks of
   // tiled_bytes per row (whole cache lines for the row passes; the column
   // tiles of a block share its lines), at least one column tile wide.
-  const ColVariant* cv = c->col_variant(sizeof(T) == 4 ? FFTPDE_C64 : FFTPDE_C128, ly, 1);
-  const int tiled_bytes = c->tiled_bytes_for(sizeof(T) == 4 ? FFTPDE_C64 : FFTPDE_C128, lx, ly);
+  const ColVariant* cv = c->col_variant(dt, ly, 1);
+  const int tiled_bytes = c->tiled_bytes_for(dt, lx, ly);
+  int lt = -1;
+  void* w = nullptr;
   if (tiled_bytes > 0 && cv) {
     int bt = 0;  // log2 of the block width in columns
     while ((int)sizeof(cx<T>) << (bt + 1) <= tiled_bytes) bt++;
-    const int lt = bt > cv->logt ? bt : cv->logt;
-    if (lt < lx) {
-      void* w = nullptr;
-      const int rcw = c->workspace(sizeof(cx<T>) * (size_t)nx * ny * batch, s, &w);
+    lt = bt > cv->logt ? bt : cv->logt;
+    if (lt >= lx) lt = -1;
+    if (lt >= 0) {
+      const int rcw = c->workspace(field * (size_t)chunk, s, &w);
       if (rcw != FFTPDE_OK) return rcw;
-      int rc = row_pass<T>(c, in, w, lx, ly, nrows, false, 1.0, s, -1, lt);
-      if (rc == FFTPDE_OK)
-        rc = col_pass<T>(c, w, nullptr, w, nullptr, lx, ly, batch, kColFwdMulInv, sym, 1, s, lt);
-      if (rc == FFTPDE_OK) rc = row_pass<T>(c, w, out, lx, ly, nrows, true, 1.0, s, lt, -1);
-      return rc;
     }
   }
-  int rc = row_pass<T>(c, in, out, lx, ly, nrows, false, 1.0, s);
-  if (rc == FFTPDE_OK) rc = col_pass<T>(c, out, nullptr, out, nullptr, lx, ly, batch, kColFwdMulInv, sym, 1, s);
-  if (rc == FFTPDE_OK) rc = row_pass<T>(c, out, out, lx, ly, nrows, true, 1.0, s);
-  return rc;
+  for (long long b0 = 0; b0 < batch; b0 += chunk) {
+    const long long nb = std::min<long long>(chunk, batch - b0);
+    const long long nrows = (long long)ny * nb;
+    const void* ib = static_cast<const char*>(in) + field * b0;
+    void* ob = static_cast<char*>(out) + field * b0;
+    void* mid = lt >= 0 ? w : ob;  // the spectrum between the passes
+    int rc = row_pass<T>(c, ib, mid, lx, ly, nrows, false, 1.0, s, -1, lt);
+    if (rc == FFTPDE_OK) rc = col_pass<T>(c, mid, nullptr, mid, nullptr, lx, ly, nb, kColFwdMulInv, sym, 1, s, lt);
+    if (rc == FFTPDE_OK) rc = row_pass<T>(c, mid, ob, lx, ly, nrows, true, 1.0, s, lt, -1);
+    if (rc != FFTPDE_OK) return rc;
+  }
+  return FFTPDE_OK;
 }
 
 template <typename T>

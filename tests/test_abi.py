@@ -237,3 +237,9 @@ def test_plan_tiled_rejects_bad_block_sizes():
     for bad in (-1, 3, 100, 1 << 17):
         assert L.fftpde_plan_tiled(DUMMY, bad) == fp.EINVAL
     assert L.fftpde_plan_tiled(None, 128) == fp.EINVAL
+
+
+def test_plan_chunk_rejects_negative_sizes():
+    fp, L = _lib()
+    assert L.fftpde_plan_chunk(DUMMY, -1) == fp.EINVAL
+    assert L.fftpde_plan_chunk(None, 1 << 20) == fp.EINVAL

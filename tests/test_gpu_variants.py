@@ -121,6 +121,8 @@ def test_autotune_picks_an_admitted_variant_and_round_trips(fp, dt, tmp_path):
     layouts = {c["name"]: c for c in rep["candidates"] if c["pass"] == "layout"}
     assert set(layouts) == {"tiled_0", "tiled_256", "tiled_1024", "tiled_4096"}
     assert layouts[f"tiled_{rep['tiled_bytes']}"]["ok"]
+    chunks = {c["name"]: c for c in rep["candidates"] if c["pass"] == "chunk"}
+    assert len(chunks) == 5 and chunks[f"chunk_{rep['chunk_bytes']}"]["ok"]
     # results with the tuned plan still match the oracle
     f = W.random_field((512, 256), seed=5)
     u = to_host(fp.solve_diffusion(to_dev(f, dt), 0.2, 0.01, 1.0, 1.0))
@@ -135,4 +137,5 @@ def test_autotune_picks_an_admitted_variant_and_round_trips(fp, dt, tmp_path):
     assert rep["row"] in active2 and rep["col"] in active2
     code = 0 if dt == "c64" else 1
     assert f"tiled {code} 8 9 {rep['tiled_bytes']}" in open(path).read()
+    assert f"chunk {code} 8 9 {rep['chunk_bytes']}" in open(path).read()
     fp.plan_select(None)
