@@ -84,19 +84,49 @@ SymParams make_sym(int op, int nx, int ny, double lx, double ly, double coef, do
   return p;
 }
 
+// Runs f(b0, nb, byte offset) over chunks of the batch of about
+// Context::chunk_bytes of field data: every pass of one chunk before the next,
+// so that what a pass writes is still in the Infinity Cache for the next.
+template <typename T, class F>
+int for_chunks(Context* c, int nx, int ny, int batch, F&& f) {
+  const size_t field = sizeof(cx<T>) * (size_t)nx * ny;
+  const long long cb = c->chunk_bytes_for(sizeof(T) == 4 ? FFTPDE_C64 : FFTPDE_C128, ilog2(nx), ilog2(ny));
+  long long chunk = cb > 0 ? std::max<long long>(1, cb / (long long)field) : batch;
+  chunk = std::min<long long>(chunk, batch);
+  for (long long b0 = 0; b0 < batch; b0 += chunk) {
+    const long long nb = std::min<long long>(chunk, batch - b0);
+    const int rc = f(b0, nb, field * (size_t)b0);
+    if (rc != FFTPDE_OK) return rc;
+  }
+  return FFTPDE_OK;
+}
+
+template <typename T>
+static const void* at(const void* p, size_t off) {
+  return p ? static_cast<const char*>(p) + off : nullptr;
+}
+template <typename T>
+static void* at(void* p, size_t off) {
+  return p ? static_cast<char*>(p) + off : nullptr;
+}
+
 template <typename T>
 int transform(Context* c, const void* in, void* out, int nx, int ny, int batch, bool inverse, hipStream_t s) {
   const int lx = ilog2(nx), ly = ilog2(ny);
   SymParams sym = make_sym(kSymScale, nx, ny, 1.0, 1.0, 0.0, 0.0);
-  int rc;
-  if (!inverse) {
-    rc = row_pass<T>(c, in, out, lx, ly, (long long)ny * batch, false, 1.0, s);
-    if (rc == FFTPDE_OK) rc = col_pass<T>(c, out, nullptr, out, nullptr, lx, ly, batch, kColForward, sym, 1, s);
-  } else {
-    rc = col_pass<T>(c, in, nullptr, out, nullptr, lx, ly, batch, kColInverse, sym, 1, s);
-    if (rc == FFTPDE_OK) rc = row_pass<T>(c, out, out, lx, ly, (long long)ny * batch, true, 1.0, s);
-  }
-  return rc;
+  return for_chunks<T>(c, nx, ny, batch, [&](long long, long long nb, size_t off) {
+    const void* ib = at<T>(in, off);
+    void* ob = at<T>(out, off);
+    int rc;
+    if (!inverse) {
+      rc = row_pass<T>(c, ib, ob, lx, ly, (long long)ny * nb, false, 1.0, s);
+      if (rc == FFTPDE_OK) rc = col_pass<T>(c, ob, nullptr, ob, nullptr, lx, ly, nb, kColForward, sym, 1, s);
+    } else {
+      rc = col_pass<T>(c, ib, nullptr, ob, nullptr, lx, ly, nb, kColInverse, sym, 1, s);
+      if (rc == FFTPDE_OK) rc = row_pass<T>(c, ob, ob, lx, ly, (long long)ny * nb, true, 1.0, s);
+    }
+    return rc;
+  });
 }
 
 // forward rows -> fused column pass -> inverse rows, for one real symbol;
@@ -146,20 +176,26 @@ template <typename T>
 int solve_wave_two(Context* c, const void* u0, const void* v0, void* u, void* v, int nx, int ny, int batch,
                    const SymParams& sym, hipStream_t s) {
   const int lx = ilog2(nx), ly = ilog2(ny);
-  const long long nrows = (long long)ny * batch;
-  void* vbuf = v;
+  const size_t field = sizeof(cx<T>) * (size_t)nx * ny;
+  const long long cb = c->chunk_bytes_for(sizeof(T) == 4 ? FFTPDE_C64 : FFTPDE_C128, lx, ly);
+  const long long chunk = std::min<long long>(cb > 0 ? std::max<long long>(1, cb / (long long)field) : batch, batch);
+  void* vbuf = nullptr;  // the velocity's spectrum when no velocity output is asked for
   if (v0 && !v) {
-    const size_t bytes = sizeof(cx<T>) * (size_t)nx * ny * batch;
-    int rc = c->workspace(bytes, s, &vbuf);
+    int rc = c->workspace(field * (size_t)chunk, s, &vbuf);
     if (rc != FFTPDE_OK) return rc;
   }
-  int rc = row_pass<T>(c, u0, u, lx, ly, nrows, false, 1.0, s);
-  if (rc == FFTPDE_OK && v0) rc = row_pass<T>(c, v0, vbuf, lx, ly, nrows, false, 1.0, s);
-  if (rc == FFTPDE_OK)
-    rc = col_pass<T>(c, u, v0 ? vbuf : nullptr, u, v, lx, ly, batch, kColFwdMulInv, sym, 2, s);
-  if (rc == FFTPDE_OK) rc = row_pass<T>(c, u, u, lx, ly, nrows, true, 1.0, s);
-  if (rc == FFTPDE_OK && v) rc = row_pass<T>(c, v, v, lx, ly, nrows, true, 1.0, s);
-  return rc;
+  return for_chunks<T>(c, nx, ny, batch, [&](long long, long long nb, size_t off) {
+    const long long nrows = (long long)ny * nb;
+    void* ub = at<T>(u, off);
+    void* vb = at<T>(v, off);
+    void* gb = v0 ? (v ? vb : vbuf) : nullptr;
+    int rc = row_pass<T>(c, at<T>(u0, off), ub, lx, ly, nrows, false, 1.0, s);
+    if (rc == FFTPDE_OK && v0) rc = row_pass<T>(c, at<T>(v0, off), gb, lx, ly, nrows, false, 1.0, s);
+    if (rc == FFTPDE_OK) rc = col_pass<T>(c, ub, gb, ub, vb, lx, ly, nb, kColFwdMulInv, sym, 2, s);
+    if (rc == FFTPDE_OK) rc = row_pass<T>(c, ub, ub, lx, ly, nrows, true, 1.0, s);
+    if (rc == FFTPDE_OK && vb) rc = row_pass<T>(c, vb, vb, lx, ly, nrows, true, 1.0, s);
+    return rc;
+  });
 }
 
 
@@ -210,19 +246,18 @@ template <typename T>
 static int materialize(Context* c, int kind, const void* F, const void* G, void* u, void* v, int nx, int ny, int batch,
                        double lx, double ly, double coef, double t, hipStream_t s) {
   const int lgx = ilog2(nx), lgy = ilog2(ny);
-  const long long nrows = (long long)ny * batch;
-  int rc;
-  if (kind == FFTPDE_DIFFUSION) {
-    const SymParams sym = make_sym(kSymDiffusion, nx, ny, lx, ly, coef, t);
-    rc = col_pass<T>(c, F, nullptr, u, nullptr, lgx, lgy, batch, kColMulInv, sym, 1, s);
-  } else {
-    const SymParams sym = make_sym(kSymWave, nx, ny, lx, ly, coef, t);
-    if (!G && !v) rc = col_pass<T>(c, F, nullptr, u, nullptr, lgx, lgy, batch, kColMulInv, sym, 1, s);
-    else rc = col_pass<T>(c, F, G, u, v, lgx, lgy, batch, kColMulInv, sym, 2, s);
-  }
-  if (rc == FFTPDE_OK) rc = row_pass<T>(c, u, u, lgx, lgy, nrows, true, 1.0, s);
-  if (rc == FFTPDE_OK && v) rc = row_pass<T>(c, v, v, lgx, lgy, nrows, true, 1.0, s);
-  return rc;
+  const SymParams sym = make_sym(kind == FFTPDE_DIFFUSION ? kSymDiffusion : kSymWave, nx, ny, lx, ly, coef, t);
+  const int nf = kind == FFTPDE_WAVE && (G || v) ? 2 : 1;
+  return for_chunks<T>(c, nx, ny, batch, [&](long long, long long nb, size_t off) {
+    const long long nrows = (long long)ny * nb;
+    void* ub = at<T>(u, off);
+    void* vb = at<T>(v, off);
+    int rc = col_pass<T>(c, at<T>(F, off), nf == 2 ? at<T>(G, off) : nullptr, ub, nf == 2 ? vb : nullptr, lgx, lgy,
+                         nb, kColMulInv, sym, nf, s);
+    if (rc == FFTPDE_OK) rc = row_pass<T>(c, ub, ub, lgx, lgy, nrows, true, 1.0, s);
+    if (rc == FFTPDE_OK && vb) rc = row_pass<T>(c, vb, vb, lgx, lgy, nrows, true, 1.0, s);
+    return rc;
+  });
 }
 
 int run_materialize(Context* c, int dtype, int kind, const void* F, const void* G, void* u, void* v, int nx, int ny,

@@ -216,3 +216,34 @@ def test_chunked_batches_are_bit_identical(fp, dt):
         fp.plan_chunk(256 << 20)
     for o in outs[1:]:
         assert torch.equal(o, outs[0])
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_chunked_transforms_wave_velocity_and_evolution_are_bit_identical(fp, dt):
+    """Every multi-pass path run in chunks (one field, three with a ragged
+    last chunk) gives the bits of the whole batch at once: 2D transforms, the
+    wave with an initial velocity and a velocity output, evolution steps."""
+    import torch
+    nx, ny, batch = 128, 256, 5
+    field = nx * ny * (8 if dt == "c64" else 16)
+    say(f"chunked paths {nx}x{ny}x{batch} {dt}")
+    u0 = to_dev(W.random_field((batch, ny, nx), seed=21), dt)
+    v0 = to_dev(W.random_field((batch, ny, nx), seed=22), dt)
+    runs = []
+    try:
+        for chunk in (0, field, 3 * field):
+            fp.plan_chunk(chunk)
+            r = [fp.fft2d_forward(u0), fp.fft2d_inverse(u0)]
+            r += list(fp.solve_wave(u0, v0, 0.8, 0.3, 1.0, 2.0, want_v=True))
+            r.append(fp.solve_wave(u0, v0, 0.8, 0.3, 1.0, 2.0)[0])
+            with fp.Evolution(fp.WAVE, u0, v0, 0.8, 1.0, 2.0) as ev:
+                u, v, _ = ev.step(7, 0.05, want_v=True)
+                r += [u, v]
+            with fp.Evolution(fp.DIFFUSION, u0, None, 0.01, 1.0, 2.0) as ev:
+                r.append(ev.step(3, 0.1)[0])
+            runs.append(r)
+    finally:
+        fp.plan_chunk(256 << 20)
+    for r in runs[1:]:
+        for a, b in zip(r, runs[0]):
+            assert torch.equal(a, b)
