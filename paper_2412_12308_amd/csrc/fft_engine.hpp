@@ -320,6 +320,31 @@ struct Engine {
   __device__ __forceinline__ static void for_each_output(int tid, F&& f) {
     for_each<NST - 1>(tid, f);
   }
+  // The same positions with n split as j + d: f(register index, line, j, d),
+  // where d = t N/R is a compile-time constant of the unrolled visit and j
+  // does not depend on t (so an address built from j is formed once per
+  // butterfly and d goes into a wave-uniform part).
+  template <int S, class F>
+  __device__ __forceinline__ static void for_each_split(int tid, F&& f) {
+    constexpr int LR = lr<S>();
+    constexpr int R = 1 << LR;
+    constexpr int M = N >> LR;
+#pragma unroll
+    for (int q = 0; q < E / R; q++) {
+      int line, j;
+      Map::split(tid + TH * q, LOGN - LR, line, j);
+#pragma unroll
+      for (int t = 0; t < R; t++) f(q * R + t, line, j, t * M);
+    }
+  }
+  template <class F>
+  __device__ __forceinline__ static void for_each_input_split(int tid, F&& f) {
+    for_each_split<0>(tid, f);
+  }
+  template <class F>
+  __device__ __forceinline__ static void for_each_output_split(int tid, F&& f) {
+    for_each_split<NST - 1>(tid, f);
+  }
 
   // Stage S's outputs go to LDS; stage S+1's inputs come back.  When the map's
   // padding is affine for this plan, each butterfly's R positions are one

@@ -85,6 +85,12 @@ struct ColArgs {
   int layout_t;       // fields stored in blocks of 2^layout_t >= 2^LOGT columns (see RowArgs); -1 row-major
 };
 
+// a type carried as a value (to pass an engine type to a generic lambda)
+template <class E>
+struct EngTag {
+  using type = E;
+};
+
 // signed frequency index a' of slot a on a 2^logn axis
 __device__ __forceinline__ int signed_index(int a, int logn) {
   return a < (1 << (logn - 1)) ? a : a - (1 << logn);
@@ -355,10 +361,38 @@ __global__ void __launch_bounds__(TH) col_kernel(ColArgs<T> a) {
     const long long xa = C & fmask;
     return ((C >> lognx) << (lognx + LOGN)) + ((xa >> ts) << (LOGN + ts)) + (xa & tmask);
   };
+  // When nx >= T every tile lies in one block of one field: its column c at
+  // row n is element base + (n << ts) + c, with base wave-uniform.  Each
+  // access is then a uniform row part d << ts (d a compile-time multiple of
+  // N/R) on a scalar base plus one 32-bit per-thread byte offset that is
+  // formed once per butterfly, instead of a 64-bit address per element.
+  const bool whole = kOneCol && lognx >= LOGT;
+  auto at_row = [&](auto* base, unsigned off, int d) {
+    using P = decltype(base);
+    using B = typename std::conditional<std::is_const<typename std::remove_pointer<P>::type>::value, const char,
+                                        char>::type;
+    return reinterpret_cast<P>(reinterpret_cast<B*>(base + ((long long)d << ts)) + off);
+  };
+  auto row_off = [&](int j, int line) -> unsigned {
+    return (((unsigned)j << ts) + (unsigned)line) * (unsigned)sizeof(cx<T>);
+  };
   // Loads are clamped to the last column (padding columns are reread and never
   // stored), so loads carry no branches and prefetches stay in flight.
   auto load = [&](long long tile, cx<T>(&dx)[E], cx<T>(&dy)[NF == 2 ? E : 1]) {
     const long long col0 = tile << LOGT;
+    if (whole) {
+      const long long cb = col_base(col0);
+      const cx<T>* b0 = a.in0 + cb;
+      const cx<T>* b1 = has_in1 ? a.in1 + cb : a.in0;
+      auto g = [&](int i, int line, int j, int d) {
+        const unsigned off = row_off(j, line);
+        dx[i] = *at_row(b0, off, d);
+        if constexpr (NF == 2) dy[i] = has_in1 ? *at_row(b1, off, d) : cx<T>{T(0), T(0)};
+      };
+      if (spec_in) Inv::for_each_input_split(tid, g);
+      else Fwd::for_each_input_split(tid, g);
+      return;
+    }
     long long cb = 0;
     if constexpr (kOneCol) cb = col_base(min(col0 + (tid & (TT - 1)), a.ncols - 1));
     auto f = [&](int i, int line, int n) {
@@ -371,20 +405,25 @@ __global__ void __launch_bounds__(TH) col_kernel(ColArgs<T> a) {
     if (spec_in) Inv::for_each_input(tid, f);
     else Fwd::for_each_input(tid, f);
   };
-  // Stores of the last stage's outputs, skipping padding columns.
-  auto store = [&](long long col0, cx<T>* out, auto&& value) {
-    if constexpr (kOneCol) {
+  // Stores of engine Eng's last-stage outputs, skipping padding columns.
+  auto emit = [&](auto eng_tag, long long col0, cx<T>* out, auto&& value) {
+    using Eng = typename decltype(eng_tag)::type;
+    if (whole) {
+      cx<T>* b = out + col_base(col0);
+      Eng::for_each_output_split(tid, [&](int i, int line, int j, int d) { *at_row(b, row_off(j, line), d) = value(i); });
+    } else if constexpr (kOneCol) {
       const long long C = col0 + (tid & (TT - 1));
       if (C >= a.ncols) return;
       cx<T>* o = out + col_base(C);
-      Inv::for_each_output(tid, [&](int i, int, int n) { o[(long long)n << ts] = value(i); });
+      Eng::for_each_output(tid, [&](int i, int, int n) { o[(long long)n << ts] = value(i); });
     } else {
-      Inv::for_each_output(tid, [&](int i, int line, int n) {
+      Eng::for_each_output(tid, [&](int i, int line, int n) {
         const long long C = col0 + line;
         if (C < a.ncols) out[col_base(C) + ((long long)n << ts)] = value(i);
       });
     }
   };
+  auto store = [&](long long col0, cx<T>* out, auto&& value) { emit(EngTag<Inv>(), col0, out, value); };
 
   if constexpr (TWM == kTwLds) {
     Fwd::load_lds_table(twl, a.tw, tid);
@@ -437,20 +476,7 @@ __global__ void __launch_bounds__(TH) col_kernel(ColArgs<T> a) {
       fwd(x, tid);
       const T sc = mode == kColInverse ? T(a.sym.scale) : T(1);
       const T si = sgn * sc;
-      if constexpr (kOneCol) {
-        const long long C = col0 + (tid & (TT - 1));
-        if (C < a.ncols) {
-          cx<T>* o = a.out0 + col_base(C);
-          Fwd::for_each_output(tid, [&](int i, int, int n) {
-            o[(long long)n << ts] = {x[i].re * sc, x[i].im * si};
-          });
-        }
-      } else {
-        Fwd::for_each_output(tid, [&](int i, int line, int n) {
-          const long long C = col0 + line;
-          if (C < a.ncols) a.out0[col_base(C) + ((long long)n << ts)] = {x[i].re * sc, x[i].im * si};
-        });
-      }
+      emit(EngTag<Fwd>(), col0, a.out0, [&](int i) { return cx<T>{x[i].re * sc, x[i].im * si}; });
     } else {
       if (!spec_in) {
         fwd(x, tid);

@@ -169,6 +169,30 @@ def test_solves_in_place(fp, dt):
 
 
 @pytest.mark.parametrize("dt", ["c64", "c128"])
+@pytest.mark.parametrize("op,nx,ny,batch", [("wave", 2048, 2048, 2), ("wave", 256, 512, 3),
+                                            ("diffusion", 512, 128, 2), ("diffusion", 4, 4096, 2),
+                                            ("wave", 4096, 16, 3)])
+def test_multi_field_solves_vs_oracle(fp, dt, op, nx, ny, batch):
+    """Diffusion and wave solves over several fields of 3-pass shapes (tiles
+    within one column block, and narrow fields whose tiles span fields):
+    every field against the oracle."""
+    say(f"multi-field {op} {nx}x{ny}x{batch} {dt}")
+    f = W.random_field((batch, ny, nx), seed=nx + ny + batch)
+    x = to_dev(f, dt)
+    if op == "wave":
+        out = to_host(fp.solve_wave(x, None, 0.9, 0.37, 1.0, 2.0)[0])
+    else:
+        out = to_host(fp.solve_diffusion(x, 0.05, 0.21, 2.0, 1.0))
+    for k in range(batch):
+        g = as_oracle_input(f[k], dt)
+        if op == "wave":
+            ref, _ = oracle.solve_wave(g, None, 1.0, 2.0, 0.9, 0.37, threads=THREADS)
+        else:
+            ref = oracle.solve_diffusion(g, 2.0, 1.0, 0.05, 0.21, threads=THREADS)
+        assert oracle.rel_l2(out[k], ref) <= tol(dt, nx, ny, 2)
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
 @pytest.mark.parametrize("nx,ny,batch", [(2048, 2048, 2), (1024, 512, 3), (4096, 64, 2), (64, 4096, 1),
                                          (8, 2048, 5), (4, 1024, 3)])
 def test_tiled_intermediate_is_bit_identical(fp, dt, nx, ny, batch):
