@@ -11,6 +11,10 @@ keeps the working set (2 x 512 MiB at B = 16) well above the 256 MiB
 Infinity Cache, so the passes run from HBM.  The same workload in FP64
 (B = 8) is reported beside it.
 
+The same problems stored as real fields (the initial data are real) are
+timed beside them: two real fields per complex transform, half the bytes per
+solve (`real_fields`; 2B FP32 / B FP64 fields).
+
 Beside it: the batched uneven launch (1024 Poisson solves, sides drawn from
 32..1024, one persistent kernel replayed from a HIP graph, FP32 and FP64,
 and the FP64 solves one at a time), and the request server under an open
@@ -95,11 +99,12 @@ def make_inputs(n: int, batch: int, seed: int = 3):
 def run_leg(fp, torch, host_fields, dtype_name: str, steps: int, warmup: int):
     """Time `steps` batched solves; returns a dict of measurements."""
     dev = torch.device("cuda:0")
-    tdt = {"c64": torch.complex64, "c128": torch.complex128}[dtype_name]
-    u0 = torch.from_numpy(host_fields).to(tdt).to(dev)
+    tdt = {"c64": torch.complex64, "c128": torch.complex128, "r32": torch.float32, "r64": torch.float64}[dtype_name]
+    real = dtype_name in ("r32", "r64")
+    u0 = torch.from_numpy(host_fields.real.copy() if real else host_fields).to(tdt).to(dev)
     out = torch.empty_like(u0)
     batch, ny, nx = u0.shape
-    bpp = 8 if dtype_name == "c64" else 16
+    bpp = {"c64": 8, "c128": 16, "r32": 4, "r64": 8}[dtype_name]
     for w in range(warmup):
         fp.solve_wave(u0, None, C_SPEED, (w + 1) * DT, 1.0, 1.0, out=out)
     torch.cuda.synchronize()
@@ -144,7 +149,8 @@ def oracle_check(out_dev, host_field, dtype_name, t):
     import numpy as np
 
     import oracle
-    x = host_field.astype(np.complex64).astype(np.complex128) if dtype_name == "c64" else host_field
+    x = host_field.real.astype(np.complex128) if dtype_name in ("r32", "r64") else host_field
+    x = x.astype(np.complex64).astype(np.complex128) if dtype_name in ("c64", "r32") else x
     ref, _ = oracle.solve_wave(x, None, 1.0, 1.0, C_SPEED, t, threads=oracle.default_threads())
     got = out_dev.cpu().numpy().astype(np.complex128)
     return oracle.rel_l2(got, ref)
@@ -323,6 +329,7 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--batch", type=int, default=16, help="FP32 batch (FP64 uses half)")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-real", action="store_true", help="skip the real-field legs")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-probe", action="store_true",
@@ -365,6 +372,23 @@ def main(argv=None):
         f64 = fields[: max(1, a.batch // 2)]
         r64 = run_leg(fp, torch, f64, "c128", a.steps, a.warmup)
         err64 = None if a.no_check else oracle_check(r64["last_out"][0], f64[0], "c128", r64["last_t"])
+    real = {}
+    if not a.no_real:
+        # the same real-valued initial data as real fields, two per complex
+        # transform: 2B FP32 / B FP64 fields, the complex legs' bytes in flight
+        for name, nb in (("r32", 2 * a.batch), ("r64", a.batch)):
+            print(f"# real {name} leg", file=sys.stderr, flush=True)
+            rf = make_inputs(N_SIDE, nb) if nb > len(fields) else fields[:nb]
+            rr = run_leg(fp, torch, rf, name, a.steps, a.warmup)
+            err = None if a.no_check else oracle_check(rr["last_out"][0], rf[0], name, rr["last_t"])
+            real[name] = {"value": round(rr["solves_per_s"], 2), "unit": "solves/s", "batch": rr["batch"],
+                          "ms_per_step": round(rr["ms_per_step"], 4), "eff_hbm_gbs": round(rr["eff_gbs"], 1),
+                          "eff_hbm_frac": round(rr["eff_gbs"] / HBM_PEAK_GBS, 4), "err_vs_oracle": err,
+                          "err_tol": 1e-12 if name == "r64" else 2 * 2e-6 * math.log2(N_SIDE),
+                          "kernels": [{"kernel": k["kernel"], "launches": k["launches"],
+                                       "avg_us": round(k["avg_us"], 2), "gbs": round(k["gbs"], 1)}
+                                      for k in rr["kernels"]]}
+            del rr
     batch = None
     if not a.no_batch:
         print("# uneven batch leg", file=sys.stderr, flush=True)
@@ -417,6 +441,10 @@ def main(argv=None):
                         "kernels": [{"kernel": k["kernel"], "launches": k["launches"],
                                      "avg_us": round(k["avg_us"], 2), "gbs": round(k["gbs"], 1)}
                                     for k in r64["kernels"]]}
+    if real:
+        line["real_fields"] = {"workload": "the same wave problems with u0 stored as real fields, solved two "
+                                           "per complex transform (S(u1 + i u2) = S(u1) + i S(u2): the symbol "
+                                           "is real and even)", **real}
     if batch:
         line["batch"] = batch
     if serve:

@@ -9,7 +9,8 @@ no GPU is present, calls raise.
 
 Tensors are complex64 (FP32 complex) or complex128 (FP64 complex) on a ROCm
 device, contiguous, shaped [..., ny, nx] with x contiguous; leading
-dimensions form the batch.
+dimensions form the batch.  The solves also take real float32 / float64
+fields (solved two per complex transform, see FFTPDE_R32 in fftpde.h).
 """
 from __future__ import annotations
 
@@ -25,6 +26,7 @@ LIB_PATH = os.path.join(_PKG, "libfftpde.so")
 OK, PENDING = 0, 1
 EINVAL, ENOMEM, EDEVICE, EBUDGET, ENOTFOUND, ECANCELED, ETIMEOUT = -1, -2, -3, -4, -5, -6, -7
 C64, C128 = 0, 1
+R32, R64 = 2, 3
 POISSON, DIFFUSION, WAVE = 0, 1, 2
 
 
@@ -277,16 +279,21 @@ def _torch():
     return torch
 
 
-def _dtype_code(t) -> int:
+def _dtype_code(t, real_ok: bool = False) -> int:
     torch = _torch()
     if t.dtype == torch.complex64:
         return C64
     if t.dtype == torch.complex128:
         return C128
-    raise TypeError(f"expected complex64 or complex128, got {t.dtype}")
+    if real_ok and t.dtype == torch.float32:
+        return R32
+    if real_ok and t.dtype == torch.float64:
+        return R64
+    raise TypeError(f"expected complex64 or complex128{' (or float32 / float64)' if real_ok else ''}, "
+                    f"got {t.dtype}")
 
 
-def _field(t, name: str):
+def _field(t, name: str, real_ok: bool = False):
     torch = _torch()
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a torch.Tensor")
@@ -298,7 +305,7 @@ def _field(t, name: str):
         raise ValueError(f"{name} must be contiguous")
     ny, nx = t.shape[-2], t.shape[-1]
     batch = t.numel() // (nx * ny) if nx * ny else 0
-    return nx, ny, batch, _dtype_code(t)
+    return nx, ny, batch, _dtype_code(t, real_ok)
 
 
 def _like(x, out, name="out"):
@@ -343,7 +350,7 @@ def fft2d_inverse(x, out=None):
 
 def solve_poisson(s, lx: float = 1.0, ly: float = 1.0, out=None):
     """Zero-mean u with lap(u) = s - mean(s) on a periodic lx-by-ly box."""
-    nx, ny, batch, dt = _field(s, "s")
+    nx, ny, batch, dt = _field(s, "s", True)
     out = _like(s, out)
     _check(lib().solve_poisson(context(s.device.index), _ptr(s), _ptr(out), nx, ny, batch,
                                float(lx), float(ly), dt, _stream(s)), "solve_poisson")
@@ -352,7 +359,7 @@ def solve_poisson(s, lx: float = 1.0, ly: float = 1.0, out=None):
 
 def solve_diffusion(u0, kappa: float, t: float, lx: float = 1.0, ly: float = 1.0, out=None):
     """u(t) for u_t = kappa lap(u), u(0) = u0, periodic box, t >= 0."""
-    nx, ny, batch, dt = _field(u0, "u0")
+    nx, ny, batch, dt = _field(u0, "u0", True)
     out = _like(u0, out)
     _check(lib().solve_diffusion(context(u0.device.index), _ptr(u0), _ptr(out), nx, ny, batch,
                                  float(lx), float(ly), float(kappa), float(t), dt, _stream(u0)),
@@ -363,9 +370,9 @@ def solve_diffusion(u0, kappa: float, t: float, lx: float = 1.0, ly: float = 1.0
 def solve_wave(u0, v0=None, c: float = 1.0, t: float = 0.0, lx: float = 1.0, ly: float = 1.0,
                out=None, v_out=None, want_v: bool = False) -> Tuple:
     """(u(t), u_t(t) or None) for u_tt = c^2 lap(u), u(0) = u0, u_t(0) = v0 (None => 0)."""
-    nx, ny, batch, dt = _field(u0, "u0")
+    nx, ny, batch, dt = _field(u0, "u0", True)
     if v0 is not None:
-        if _field(v0, "v0") != (nx, ny, batch, dt) or v0.device != u0.device:
+        if _field(v0, "v0", True) != (nx, ny, batch, dt) or v0.device != u0.device:
             raise ValueError("v0 must match u0")
     out = _like(u0, out)
     if want_v or v_out is not None:

@@ -177,6 +177,8 @@ int fftpde_batch_create(fftpde_ctx* ctx, const fftpde_job* jobs, int njobs, int 
     b->args.step_items[s] = (unsigned)n;
   }
   b->args.tw = fp64 ? static_cast<const void*>(c->tw64) : static_cast<const void*>(c->tw32);
+  for (int l = 0; l <= kBatchMaxLog; l++)
+    for (int r = 0; r < 2; r++) b->args.stw[l][r] = l >= 1 ? c->stage_tw_at[l][3][r] : 0;
   e = hipMemcpy(base + o_jobs, desc.data(), sizeof(BatchJobDesc) * desc.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(base + o_items, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice);

@@ -8,7 +8,8 @@ namespace {
 // Row tile: LINES rows of length 2^LOGN, forward (or inverse by conjugation).
 template <typename T, int LOGN>
 __device__ __forceinline__ void row_tile(const cx<T>* __restrict__ in, cx<T>* out, int nrows, int tile,
-                                         bool inverse, const cx<T>* __restrict__ tw, cx<T>* lds, int tid) {
+                                         bool inverse, const cx<T>* __restrict__ tw, const BatchArgs& a, cx<T>* lds,
+                                         int tid) {
   constexpr int E = BatchCfg<T>::E;
   constexpr int N = 1 << LOGN;
   constexpr int LINES = BatchCfg<T>::kTile / N;
@@ -24,7 +25,7 @@ __device__ __forceinline__ void row_tile(const cx<T>* __restrict__ in, cx<T>* ou
     const cx<T> v = in[((long long)row << LOGN) + n];
     x[i] = {v.re, sgn * v.im};
   });
-  Eng::run(x, lds, tw, tid);
+  Eng::run_stage(x, lds, tw + a.stw[LOGN][0], tid);
   Eng::for_each_output(tid, [&](int i, int line, int n) {
     const int row = row0 + line;
     if (row < nrows) out[((long long)row << LOGN) + n] = {x[i].re, sgn * x[i].im};
@@ -35,7 +36,7 @@ __device__ __forceinline__ void row_tile(const cx<T>* __restrict__ in, cx<T>* ou
 // transform, the real symbol (1/(nx ny) folded in), inverse y transform.
 template <typename T, int LOGN>
 __device__ __forceinline__ void col_tile(cx<T>* data, int lognx, int tile, const SymParams& sym,
-                                         const cx<T>* __restrict__ tw, cx<T>* lds, int tid) {
+                                         const cx<T>* __restrict__ tw, const BatchArgs& a, cx<T>* lds, int tid) {
   constexpr int E = BatchCfg<T>::E;
   constexpr int LOGT = BatchCfg<T>::kLogTile - LOGN;
   constexpr int TT = 1 << LOGT;
@@ -55,7 +56,7 @@ __device__ __forceinline__ void col_tile(cx<T>* data, int lognx, int tile, const
   const cx<T>* src = data + Cl;
   cx<T> x[E];
   Fwd::for_each_input(tid, [&](int i, int, int n) { x[i] = src[(long long)n << lognx]; });
-  Fwd::run(x, lds, tw, tid);
+  Fwd::run_stage(x, lds, tw + a.stw[LOGN][0], tid);
   auto mul = [&](auto tag) {
     constexpr int OP = decltype(tag)::value;
     const Symbol<T, OP> s(sym, Cl);
@@ -70,7 +71,7 @@ __device__ __forceinline__ void col_tile(cx<T>* data, int lognx, int tile, const
     case kSymWave: mul(std::integral_constant<int, kSymWave>()); break;
     default: mul(std::integral_constant<int, kSymScale>()); break;
   }
-  Inv::run(x, lds, tw, tid);
+  Inv::run_stage(x, lds, tw + a.stw[LOGN][1], tid);
   if (C < ncols) {
     cx<T>* dst = data + C;
     Inv::for_each_output(tid, [&](int i, int, int n) { dst[(long long)n << lognx] = conjg(x[i]); });
@@ -79,19 +80,19 @@ __device__ __forceinline__ void col_tile(cx<T>* data, int lognx, int tile, const
 
 template <typename T, int L = kBatchMinLog>
 __device__ __forceinline__ void dispatch_row(int logn, const cx<T>* in, cx<T>* out, int nrows, int tile,
-                                             bool inverse, const cx<T>* tw, cx<T>* lds, int tid) {
+                                             bool inverse, const cx<T>* tw, const BatchArgs& a, cx<T>* lds, int tid) {
   if constexpr (L <= kBatchMaxLog) {
-    if (logn == L) row_tile<T, L>(in, out, nrows, tile, inverse, tw, lds, tid);
-    else dispatch_row<T, L + 1>(logn, in, out, nrows, tile, inverse, tw, lds, tid);
+    if (logn == L) row_tile<T, L>(in, out, nrows, tile, inverse, tw, a, lds, tid);
+    else dispatch_row<T, L + 1>(logn, in, out, nrows, tile, inverse, tw, a, lds, tid);
   }
 }
 
 template <typename T, int L = kBatchMinLog>
 __device__ __forceinline__ void dispatch_col(int logn, cx<T>* data, int lognx, int tile, const SymParams& sym,
-                                             const cx<T>* tw, cx<T>* lds, int tid) {
+                                             const cx<T>* tw, const BatchArgs& a, cx<T>* lds, int tid) {
   if constexpr (L <= kBatchMaxLog) {
-    if (logn == L) col_tile<T, L>(data, lognx, tile, sym, tw, lds, tid);
-    else dispatch_col<T, L + 1>(logn, data, lognx, tile, sym, tw, lds, tid);
+    if (logn == L) col_tile<T, L>(data, lognx, tile, sym, tw, a, lds, tid);
+    else dispatch_col<T, L + 1>(logn, data, lognx, tile, sym, tw, a, lds, tid);
   }
 }
 
@@ -174,10 +175,10 @@ __global__ void __launch_bounds__(kBatchTH) batch_kernel(BatchArgs a) {
     const int lognx = job.sym.lognx, logny = job.sym.logny;
     cx<T>* out = static_cast<cx<T>*>(job.out);
     if (item.step == 1) {
-      dispatch_col<T>(logny, out, lognx, item.tile, job.sym, tw, lds, tid);
+      dispatch_col<T>(logny, out, lognx, item.tile, job.sym, tw, a, lds, tid);
     } else {
       const cx<T>* src = item.step == 0 ? static_cast<const cx<T>*>(job.in) : out;
-      dispatch_row<T>(lognx, src, out, 1 << logny, item.tile, item.step == 2, tw, lds, tid);
+      dispatch_row<T>(lognx, src, out, 1 << logny, item.tile, item.step == 2, tw, a, lds, tid);
     }
     if (item.step < 2) {
       if (tid == 0) s_note[nnote] = 2 * item.job + item.step;

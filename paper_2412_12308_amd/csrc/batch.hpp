@@ -65,6 +65,9 @@ struct BatchArgs {
   int njobs;
   unsigned step_items[2];  // tiles of steps 0 and 1, whole batch
   const void* tw;
+  // entry offsets from tw of the stage tables (Engine::stw_off) of the
+  // radix-8 plans: stw[log2 length][0 forward, 1 reversed]
+  int stw[kBatchMaxLog + 1][2];
 };
 
 hipError_t batch_launch(int fp64, const BatchArgs& a, int grid, hipStream_t s);

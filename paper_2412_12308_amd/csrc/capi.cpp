@@ -82,7 +82,7 @@ int ilog2(int n) {
   return l;
 }
 bool aligned(const void* p, int dtype) {
-  const uintptr_t a = dtype == FFTPDE_C64 ? 8 : 16;
+  const uintptr_t a = dtype == FFTPDE_R32 ? 4 : (dtype == FFTPDE_C64 || dtype == FFTPDE_R64) ? 8 : 16;
   return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0;
 }
 
@@ -216,8 +216,24 @@ int fftpde_create(fftpde_ctx** out, int device) {
     t64[e] = {cs, -sn};
     t32[e] = {(float)cs, (float)(-sn)};
   }
-  hipError_t e1 = hipMalloc(&c->tw64, sizeof(cx<double>) * kTw);
-  hipError_t e2 = hipMalloc(&c->tw32, sizeof(cx<float>) * kTw);
+  // stage tables: copies of table entries, so every twiddle source gives the
+  // same values
+  for (int logn = 1; logn <= 12; logn++)
+    for (int lr = 1; lr <= Context::kStageMaxLr; lr++)
+      for (int rev = 0; rev < 2; rev++) {
+        c->stage_tw_at[logn][lr][rev] = (int)t64.size();
+        const int n = stage_tw_entries(logn, lr, rev != 0);
+        for (int i = 0; i < n; i++) {
+          const int e = stage_tw_exponent(logn, lr, rev != 0, i);
+          const cx<double> w64 = t64[e];
+          const cx<float> w32 = t32[e];
+          t64.push_back(w64);
+          t32.push_back(w32);
+        }
+      }
+  const size_t ntw = t64.size();
+  hipError_t e1 = hipMalloc(&c->tw64, sizeof(cx<double>) * ntw);
+  hipError_t e2 = hipMalloc(&c->tw32, sizeof(cx<float>) * ntw);
   if (e1 != hipSuccess || e2 != hipSuccess) {
     set_error("hipMalloc(twiddles)", e1 != hipSuccess ? e1 : e2);
     if (e1 == hipSuccess) (void)hipFree(c->tw64);
@@ -225,8 +241,8 @@ int fftpde_create(fftpde_ctx** out, int device) {
     delete c;
     return FFTPDE_ENOMEM;
   }
-  e1 = hipMemcpy(c->tw64, t64.data(), sizeof(cx<double>) * kTw, hipMemcpyHostToDevice);
-  e2 = hipMemcpy(c->tw32, t32.data(), sizeof(cx<float>) * kTw, hipMemcpyHostToDevice);
+  e1 = hipMemcpy(c->tw64, t64.data(), sizeof(cx<double>) * ntw, hipMemcpyHostToDevice);
+  e2 = hipMemcpy(c->tw32, t32.data(), sizeof(cx<float>) * ntw, hipMemcpyHostToDevice);
   if (e1 != hipSuccess || e2 != hipSuccess) {
     set_error("hipMemcpy(twiddles)", e1 != hipSuccess ? e1 : e2);
     (void)hipFree(c->tw64);
@@ -438,10 +454,11 @@ int fftpde_destroy(fftpde_ctx* ctx) {
 // ---------------------------------------------------------------------------
 namespace {
 
-int check_common(fftpde_ctx* ctx, int nx, int ny, int batch, int dtype) {
+int check_common(fftpde_ctx* ctx, int nx, int ny, int batch, int dtype, bool real_ok = false) {
   if (!ctx) return FFTPDE_EINVAL;
   if (!pow2_side(nx) || !pow2_side(ny) || batch < 1) return FFTPDE_EINVAL;
-  if (dtype != FFTPDE_C64 && dtype != FFTPDE_C128) return FFTPDE_EINVAL;
+  const bool real = dtype == FFTPDE_R32 || dtype == FFTPDE_R64;
+  if (dtype != FFTPDE_C64 && dtype != FFTPDE_C128 && !(real_ok && real)) return FFTPDE_EINVAL;
   return FFTPDE_OK;
 }
 
@@ -477,7 +494,7 @@ int fft2d_inverse(fftpde_ctx* ctx, const void* in, void* out, int nx, int ny, in
 
 int solve_poisson(fftpde_ctx* ctx, const void* s_in, void* u, int nx, int ny, int batch, double lx, double ly,
                   int dtype, fftpde_stream stream) {
-  int rc = check_common(ctx, nx, ny, batch, dtype);
+  int rc = check_common(ctx, nx, ny, batch, dtype, true);
   if (rc == FFTPDE_OK) rc = check_field(s_in, dtype);
   if (rc == FFTPDE_OK) rc = check_field(u, dtype);
   if (rc == FFTPDE_OK && !(finite_pos(lx) && finite_pos(ly))) rc = FFTPDE_EINVAL;
@@ -490,7 +507,7 @@ int solve_poisson(fftpde_ctx* ctx, const void* s_in, void* u, int nx, int ny, in
 
 int solve_diffusion(fftpde_ctx* ctx, const void* u0, void* u, int nx, int ny, int batch, double lx, double ly,
                     double kappa, double t, int dtype, fftpde_stream stream) {
-  int rc = check_common(ctx, nx, ny, batch, dtype);
+  int rc = check_common(ctx, nx, ny, batch, dtype, true);
   if (rc == FFTPDE_OK) rc = check_field(u0, dtype);
   if (rc == FFTPDE_OK) rc = check_field(u, dtype);
   if (rc == FFTPDE_OK && !(finite_pos(lx) && finite_pos(ly))) rc = FFTPDE_EINVAL;
@@ -505,7 +522,7 @@ int solve_diffusion(fftpde_ctx* ctx, const void* u0, void* u, int nx, int ny, in
 
 int solve_wave(fftpde_ctx* ctx, const void* u0, const void* v0, void* u, void* v, int nx, int ny, int batch,
                double lx, double ly, double c_speed, double t, int dtype, fftpde_stream stream) {
-  int rc = check_common(ctx, nx, ny, batch, dtype);
+  int rc = check_common(ctx, nx, ny, batch, dtype, true);
   if (rc == FFTPDE_OK) rc = check_field(u0, dtype);
   if (rc == FFTPDE_OK) rc = check_field(u, dtype);
   if (rc == FFTPDE_OK && v0) rc = check_field(v0, dtype);

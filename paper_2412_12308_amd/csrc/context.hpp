@@ -24,6 +24,18 @@ struct Context {
   int device = 0;
   cx<float>* tw32 = nullptr;   // exp(-2 pi i e/4096), FP64-generated, rounded once
   cx<double>* tw64 = nullptr;  // the same in FP64
+  // Behind the 4096 entries of both tables: the stage tables of every plan
+  // (log2 length 1..12, max log-radix 1..kStageMaxLr, forward / reversed),
+  // entry offsets stage_tw_at[logn][maxlr][rev] (Engine::stw_off).
+  static constexpr int kStageMaxLr = 5;
+  int stage_tw_at[13][kStageMaxLr + 1][2] = {};
+  template <typename T>
+  const cx<T>* stage_tw(int logn, int maxlr, bool rev) const {
+    if (logn < 1 || logn > 12 || maxlr < 1 || maxlr > kStageMaxLr) return nullptr;
+    const int o = stage_tw_at[logn][maxlr][rev ? 1 : 0];
+    if constexpr (sizeof(T) == 4) return tw32 + o;
+    else return tw64 + o;
+  }
   // Scratch fields for solves that need one, one per stream so that calls on
   // different streams never share it (grown on demand, freed at destroy).
   struct Work {

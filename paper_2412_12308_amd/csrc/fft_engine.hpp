@@ -433,8 +433,41 @@ struct Engine {
   //   TwSrc::regs    all stages' twiddles held in registers (they do not
   //                  depend on the tile, so a persistent workgroup loads them
   //                  once);
-  //   TwSrc::lds     a workgroup copy of w_N^e, e < N, in LDS.
-  enum class TwSrc { global, regs, lds };
+  //   TwSrc::lds     a workgroup copy of w_N^e, e < N, in LDS;
+  //   TwSrc::stage   per-stage tables in global memory (see stage_tw_off),
+  //                  requested one stage ahead like the global table.
+  enum class TwSrc { global, regs, lds, stage };
+
+  // Stage tables: one table per engine plan holding, for every stage S >= 1,
+  // the values w_{Ns R}^{t k} at entry stw_off<S>() + (t - 1) Ns + k
+  // (t = 1 .. R-1, k < Ns): t-major, so for a fixed t the lanes of a wave,
+  // which hold consecutive k, read consecutive entries (one or two cache
+  // lines per load instead of a gather over the 4096-entry table).  The
+  // values are the 4096-entry table's entries (t k) 4096 / (Ns R), so results
+  // are bit-identical to the global table's.
+  template <int S>
+  static constexpr int stw_off() {
+    if constexpr (S <= 1) return 0;
+    else return stw_off<S - 1>() + (((1 << lr<S - 1>()) - 1) << lns<S - 1>());
+  }
+
+  template <int S, class W>
+  __device__ __forceinline__ static void load_tw_stage(W& w, int off, const cx<T>* __restrict__ tws, int tid) {
+    constexpr int LR = lr<S>();
+    constexpr int R = 1 << LR;
+    constexpr int LNS = lns<S>();
+    constexpr int NS = 1 << LNS;
+    if constexpr (NS > 1) {
+#pragma unroll
+      for (int q = 0; q < E / R; q++) {
+        int line, j;
+        Map::split(tid + TH * q, LOGN - LR, line, j);
+        const cx<T>* b = tws + stw_off<S>() + (j & (NS - 1));
+#pragma unroll
+        for (int t = 1; t < R; t++) w[off + q * (R - 1) + t - 1] = b[(t - 1) * NS];
+      }
+    }
+  }
 
   template <int S, class W>
   __device__ __forceinline__ static void load_tw(W& w, int off, const cx<T>* __restrict__ tw, int tid) {
@@ -497,9 +530,10 @@ struct Engine {
       dft<R>(v);
     }
     if constexpr (S + 1 < NST) {
-      if constexpr (SRC == TwSrc::global) {
+      if constexpr (SRC == TwSrc::global || SRC == TwSrc::stage) {
         cx<T> wn[twn<S + 1>() > 0 ? twn<S + 1>() : 1];
-        load_tw<S + 1>(wn, 0, tw, tid);
+        if constexpr (SRC == TwSrc::stage) load_tw_stage<S + 1>(wn, 0, tw, tid);
+        else load_tw<S + 1>(wn, 0, tw, tid);
         exchange<S>(x, lds, tid);
         stage<S + 1, SRC>(x, lds, tw, twl, tid, wn);
       } else {
@@ -517,6 +551,11 @@ struct Engine {
   // Register twiddles from load_all_tw.
   __device__ __forceinline__ static void run_regs(cx<T> (&x)[E], Word* lds, const cx<T> (&w)[kTwRegs], int tid) {
     stage<0, TwSrc::regs>(x, lds, nullptr, nullptr, tid, w);
+  }
+  // Stage-table twiddles (tws: this plan's table, see stw_off).
+  __device__ __forceinline__ static void run_stage(cx<T> (&x)[E], Word* lds, const cx<T>* __restrict__ tws, int tid) {
+    cx<T> w0[1];
+    stage<0, TwSrc::stage>(x, lds, tws, nullptr, tid, w0);
   }
   // LDS table twiddles from load_lds_table.
   __device__ __forceinline__ static void run_lds(cx<T> (&x)[E], Word* lds, const cx<T>* twl, int tid) {
@@ -560,5 +599,27 @@ struct TileWalk {
     return g < end ? g * GROUP : -1;
   }
 };
+
+// Entries of the stage table of the (logn, maxlr, rev) plan (host and
+// device), and the value of each entry as an exponent of w = exp(-2 pi i/4096):
+// entry i of the table is w^stage_tw_exponent(logn, maxlr, rev, i).
+constexpr int stage_tw_entries(int logn, int maxlr, bool rev) {
+  int n = 0;
+  for (int s = 1; s < plan_nstages(logn, maxlr); s++)
+    n += ((1 << plan_lr(logn, maxlr, s, rev)) - 1) << plan_lns(logn, maxlr, s, rev);
+  return n;
+}
+inline int stage_tw_exponent(int logn, int maxlr, bool rev, int i) {
+  for (int s = 1; s < plan_nstages(logn, maxlr); s++) {
+    const int lr = plan_lr(logn, maxlr, s, rev), lns = plan_lns(logn, maxlr, s, rev);
+    const int size = ((1 << lr) - 1) << lns;
+    if (i < size) {
+      const int t = 1 + (i >> lns), k = i & ((1 << lns) - 1);
+      return (t * k) << (kTwLog - lns - lr);
+    }
+    i -= size;
+  }
+  return -1;
+}
 
 }  // namespace fftpde

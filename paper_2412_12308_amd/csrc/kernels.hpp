@@ -36,7 +36,7 @@ enum SymOp : int {
 };
 
 // Where the passes read their twiddles (see Engine::TwSrc).
-enum TwMode : int { kTwGlobal = 0, kTwRegs = 1, kTwLds = 2 };
+enum TwMode : int { kTwGlobal = 0, kTwRegs = 1, kTwLds = 2, kTwStage = 3 };
 
 struct SymParams {
   int op;
@@ -69,6 +69,14 @@ struct RowArgs {
   // within it; t = log2 of the row length is the plain row-major layout.
   int logny;
   int in_t, out_t;
+  // Real fields in pairs (row kernels compiled with REAL): row r of the pass
+  // is row y = r mod ny of real fields 2p and 2p + 1 (p = r / ny), taken as
+  // the real and imaginary parts of one complex row; nreal fields exist
+  // (field 2p + 1 >= nreal reads as zero and is not written).  real_in: the
+  // input is such real fields (row-major, points of type T); real_out: the
+  // output is.  The other side is complex as usual.
+  int real_in, real_out;
+  long long nreal;
 };
 
 template <typename T>
@@ -83,6 +91,10 @@ struct ColArgs {
   int mode;           // ColMode
   SymParams sym;
   int layout_t;       // fields stored in blocks of 2^layout_t >= 2^LOGT columns (see RowArgs); -1 row-major
+  // Stage tables (Engine::stw_off) of the forward and the inverse engine's
+  // plans, for TWM = kTwStage.
+  const cx<T>* twf;
+  const cx<T>* twi;
 };
 
 // a type carried as a value (to pass an engine type to a generic lambda)
@@ -111,6 +123,26 @@ __device__ __forceinline__ double sqrt_fp64_from_fp32(double v) {
   const double r = fma(-d, d, v);
   const double h = fma(r, double(0.5f * __builtin_amdgcn_rcpf(s0)), d);
   return v > 0.0 ? h : 0.0;
+}
+
+// cos(pi r) for |r| <= 1/2 in FP32: the Taylor series of cos about 0 in
+// u = r^2, terms (-1)^k pi^(2k) / (2k)! u^k for k <= 6, evaluated by Horner's
+// rule.  The first omitted term is below (pi/2)^14 / 14! < 7e-9, under FP32
+// rounding of values near 1.
+constexpr double cospi_taylor(int k) {
+  double c = 1.0;
+  for (int i = 1; i <= 2 * k; i++) c *= 3.14159265358979323846264338327950288 / i;
+  return (k & 1) ? -c : c;
+}
+__device__ __forceinline__ float cospi_half(float r) {
+  const float u = r * r;
+  float p = float(cospi_taylor(6));
+  p = fmaf(p, u, float(cospi_taylor(5)));
+  p = fmaf(p, u, float(cospi_taylor(4)));
+  p = fmaf(p, u, float(cospi_taylor(3)));
+  p = fmaf(p, u, float(cospi_taylor(2)));
+  p = fmaf(p, u, float(cospi_taylor(1)));
+  return fmaf(p, u, 1.0f);
 }
 
 template <typename T, int OP>
@@ -184,7 +216,11 @@ struct Symbol<T, kSymWave> {
     if constexpr (sizeof(T) == 4) {
       double h = sqrt_fp64_from_fp32(h2);  // w t / pi
       h = fma(-2.0, rint(0.5 * h), h);     // exact reduction to [-1, 1]
-      return scale * cospif(float(h));
+      // cos(pi h) = (-1)^m cos(pi (h - m)), m = rint(h) in {-1, 0, 1}; h - m
+      // is exact and lies in [-1/2, 1/2]
+      const double m = rint(h);
+      const float c = cospi_half(float(h - m));
+      return (m != 0.0 ? -scale : scale) * c;
     } else {
       return scale * cospi(sqrt(h2));
     }
@@ -246,7 +282,7 @@ struct WaveCoeffs {
 // while the current tile is transformed, so HBM reads continue through the
 // LDS exchanges.
 // ---------------------------------------------------------------------------
-template <typename T, int LOGN, int E, int TH, int MAXLR, bool PF, int TWM>
+template <typename T, int LOGN, int E, int TH, int MAXLR, bool PF, int TWM, bool REAL>
 __global__ void __launch_bounds__(TH) row_kernel(RowArgs<T> a) {
   constexpr int N = 1 << LOGN;
   constexpr int LINES = E * TH / N;
@@ -267,6 +303,14 @@ __global__ void __launch_bounds__(TH) row_kernel(RowArgs<T> a) {
     const long long f = row >> logny, yy = row & ymask;
     return (f << (logny + LOGN)) + ((long long)(n >> t) << (logny + t)) + (yy << t) + (n & ((1 << t) - 1));
   };
+  // real fields of a pair: the first field's point (y, n) of pass row r and
+  // the distance to the second field's
+  const long long field_pts = 1ll << (logny + LOGN);
+  auto real_row = [&](long long row) -> long long {
+    const long long p = row >> logny, yy = row & ymask;
+    return (((2 * p) << logny) + yy) << LOGN;
+  };
+  auto has_second = [&](long long row) { return 2 * (row >> logny) + 1 < a.nreal; };
   // raw loads; the inverse's conjugation is applied when the tile is consumed
   // so that a prefetch never waits for its own data
   auto load = [&](long long tile, cx<T>(&dst)[E]) {
@@ -275,6 +319,13 @@ __global__ void __launch_bounds__(TH) row_kernel(RowArgs<T> a) {
       // clamped, unconditional loads (padding rows reread the last row and are
       // never stored) keep the loads free of branches
       const long long row = min(row0 + line, a.nrows - 1);
+      if constexpr (REAL) {
+        if (a.real_in) {
+          const T* re = reinterpret_cast<const T*>(a.in) + real_row(row) + n;
+          dst[i] = {__builtin_nontemporal_load(re), has_second(row) ? __builtin_nontemporal_load(re + field_pts) : T(0)};
+          return;
+        }
+      }
       dst[i] = load_stream(&a.in[offset(row, n, a.in_t)]);
     });
   };
@@ -300,7 +351,16 @@ __global__ void __launch_bounds__(TH) row_kernel(RowArgs<T> a) {
     const long long row0 = tile * LINES;
     Eng::for_each_output(tid, [&](int i, int line, int n) {
       const long long row = row0 + line;
-      if (row < a.nrows) a.out[offset(row, n, a.out_t)] = {x[i].re * sr, x[i].im * si};
+      if (row >= a.nrows) return;
+      if constexpr (REAL) {
+        if (a.real_out) {
+          T* re = reinterpret_cast<T*>(a.out) + real_row(row) + n;
+          re[0] = x[i].re * sr;
+          if (has_second(row)) re[field_pts] = x[i].im * si;
+          return;
+        }
+      }
+      a.out[offset(row, n, a.out_t)] = {x[i].re * sr, x[i].im * si};
     });
     if (!more) break;
     if constexpr (PF) {
@@ -318,14 +378,16 @@ __global__ void __launch_bounds__(TH) row_kernel(RowArgs<T> a) {
 // are numbered C = field * nx + x over the whole batch.  NF = 2 carries a
 // second field (the wave's velocity) through the pass.  SPLIT exchanges the
 // real and imaginary parts through LDS one after the other (half the LDS, so
-// two workgroups fit per CU at the large sizes); PF prefetches the next tile.
+// two workgroups fit per CU at the large sizes); PF prefetches the next tile;
+// FUSED compiles the [forward, symbol, inverse] mode alone.
 // ---------------------------------------------------------------------------
-template <typename T, int LOGN, int LOGT, int E, int TH, int MAXLR, int NF, bool SPLIT, bool PF, int TWM>
+template <typename T, int LOGN, int LOGT, int E, int TH, int MAXLR, int NF, bool SPLIT, bool PF, int TWM, bool FUSED>
 __global__ void __launch_bounds__(TH) col_kernel(ColArgs<T> a) {
   constexpr int N = 1 << LOGN;
   constexpr int TT = 1 << LOGT;
   static_assert(N * TT == E * TH, "tile must hold whole columns");
-  static_assert(TWM == kTwGlobal || TWM == kTwLds, "column pass twiddles: global table or LDS");
+  static_assert(TWM == kTwGlobal || TWM == kTwLds || TWM == kTwStage,
+                "column pass twiddles: global table, LDS or stage tables");
   // When TH is a multiple of T every thread stays on one column of the tile.
   constexpr bool kOneCol = (TH % TT) == 0;
   using FMap = ColMap<LOGN, LOGT, plan_pad(LOGN, MAXLR, false)>;
@@ -347,7 +409,9 @@ __global__ void __launch_bounds__(TH) col_kernel(ColArgs<T> a) {
   if (walk.first < 0) return;
   const int lognx = a.lognx;
   const long long fmask = (1ll << lognx) - 1;
-  const int mode = a.mode;
+  // FUSED: the solves' pass [forward, symbol, inverse] only; the other modes'
+  // code is left out, which frees registers (one more resident wave per SIMD).
+  const int mode = FUSED ? int(kColFwdMulInv) : a.mode;
   const bool spec_in = mode == kColMulInv;
   const T sgn = mode == kColInverse ? T(-1) : T(1);
   const bool has_in1 = a.in1 != nullptr;
@@ -431,10 +495,12 @@ __global__ void __launch_bounds__(TH) col_kernel(ColArgs<T> a) {
   }
   auto fwd = [&](cx<T>(&v)[E], int t) {
     if constexpr (TWM == kTwLds) Fwd::run_lds(v, lds, twl, t);
+    else if constexpr (TWM == kTwStage) Fwd::run_stage(v, lds, a.twf, t);
     else Fwd::run(v, lds, a.tw, t);
   };
   auto inv = [&](cx<T>(&v)[E], int t) {
     if constexpr (TWM == kTwLds) Inv::run_lds(v, lds, twl, t);
+    else if constexpr (TWM == kTwStage) Inv::run_stage(v, lds, a.twi, t);
     else Inv::run(v, lds, a.tw, t);
   };
   // Multiply by a real symbol and conjugate (for the inverse by conjugation).
@@ -546,6 +612,8 @@ using OccFn = int (*)();
 struct RowVariant {
   LaunchFn launch;
   OccFn occupancy;
+  LaunchFn launch_real;  // the same configuration with real-pair I/O (RowArgs::real_in / real_out)
+  OccFn occupancy_real;
   int logn, e, th, maxlr, lines, pf, twm;
   int lds_bytes;
   const char* name;
@@ -554,46 +622,48 @@ struct RowVariant {
 struct ColVariant {
   LaunchFn launch;
   OccFn occupancy;
+  LaunchFn launch_fused;  // the same configuration compiled for kColFwdMulInv only
+  OccFn occupancy_fused;
   int logn, logt, e, th, maxlr, nf, split, pf, twm;
   int lds_bytes;
   const char* name;
 };
 
-template <typename T, int LOGN, int E, int TH, int MAXLR, bool PF, int TWM>
+template <typename T, int LOGN, int E, int TH, int MAXLR, bool PF, int TWM, bool REAL>
 hipError_t launch_row(const void* args, long long nrows, long long max_blocks, hipStream_t s) {
   constexpr int LINES = E * TH / (1 << LOGN);
   long long grid = (nrows + LINES - 1) / LINES;
   if (max_blocks > 0 && grid > max_blocks) grid = max_blocks;
   if (grid <= 0 || grid > 0x7fffffffll) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((row_kernel<T, LOGN, E, TH, MAXLR, PF, TWM>), dim3((unsigned)grid), dim3(TH), 0, s,
+  hipLaunchKernelGGL((row_kernel<T, LOGN, E, TH, MAXLR, PF, TWM, REAL>), dim3((unsigned)grid), dim3(TH), 0, s,
                      *static_cast<const RowArgs<T>*>(args));
   return hipGetLastError();
 }
 
-template <typename T, int LOGN, int E, int TH, int MAXLR, bool PF, int TWM>
+template <typename T, int LOGN, int E, int TH, int MAXLR, bool PF, int TWM, bool REAL>
 int occ_row() {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, row_kernel<T, LOGN, E, TH, MAXLR, PF, TWM>, TH, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, row_kernel<T, LOGN, E, TH, MAXLR, PF, TWM, REAL>, TH, 0) !=
       hipSuccess)
     return 0;
   return n;
 }
 
-template <typename T, int LOGN, int LOGT, int E, int TH, int MAXLR, int NF, bool SPLIT, bool PF, int TWM>
+template <typename T, int LOGN, int LOGT, int E, int TH, int MAXLR, int NF, bool SPLIT, bool PF, int TWM, bool FUSED>
 hipError_t launch_col(const void* args, long long ncols, long long max_blocks, hipStream_t s) {
   long long grid = (ncols + (1 << LOGT) - 1) >> LOGT;
   if (max_blocks > 0 && grid > max_blocks) grid = max_blocks;
   if (grid <= 0 || grid > 0x7fffffffll) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((col_kernel<T, LOGN, LOGT, E, TH, MAXLR, NF, SPLIT, PF, TWM>), dim3((unsigned)grid), dim3(TH), 0,
-                     s, *static_cast<const ColArgs<T>*>(args));
+  hipLaunchKernelGGL((col_kernel<T, LOGN, LOGT, E, TH, MAXLR, NF, SPLIT, PF, TWM, FUSED>), dim3((unsigned)grid),
+                     dim3(TH), 0, s, *static_cast<const ColArgs<T>*>(args));
   return hipGetLastError();
 }
 
-template <typename T, int LOGN, int LOGT, int E, int TH, int MAXLR, int NF, bool SPLIT, bool PF, int TWM>
+template <typename T, int LOGN, int LOGT, int E, int TH, int MAXLR, int NF, bool SPLIT, bool PF, int TWM, bool FUSED>
 int occ_col() {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, col_kernel<T, LOGN, LOGT, E, TH, MAXLR, NF, SPLIT, PF, TWM>, TH,
-                                                   0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &n, col_kernel<T, LOGN, LOGT, E, TH, MAXLR, NF, SPLIT, PF, TWM, FUSED>, TH, 0) != hipSuccess)
     return 0;
   return n;
 }
@@ -610,15 +680,19 @@ constexpr int lds_elems_col(int logt) {
 }
 
 #define FFTPDE_ROW_VARIANT(T, LOGN, E, TH, MAXLR, PF, TWM)                                     \
-  {&::fftpde::launch_row<T, LOGN, E, TH, MAXLR, PF, TWM>,                                      \
-   &::fftpde::occ_row<T, LOGN, E, TH, MAXLR, PF, TWM>,                                         \
+  {&::fftpde::launch_row<T, LOGN, E, TH, MAXLR, PF, TWM, false>,                               \
+   &::fftpde::occ_row<T, LOGN, E, TH, MAXLR, PF, TWM, false>,                                  \
+   &::fftpde::launch_row<T, LOGN, E, TH, MAXLR, PF, TWM, true>,                                \
+   &::fftpde::occ_row<T, LOGN, E, TH, MAXLR, PF, TWM, true>,                                   \
    LOGN, E, TH, MAXLR, (E) * (TH) >> (LOGN), PF, TWM,                                          \
    int(::fftpde::lds_elems_row<LOGN, MAXLR>((E) * (TH) >> (LOGN)) * sizeof(::fftpde::cx<T>)), \
    "row_" #T "_n" #LOGN "_e" #E "_th" #TH "_r" #MAXLR "_pf" #PF "_tw" #TWM}
 
 #define FFTPDE_COL_VARIANT(T, LOGN, LOGT, E, TH, MAXLR, NF, SPLIT, PF, TWM)                           \
-  {&::fftpde::launch_col<T, LOGN, LOGT, E, TH, MAXLR, NF, SPLIT, PF, TWM>,                            \
-   &::fftpde::occ_col<T, LOGN, LOGT, E, TH, MAXLR, NF, SPLIT, PF, TWM>,                               \
+  {&::fftpde::launch_col<T, LOGN, LOGT, E, TH, MAXLR, NF, SPLIT, PF, TWM, false>,                     \
+   &::fftpde::occ_col<T, LOGN, LOGT, E, TH, MAXLR, NF, SPLIT, PF, TWM, false>,                        \
+   &::fftpde::launch_col<T, LOGN, LOGT, E, TH, MAXLR, NF, SPLIT, PF, TWM, true>,                      \
+   &::fftpde::occ_col<T, LOGN, LOGT, E, TH, MAXLR, NF, SPLIT, PF, TWM, true>,                         \
    LOGN, LOGT, E, TH, MAXLR, NF, SPLIT, PF, TWM,                                                      \
    int(::fftpde::lds_elems_col<LOGN, MAXLR>(LOGT) * ((SPLIT) ? sizeof(T) : sizeof(::fftpde::cx<T>)) + \
        ((TWM) == 2 ? (1 << (LOGN)) * sizeof(::fftpde::cx<T>) : 0)),                                  \

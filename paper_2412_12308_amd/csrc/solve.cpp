@@ -31,14 +31,17 @@ static const cx<T>* twiddles(const Context* c) {
 
 template <typename T>
 int row_pass(Context* c, const void* in, void* out, int lognx, int logny, long long nrows, bool inverse,
-             double scale, hipStream_t s, int in_t, int out_t) {
+             double scale, hipStream_t s, int in_t, int out_t, int real_in, int real_out, long long nreal) {
   const RowVariant* v = c->row_variant(sizeof(T) == 4 ? FFTPDE_C64 : FFTPDE_C128, lognx);
   if (!v) return FFTPDE_EINVAL;
   RowArgs<T> a{static_cast<const cx<T>*>(in), static_cast<cx<T>*>(out), twiddles<T>(c), nrows, inverse ? 1 : 0,
-               T(scale), logny, in_t < 0 ? lognx : in_t, out_t < 0 ? lognx : out_t};
+               T(scale), logny, in_t < 0 ? lognx : in_t, out_t < 0 ? lognx : out_t, real_in, real_out, nreal};
   const double bytes = 2.0 * sizeof(cx<T>) * (double)nrows * (double)(1 << lognx);
-  const long long maxb = v->pf ? c->max_blocks(v, v->occupancy) : 0;
-  hipError_t e = timed_launch(c, v->name, bytes, s, [&] { return v->launch(&a, nrows, maxb, s); });
+  const bool real = real_in || real_out;
+  const LaunchFn launch = real ? v->launch_real : v->launch;
+  const OccFn occ = real ? v->occupancy_real : v->occupancy;
+  const long long maxb = v->pf ? c->max_blocks(reinterpret_cast<const void*>(occ), occ) : 0;
+  hipError_t e = timed_launch(c, v->name, bytes, s, [&] { return launch(&a, nrows, maxb, s); });
   if (e != hipSuccess) {
     set_last_error(v->name, e);
     return FFTPDE_EDEVICE;
@@ -54,11 +57,16 @@ int col_pass(Context* c, const void* in0, const void* in1, void* out0, void* out
   // a block holds whole tiles and never spans fields
   if (layout_t >= 0 && (layout_t < v->logt || layout_t > lognx)) return FFTPDE_EINVAL;
   ColArgs<T> a{static_cast<const cx<T>*>(in0), static_cast<const cx<T>*>(in1), static_cast<cx<T>*>(out0),
-               static_cast<cx<T>*>(out1), twiddles<T>(c), batch << lognx, lognx, mode, sym, layout_t};
+               static_cast<cx<T>*>(out1), twiddles<T>(c), batch << lognx, lognx, mode, sym, layout_t,
+               c->stage_tw<T>(logny, v->maxlr, false), c->stage_tw<T>(logny, v->maxlr, true)};
   const double field = sizeof(cx<T>) * (double)batch * (double)(1ll << (lognx + logny));
   const double bytes = field * ((in0 ? 1 : 0) + (in1 ? 1 : 0) + (out0 ? 1 : 0) + (out1 ? 1 : 0));
-  const long long maxb = v->pf ? c->max_blocks(v, v->occupancy) : 0;
-  hipError_t e = timed_launch(c, v->name, bytes, s, [&] { return v->launch(&a, batch << lognx, maxb, s); });
+  // the [forward, symbol, inverse] pass runs the kernel compiled for it alone
+  const bool fused = mode == kColFwdMulInv;
+  const LaunchFn launch = fused ? v->launch_fused : v->launch;
+  const OccFn occ = fused ? v->occupancy_fused : v->occupancy;
+  const long long maxb = v->pf ? c->max_blocks(reinterpret_cast<const void*>(occ), occ) : 0;
+  hipError_t e = timed_launch(c, v->name, bytes, s, [&] { return launch(&a, batch << lognx, maxb, s); });
   if (e != hipSuccess) {
     set_last_error(v->name, e);
     return FFTPDE_EDEVICE;
@@ -216,6 +224,61 @@ int small_pass(Context* c, const void* in, void* out, int nx, int ny, int batch,
   return FFTPDE_OK;
 }
 
+// Real fields, two per complex transform.  The three symbols are real and
+// even in k, so a solve S maps real fields to real fields and is complex
+// linear: S(u1 + i u2) = S(u1) + i S(u2).  Fields 2p and 2p + 1 enter the
+// forward row pass as the real and imaginary parts of one complex field and
+// leave the inverse row pass the same way; nothing else changes, and each
+// real field moves half the bytes of a complex one.  The pair's spectra live
+// in the context's per-stream scratch (tiled like solve_real_symbol's when
+// there is no velocity field).
+template <typename T>
+int solve_real_pairs(Context* c, const void* in, const void* in2, void* out, void* out2, int nx, int ny, int batch,
+                     const SymParams& sym, hipStream_t s) {
+  const int dt = sizeof(T) == 4 ? FFTPDE_C64 : FFTPDE_C128;
+  const int lx = ilog2(nx), ly = ilog2(ny);
+  const long long pts = (long long)nx * ny;
+  const size_t pair_bytes = sizeof(cx<T>) * (size_t)pts;  // one complex field per pair
+  const long long npairs = (batch + 1) / 2;
+  const long long cb = c->chunk_bytes_for(dt, lx, ly);
+  long long chunk = cb > 0 ? std::max<long long>(1, cb / (long long)pair_bytes) : npairs;
+  chunk = std::min<long long>(chunk, npairs);
+  const int nf = (sym.op == kSymWave && (in2 || out2)) ? 2 : 1;
+  const ColVariant* cv = c->col_variant(dt, ly, nf);
+  if (!cv) return FFTPDE_EINVAL;
+  int lt = -1;
+  const int tiled_bytes = c->tiled_bytes_for(dt, lx, ly);
+  if (nf == 1 && tiled_bytes > 0) {
+    int bt = 0;
+    while ((int)sizeof(cx<T>) << (bt + 1) <= tiled_bytes) bt++;
+    lt = bt > cv->logt ? bt : cv->logt;
+    if (lt >= lx) lt = -1;
+  }
+  void* w = nullptr;
+  const int rcw = c->workspace(pair_bytes * (size_t)chunk * nf, s, &w);
+  if (rcw != FFTPDE_OK) return rcw;
+  void* mid = w;
+  void* mid2 = nf == 2 ? static_cast<char*>(w) + pair_bytes * (size_t)chunk : nullptr;
+  for (long long p0 = 0; p0 < npairs; p0 += chunk) {
+    const long long np = std::min<long long>(chunk, npairs - p0);
+    const long long nrows = (long long)ny * np;
+    const long long f0 = 2 * p0, nreal = std::min<long long>(2 * np, batch - f0);
+    const size_t off = sizeof(T) * (size_t)(f0 * pts);
+    int rc = row_pass<T>(c, at<T>(in, off), mid, lx, ly, nrows, false, 1.0, s, -1, lt, 1, 0, nreal);
+    if (rc == FFTPDE_OK && nf == 2) {
+      if (in2) rc = row_pass<T>(c, at<T>(in2, off), mid2, lx, ly, nrows, false, 1.0, s, -1, -1, 1, 0, nreal);
+    }
+    if (rc == FFTPDE_OK)
+      rc = col_pass<T>(c, mid, nf == 2 && in2 ? mid2 : nullptr, mid, nf == 2 && out2 ? mid2 : nullptr, lx, ly, np,
+                       kColFwdMulInv, sym, nf, s, lt);
+    if (rc == FFTPDE_OK) rc = row_pass<T>(c, mid, at<T>(out, off), lx, ly, nrows, true, 1.0, s, lt, -1, 0, 1, nreal);
+    if (rc == FFTPDE_OK && out2)
+      rc = row_pass<T>(c, mid2, at<T>(out2, off), lx, ly, nrows, true, 1.0, s, -1, -1, 0, 1, nreal);
+    if (rc != FFTPDE_OK) return rc;
+  }
+  return FFTPDE_OK;
+}
+
 int run_transform(Context* c, int dtype, bool inverse, const void* in, void* out, int nx, int ny, int batch,
                   hipStream_t s) {
   const SymParams sym = make_sym(kSymScale, nx, ny, 1.0, 1.0, 0.0, 0.0);
@@ -231,6 +294,8 @@ int run_solve(Context* c, int dtype, int op, const void* in, const void* in2, vo
               int batch, double lx, double ly, double coef, double t, hipStream_t s) {
   const int sop = op == FFTPDE_POISSON ? kSymPoisson : op == FFTPDE_DIFFUSION ? kSymDiffusion : kSymWave;
   const SymParams sym = make_sym(sop, nx, ny, lx, ly, coef, t);
+  if (dtype == FFTPDE_R32) return solve_real_pairs<float>(c, in, in2, out, out2, nx, ny, batch, sym, s);
+  if (dtype == FFTPDE_R64) return solve_real_pairs<double>(c, in, in2, out, out2, nx, ny, batch, sym, s);
   if (op != FFTPDE_WAVE || (!in2 && !out2)) {
     const int r = dtype == FFTPDE_C64 ? small_pass<float>(c, in, out, nx, ny, batch, kColFwdMulInv, sym, s)
                                       : small_pass<double>(c, in, out, nx, ny, batch, kColFwdMulInv, sym, s);
@@ -288,9 +353,10 @@ int run_diag(Context* c, int dtype, int kind, const void* F, const void* G, int 
   return FFTPDE_OK;
 }
 
-template int row_pass<float>(Context*, const void*, void*, int, int, long long, bool, double, hipStream_t, int, int);
+template int row_pass<float>(Context*, const void*, void*, int, int, long long, bool, double, hipStream_t, int, int,
+                             int, int, long long);
 template int row_pass<double>(Context*, const void*, void*, int, int, long long, bool, double, hipStream_t, int,
-                              int);
+                              int, int, int, long long);
 template int col_pass<float>(Context*, const void*, const void*, void*, void*, int, int, long long, int,
                              const SymParams&, int, hipStream_t, int);
 template int col_pass<double>(Context*, const void*, const void*, void*, void*, int, int, long long, int,

@@ -27,9 +27,12 @@ SymParams make_sym(int op, int nx, int ny, double lx, double ly, double coef, do
 // One row pass over nrows = batch * 2^logny rows of length 2^lognx (forward,
 // or inverse by conjugation with `scale`).  in_t / out_t: log2 of the column
 // block width of the input / output layout (see RowArgs), -1 = row-major.
+// real_in / real_out: that side holds nreal real fields, read or written in
+// pairs (row r of the pass = row r mod ny of fields 2p, 2p + 1, p = r / ny).
 template <typename T>
 int row_pass(Context* c, const void* in, void* out, int lognx, int logny, long long nrows, bool inverse,
-             double scale, hipStream_t s, int in_t = -1, int out_t = -1);
+             double scale, hipStream_t s, int in_t = -1, int out_t = -1, int real_in = 0, int real_out = 0,
+             long long nreal = 0);
 
 // One column pass over `batch` fields of 2^lognx columns of length 2^logny;
 // layout_t >= 0: the fields are stored in blocks of 2^layout_t columns

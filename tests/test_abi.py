@@ -65,13 +65,29 @@ P = (ctypes.cast(BUF, ctypes.c_void_p).value + 15) // 16 * 16  # 16-byte aligned
 
 @pytest.mark.parametrize("nx,ny,batch,dtype", [
     (3, 4, 1, 0), (4, 6, 1, 0), (1, 4, 1, 0), (4, 1, 1, 1), (8192, 4, 1, 0), (4, 8192, 1, 1),
-    (0, 4, 1, 0), (-4, 4, 1, 0), (4, 4, 0, 0), (4, 4, -1, 1), (4, 4, 1, 2), (4, 4, 1, -1),
+    (0, 4, 1, 0), (-4, 4, 1, 0), (4, 4, 0, 0), (4, 4, -1, 1), (4, 4, 1, 4), (4, 4, 1, -1), (4, 6, 1, 2),
 ])
 def test_transforms_reject_bad_shape_or_dtype(nx, ny, batch, dtype):
     fp, L = _lib()
     assert L.fft2d_forward(DUMMY, P, P, nx, ny, batch, dtype, None) == fp.EINVAL
     assert L.fft2d_inverse(DUMMY, P, P, nx, ny, batch, dtype, None) == fp.EINVAL
     assert L.solve_poisson(DUMMY, P, P, nx, ny, batch, 1.0, 1.0, dtype, None) == fp.EINVAL
+
+
+@pytest.mark.parametrize("dtype", [2, 3])
+def test_transforms_take_complex_fields_only(dtype):
+    """Real dtypes (FFTPDE_R32 / R64) are for the solves; the 2D transforms
+    reject them before touching the context."""
+    fp, L = _lib()
+    assert (fp.R32, fp.R64) == (2, 3)
+    assert L.fft2d_forward(DUMMY, P, P, 4, 4, 1, dtype, None) == fp.EINVAL
+    assert L.fft2d_inverse(DUMMY, P, P, 4, 4, 1, dtype, None) == fp.EINVAL
+
+
+def test_real_fields_need_their_own_alignment():
+    fp, L = _lib()
+    assert L.solve_poisson(DUMMY, P + 2, P, 4, 4, 1, 1.0, 1.0, 2, None) == fp.EINVAL  # FP32 needs 4 B
+    assert L.solve_poisson(DUMMY, P + 4, P, 4, 4, 1, 1.0, 1.0, 3, None) == fp.EINVAL  # FP64 needs 8 B
 
 
 def test_null_context_and_null_or_misaligned_pointers():
