@@ -69,13 +69,12 @@ struct RowArgs {
   // within it; t = log2 of the row length is the plain row-major layout.
   int logny;
   int in_t, out_t;
-  // Real fields in pairs (row kernels compiled with REAL): row r of the pass
-  // is row y = r mod ny of real fields 2p and 2p + 1 (p = r / ny), taken as
-  // the real and imaginary parts of one complex row; nreal fields exist
-  // (field 2p + 1 >= nreal reads as zero and is not written).  real_in: the
-  // input is such real fields (row-major, points of type T); real_out: the
-  // output is.  The other side is complex as usual.
-  int real_in, real_out;
+  // Real fields in pairs (row kernels compiled with RIO = 1: real input,
+  // RIO = 2: real output; the other side is complex as usual): row r of the
+  // pass is row y = r mod ny of real fields 2p and 2p + 1 (p = r / ny),
+  // row-major points of type T, taken as the real and imaginary parts of one
+  // complex row.  nreal fields exist: field 2p + 1 >= nreal reads as zero and
+  // is not written.
   long long nreal;
 };
 
@@ -282,7 +281,17 @@ struct WaveCoeffs {
 // while the current tile is transformed, so HBM reads continue through the
 // LDS exchanges.
 // ---------------------------------------------------------------------------
-template <typename T, int LOGN, int E, int TH, int MAXLR, bool PF, int TWM, bool REAL>
+// 16-byte (or narrower, for rows shorter than that) vectors of real points.
+template <typename T, int VEC>
+struct RealVec {
+  typedef T type __attribute__((ext_vector_type(VEC)));
+};
+
+// RIO = 0: complex rows in and out.  RIO = 1: the input is real fields in
+// pairs (RowArgs::real_in), RIO = 2: the output is (RowArgs::real_out).  Real
+// rows move as whole 16-byte vectors, staged through the LDS buffer between
+// their row-major order and the engine's first-stage (or last-stage) order.
+template <typename T, int LOGN, int E, int TH, int MAXLR, bool PF, int TWM, int RIO>
 __global__ void __launch_bounds__(TH) row_kernel(RowArgs<T> a) {
   constexpr int N = 1 << LOGN;
   constexpr int LINES = E * TH / N;
@@ -290,7 +299,9 @@ __global__ void __launch_bounds__(TH) row_kernel(RowArgs<T> a) {
   static_assert(TWM == kTwGlobal || TWM == kTwRegs, "row pass twiddles: global table or registers");
   using Map = RowMap<LOGN, LINES, plan_pad(LOGN, MAXLR, false)>;
   using Eng = Engine<T, LOGN, E, TH, MAXLR, false, Map, false>;
-  __shared__ typename Eng::Word lds[Eng::kLdsWords];
+  // real rows are staged through LDS even when the transform needs no exchange
+  constexpr int kLds = (RIO != 0 && Map::kLdsElems > Eng::kLdsWords) ? Map::kLdsElems : Eng::kLdsWords;
+  __shared__ typename Eng::Word lds[kLds];
 
   int tid = threadIdx.x;
   const long long ntiles = (a.nrows + LINES - 1) / LINES;
@@ -303,14 +314,6 @@ __global__ void __launch_bounds__(TH) row_kernel(RowArgs<T> a) {
     const long long f = row >> logny, yy = row & ymask;
     return (f << (logny + LOGN)) + ((long long)(n >> t) << (logny + t)) + (yy << t) + (n & ((1 << t) - 1));
   };
-  // real fields of a pair: the first field's point (y, n) of pass row r and
-  // the distance to the second field's
-  const long long field_pts = 1ll << (logny + LOGN);
-  auto real_row = [&](long long row) -> long long {
-    const long long p = row >> logny, yy = row & ymask;
-    return (((2 * p) << logny) + yy) << LOGN;
-  };
-  auto has_second = [&](long long row) { return 2 * (row >> logny) + 1 < a.nreal; };
   // raw loads; the inverse's conjugation is applied when the tile is consumed
   // so that a prefetch never waits for its own data
   auto load = [&](long long tile, cx<T>(&dst)[E]) {
@@ -319,29 +322,98 @@ __global__ void __launch_bounds__(TH) row_kernel(RowArgs<T> a) {
       // clamped, unconditional loads (padding rows reread the last row and are
       // never stored) keep the loads free of branches
       const long long row = min(row0 + line, a.nrows - 1);
-      if constexpr (REAL) {
-        if (a.real_in) {
-          const T* re = reinterpret_cast<const T*>(a.in) + real_row(row) + n;
-          dst[i] = {__builtin_nontemporal_load(re), has_second(row) ? __builtin_nontemporal_load(re + field_pts) : T(0)};
-          return;
-        }
-      }
       dst[i] = load_stream(&a.in[offset(row, n, a.in_t)]);
     });
   };
+
+  // Real pairs: pass row r is row y = r mod ny of real fields 2p and 2p + 1
+  // (p = r / ny); each thread moves KV vectors of VEC points per field.
+  constexpr int VEC = (16 / (int)sizeof(T)) < N ? 16 / (int)sizeof(T) : N;
+  using RV = typename RealVec<T, VEC>::type;
+  constexpr int VROW = N / VEC;
+  constexpr int KV = LINES * VROW / TH;
+  static_assert(RIO == 0 || (KV >= 1 && KV * TH == LINES * VROW), "real rows: whole vectors per thread");
+  const long long field_pts = 1ll << (logny + LOGN);
+  auto real_row = [&](long long row) -> long long {
+    const long long p = row >> logny, yy = row & ymask;
+    return (((2 * p) << logny) + yy) << LOGN;
+  };
+  auto has_second = [&](long long row) { return 2 * (row >> logny) + 1 < a.nreal; };
+  RV rv[RIO == 1 ? 2 * KV : 1];
+  // loads of a tile's real rows (padding rows reread the last row); a missing
+  // second field reads the first field's row and is replaced by zeros
+  auto rload = [&](long long tile) {
+    const T* in = reinterpret_cast<const T*>(a.in);
+#pragma unroll
+    for (int k = 0; k < KV; k++) {
+      const int f = tid + TH * k, line = f / VROW, n0 = (f % VROW) * VEC;
+      const long long row = min(tile * LINES + line, a.nrows - 1);
+      const bool two = has_second(row);
+      const T* re = in + real_row(row) + n0;
+      const RV u = __builtin_nontemporal_load(reinterpret_cast<const RV*>(re));
+      const RV v = __builtin_nontemporal_load(reinterpret_cast<const RV*>(two ? re + field_pts : re));
+      rv[k] = u;
+      rv[KV + k] = two ? v : RV(T(0));
+    }
+  };
+  // the loaded real rows into the engine's input order
+  auto rstage_in = [&](cx<T>(&dst)[E]) {
+#pragma unroll
+    for (int k = 0; k < KV; k++) {
+      const int f = tid + TH * k, line = f / VROW, n0 = (f % VROW) * VEC;
+#pragma unroll
+      for (int j = 0; j < VEC; j++) lds[Map::lds(line, n0 + j)] = cx<T>{rv[k][j], rv[KV + k][j]};
+    }
+    lds_barrier();
+    Eng::for_each_input(tid, [&](int i, int line, int n) { dst[i] = lds[Map::lds(line, n)]; });
+    lds_barrier();
+  };
+  // the last stage's outputs back to real rows: real parts to field 2p,
+  // imaginary parts to field 2p + 1
+  auto rstore = [&](long long tile, const cx<T>(&src)[E], T sr, T si) {
+    Eng::for_each_output(tid, [&](int i, int line, int n) { lds[Map::lds(line, n)] = src[i]; });
+    lds_barrier();
+    T* out = reinterpret_cast<T*>(a.out);
+#pragma unroll
+    for (int k = 0; k < KV; k++) {
+      const int f = tid + TH * k, line = f / VROW, n0 = (f % VROW) * VEC;
+      const long long row = tile * LINES + line;
+      RV u, v;
+#pragma unroll
+      for (int j = 0; j < VEC; j++) {
+        const cx<T> w = lds[Map::lds(line, n0 + j)];
+        u[j] = w.re * sr;
+        v[j] = w.im * si;
+      }
+      if (row < a.nrows) {
+        T* re = out + real_row(row) + n0;
+        *reinterpret_cast<RV*>(re) = u;
+        if (has_second(row)) *reinterpret_cast<RV*>(re + field_pts) = v;
+      }
+    }
+    lds_barrier();
+  };
+
   cx<T> wall[TWM == kTwRegs ? Eng::kTwRegs : 1];
   if constexpr (TWM == kTwRegs) Eng::load_all_tw(wall, a.tw, tid);
   const T sgn = a.inverse ? T(-1) : T(1);
   const T sr = a.scale, si = sgn * a.scale;
   cx<T> x[E];
-  cx<T> nxt[PF ? E : 1];
+  cx<T> nxt[(PF && RIO != 1) ? E : 1];
   long long tile = walk.first;
-  load(tile, x);
+  if constexpr (RIO == 1) rload(tile);
+  else load(tile, x);
   while (true) {
     tid = opaque(tid);
     const long long nt = walk.next(tile);
     const bool more = nt >= 0;
-    if constexpr (PF) {
+    if constexpr (RIO == 1) {
+      rstage_in(x);
+      // the vector registers are free again: the next tile's rows go there
+      if constexpr (PF) {
+        if (more) rload(nt);
+      }
+    } else if constexpr (PF) {
       if (more) load(nt, nxt);
     }
 #pragma unroll
@@ -349,21 +421,18 @@ __global__ void __launch_bounds__(TH) row_kernel(RowArgs<T> a) {
     if constexpr (TWM == kTwRegs) Eng::run_regs(x, lds, wall, tid);
     else Eng::run(x, lds, a.tw, tid);
     const long long row0 = tile * LINES;
-    Eng::for_each_output(tid, [&](int i, int line, int n) {
-      const long long row = row0 + line;
-      if (row >= a.nrows) return;
-      if constexpr (REAL) {
-        if (a.real_out) {
-          T* re = reinterpret_cast<T*>(a.out) + real_row(row) + n;
-          re[0] = x[i].re * sr;
-          if (has_second(row)) re[field_pts] = x[i].im * si;
-          return;
-        }
-      }
-      a.out[offset(row, n, a.out_t)] = {x[i].re * sr, x[i].im * si};
-    });
+    if constexpr (RIO == 2) {
+      rstore(tile, x, sr, si);
+    } else {
+      Eng::for_each_output(tid, [&](int i, int line, int n) {
+        const long long row = row0 + line;
+        if (row < a.nrows) a.out[offset(row, n, a.out_t)] = {x[i].re * sr, x[i].im * si};
+      });
+    }
     if (!more) break;
-    if constexpr (PF) {
+    if constexpr (RIO == 1) {
+      if constexpr (!PF) rload(nt);
+    } else if constexpr (PF) {
 #pragma unroll
       for (int i = 0; i < E; i++) x[i] = nxt[i];
     } else {
@@ -612,8 +681,11 @@ using OccFn = int (*)();
 struct RowVariant {
   LaunchFn launch;
   OccFn occupancy;
-  LaunchFn launch_real;  // the same configuration with real-pair I/O (RowArgs::real_in / real_out)
-  OccFn occupancy_real;
+  // the same configuration with real-pair input (forward) / output (inverse)
+  LaunchFn launch_rin;
+  OccFn occupancy_rin;
+  LaunchFn launch_rout;
+  OccFn occupancy_rout;
   int logn, e, th, maxlr, lines, pf, twm;
   int lds_bytes;
   const char* name;
@@ -629,21 +701,21 @@ struct ColVariant {
   const char* name;
 };
 
-template <typename T, int LOGN, int E, int TH, int MAXLR, bool PF, int TWM, bool REAL>
+template <typename T, int LOGN, int E, int TH, int MAXLR, bool PF, int TWM, int RIO>
 hipError_t launch_row(const void* args, long long nrows, long long max_blocks, hipStream_t s) {
   constexpr int LINES = E * TH / (1 << LOGN);
   long long grid = (nrows + LINES - 1) / LINES;
   if (max_blocks > 0 && grid > max_blocks) grid = max_blocks;
   if (grid <= 0 || grid > 0x7fffffffll) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((row_kernel<T, LOGN, E, TH, MAXLR, PF, TWM, REAL>), dim3((unsigned)grid), dim3(TH), 0, s,
+  hipLaunchKernelGGL((row_kernel<T, LOGN, E, TH, MAXLR, PF, TWM, RIO>), dim3((unsigned)grid), dim3(TH), 0, s,
                      *static_cast<const RowArgs<T>*>(args));
   return hipGetLastError();
 }
 
-template <typename T, int LOGN, int E, int TH, int MAXLR, bool PF, int TWM, bool REAL>
+template <typename T, int LOGN, int E, int TH, int MAXLR, bool PF, int TWM, int RIO>
 int occ_row() {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, row_kernel<T, LOGN, E, TH, MAXLR, PF, TWM, REAL>, TH, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, row_kernel<T, LOGN, E, TH, MAXLR, PF, TWM, RIO>, TH, 0) !=
       hipSuccess)
     return 0;
   return n;
@@ -680,10 +752,12 @@ constexpr int lds_elems_col(int logt) {
 }
 
 #define FFTPDE_ROW_VARIANT(T, LOGN, E, TH, MAXLR, PF, TWM)                                     \
-  {&::fftpde::launch_row<T, LOGN, E, TH, MAXLR, PF, TWM, false>,                               \
-   &::fftpde::occ_row<T, LOGN, E, TH, MAXLR, PF, TWM, false>,                                  \
-   &::fftpde::launch_row<T, LOGN, E, TH, MAXLR, PF, TWM, true>,                                \
-   &::fftpde::occ_row<T, LOGN, E, TH, MAXLR, PF, TWM, true>,                                   \
+  {&::fftpde::launch_row<T, LOGN, E, TH, MAXLR, PF, TWM, 0>,                                   \
+   &::fftpde::occ_row<T, LOGN, E, TH, MAXLR, PF, TWM, 0>,                                      \
+   &::fftpde::launch_row<T, LOGN, E, TH, MAXLR, PF, TWM, 1>,                                   \
+   &::fftpde::occ_row<T, LOGN, E, TH, MAXLR, PF, TWM, 1>,                                      \
+   &::fftpde::launch_row<T, LOGN, E, TH, MAXLR, PF, TWM, 2>,                                   \
+   &::fftpde::occ_row<T, LOGN, E, TH, MAXLR, PF, TWM, 2>,                                      \
    LOGN, E, TH, MAXLR, (E) * (TH) >> (LOGN), PF, TWM,                                          \
    int(::fftpde::lds_elems_row<LOGN, MAXLR>((E) * (TH) >> (LOGN)) * sizeof(::fftpde::cx<T>)), \
    "row_" #T "_n" #LOGN "_e" #E "_th" #TH "_r" #MAXLR "_pf" #PF "_tw" #TWM}

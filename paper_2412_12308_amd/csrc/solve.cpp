@@ -35,11 +35,10 @@ int row_pass(Context* c, const void* in, void* out, int lognx, int logny, long l
   const RowVariant* v = c->row_variant(sizeof(T) == 4 ? FFTPDE_C64 : FFTPDE_C128, lognx);
   if (!v) return FFTPDE_EINVAL;
   RowArgs<T> a{static_cast<const cx<T>*>(in), static_cast<cx<T>*>(out), twiddles<T>(c), nrows, inverse ? 1 : 0,
-               T(scale), logny, in_t < 0 ? lognx : in_t, out_t < 0 ? lognx : out_t, real_in, real_out, nreal};
+               T(scale), logny, in_t < 0 ? lognx : in_t, out_t < 0 ? lognx : out_t, nreal};
   const double bytes = 2.0 * sizeof(cx<T>) * (double)nrows * (double)(1 << lognx);
-  const bool real = real_in || real_out;
-  const LaunchFn launch = real ? v->launch_real : v->launch;
-  const OccFn occ = real ? v->occupancy_real : v->occupancy;
+  const LaunchFn launch = real_in ? v->launch_rin : real_out ? v->launch_rout : v->launch;
+  const OccFn occ = real_in ? v->occupancy_rin : real_out ? v->occupancy_rout : v->occupancy;
   const long long maxb = v->pf ? c->max_blocks(reinterpret_cast<const void*>(occ), occ) : 0;
   hipError_t e = timed_launch(c, v->name, bytes, s, [&] { return launch(&a, nrows, maxb, s); });
   if (e != hipSuccess) {
