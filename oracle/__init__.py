@@ -17,7 +17,11 @@ forward = identity; Parseval; the conjugation identity of the iDFT;
 periodicity; single complex exponentials; butterfly identities; numpy.fft
 on large sizes; manufactured Poisson modes; the periodic-image Gaussian
 for diffusion; the standing wave and its energy 17 pi^2; mean
-conservation; diffusion semigroup; wave time reversibility.
+conservation; diffusion semigroup; wave time reversibility.  Sources
+constant in time (tests/test_oracle_sources.py): single modes against the
+forced oscillator and forced decay, constant fields against the k = 0 ODE,
+the equations checked by finite differences in time, the source-free limit,
+the long-time diffusion limit against the Poisson solve.
 """
 from __future__ import annotations
 
@@ -63,8 +67,11 @@ def _load():
         lib.oracle_solve_diffusion.argtypes = [dp, dp, i, i, d, d, d, d, i]
         lib.oracle_wave_spectra.argtypes = [dp, dp, dp, dp, i, i, d, d, d, d]
         lib.oracle_solve_wave.argtypes = [dp, dp, dp, dp, i, i, d, d, d, d, i]
+        lib.oracle_solve_diffusion_source.argtypes = [dp, dp, dp, i, i, d, d, d, d, i]
+        lib.oracle_solve_wave_source.argtypes = [dp, dp, dp, dp, dp, i, i, d, d, d, d, i]
         for f in (lib.oracle_fft1d, lib.oracle_fft2d, lib.oracle_ifft2d, lib.oracle_solve_poisson,
-                  lib.oracle_solve_diffusion, lib.oracle_wave_spectra, lib.oracle_solve_wave):
+                  lib.oracle_solve_diffusion, lib.oracle_wave_spectra, lib.oracle_solve_wave,
+                  lib.oracle_solve_diffusion_source, lib.oracle_solve_wave_source):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -156,6 +163,31 @@ def solve_wave(u0, v0, lx: float, ly: float, c: float, t: float, want_v: bool = 
     v = np.empty_like(u0) if want_v else None
     _check(_load().oracle_solve_wave(_ptr(u0), _ptr(v0), _ptr(u), _ptr(v), nx, ny, lx, ly, c, t,
                                      threads), "wave")
+    return u, v
+
+
+def solve_diffusion_source(f, s, lx: float, ly: float, kappa: float, t: float,
+                           threads: int = 1) -> np.ndarray:
+    """u(t) for u_t = kappa lap(u) + s, u(0) = f, with s constant in time."""
+    f, s = _c128(f), _c128(s)
+    ny, nx = f.shape
+    u = np.empty_like(f)
+    _check(_load().oracle_solve_diffusion_source(_ptr(f), _ptr(s), _ptr(u), nx, ny, lx, ly, kappa, t,
+                                                 threads), "diffusion_source")
+    return u
+
+
+def solve_wave_source(f, g, s, lx: float, ly: float, c: float, t: float, want_v: bool = False,
+                      threads: int = 1) -> Tuple[np.ndarray, Optional[np.ndarray]]:
+    """(u(t), u_t(t)) for u_tt = c^2 lap(u) + s, u(0) = f, u_t(0) = g (None => 0),
+    s constant in time."""
+    f, s = _c128(f), _c128(s)
+    g = None if g is None else _c128(g)
+    ny, nx = f.shape
+    u = np.empty_like(f)
+    v = np.empty_like(f) if want_v else None
+    _check(_load().oracle_solve_wave_source(_ptr(f), _ptr(g), _ptr(s), _ptr(u), _ptr(v), nx, ny, lx, ly,
+                                            c, t, threads), "wave_source")
     return u, v
 
 

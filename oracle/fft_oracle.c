@@ -29,6 +29,9 @@
  *     w = c|k| != 0 and f^ + g^ t for w = 0, Eq. (OmegaNonZero) and
  *     Eq. (OmegaZero); the velocity is its time derivative,
  *     v^(t) = -w f^ sin(w t) + g^ cos(w t).
+ *   - Sources constant in time (Sec. III.B, III.C): forced decay and the
+ *     forced oscillator per coefficient, with the constant particular
+ *     solution of the oscillator written out (see oracle_solve_wave_source).
  *   - Wavenumbers: angular k = 2 pi a'/L with a' the signed index
  *     (a' = a for a < N/2, a - N otherwise), Sec. II.D discrete frequencies
  *     with the frequency shift of Sec. II.B.
@@ -317,6 +320,113 @@ done:
     free(F);
     free(G);
     free(U);
+    free(V);
+    return rc;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Time-independent sources                                                */
+/* ---------------------------------------------------------------------- */
+
+/* Diffusion with a source constant in time (Sec. III.B): each coefficient
+ * obeys du^/dt = -kappa|k|^2 u^ + s^ (Eq. (DiffusionIVPFS) with diffusivity
+ * kappa), u^(0) = f^, so with q = kappa|k|^2
+ *   u^(t) = f^ exp(-q t) + s^ (1 - exp(-q t)) / q     (q > 0)
+ *   u^(t) = f^ + s^ t                                  (q = 0). */
+int oracle_solve_diffusion_source(const double *f, const double *s, double *u, int nx, int ny,
+                                  double lx, double ly, double kappa, double t, int threads)
+{
+    if (lx <= 0 || ly <= 0 || kappa < 0 || t < 0) return -1;
+    size_t p = (size_t)nx * ny;
+    cplx *F = (cplx *)malloc(sizeof(cplx) * p);
+    cplx *S = (cplx *)malloc(sizeof(cplx) * p);
+    int rc = -2;
+    if (!F || !S) goto done;
+    rc = oracle_fft2d(f, (double *)F, nx, ny, -1, threads);
+    if (!rc) rc = oracle_fft2d(s, (double *)S, nx, ny, -1, threads);
+    if (rc) goto done;
+    for (int b = 0; b < ny; b++) {
+        double ky = wavenumber(b, ny, ly);
+        for (int a = 0; a < nx; a++) {
+            double kx = wavenumber(a, nx, lx);
+            double q = kappa * (kx * kx + ky * ky);
+            size_t i = (size_t)b * nx + a;
+            double e, m;
+            if (q == 0.0) {
+                e = 1.0;
+                m = t;
+            } else {
+                e = exp(-q * t);
+                m = (1.0 - e) / q;
+            }
+            F[i].re = F[i].re * e + S[i].re * m;
+            F[i].im = F[i].im * e + S[i].im * m;
+        }
+    }
+    rc = oracle_ifft2d((double *)F, u, nx, ny, threads);
+done:
+    free(F);
+    free(S);
+    return rc;
+}
+
+/* Wave with a source constant in time (Sec. III.C): each coefficient is a
+ * forced oscillator u^'' + w^2 u^ = s^ (Eq. (WaveEquationFourierSpace)),
+ * u^(0) = f^, u^'(0) = g^, w = c|k|:
+ *   w = 0:  u^ = s^ t^2/2 + g^ t + f^                    (Eq. (OmegaZero))
+ *           v^ = s^ t + g^
+ *   w > 0:  u^ = (f^ - s^/w^2) cos(w t) + g^ sin(w t)/w + s^/w^2
+ *           v^ = -w (f^ - s^/w^2) sin(w t) + g^ cos(w t)
+ * The constant particular solution s^/w^2 is written out here; Eq.
+ * (OmegaNonZero) as printed leaves it out, and without it u^ would not
+ * satisfy the oscillator equation.  g, v may be NULL (g = 0; no velocity). */
+int oracle_solve_wave_source(const double *f, const double *g, const double *s, double *u, double *v,
+                             int nx, int ny, double lx, double ly, double c, double t, int threads)
+{
+    if (lx <= 0 || ly <= 0 || c < 0) return -1;
+    size_t p = (size_t)nx * ny;
+    cplx *F = (cplx *)malloc(sizeof(cplx) * p);
+    cplx *G = g ? (cplx *)malloc(sizeof(cplx) * p) : NULL;
+    cplx *S = (cplx *)malloc(sizeof(cplx) * p);
+    cplx *V = v ? (cplx *)malloc(sizeof(cplx) * p) : NULL;
+    int rc = -2;
+    if (!F || !S || (g && !G) || (v && !V)) goto done;
+    rc = oracle_fft2d(f, (double *)F, nx, ny, -1, threads);
+    if (!rc && g) rc = oracle_fft2d(g, (double *)G, nx, ny, -1, threads);
+    if (!rc) rc = oracle_fft2d(s, (double *)S, nx, ny, -1, threads);
+    if (rc) goto done;
+    for (int b = 0; b < ny; b++) {
+        double ky = wavenumber(b, ny, ly);
+        for (int a = 0; a < nx; a++) {
+            double kx = wavenumber(a, nx, lx);
+            double w = c * sqrt(kx * kx + ky * ky);
+            size_t i = (size_t)b * nx + a;
+            cplx ff = F[i], ss = S[i];
+            cplx gg = G ? G[i] : (cplx){0.0, 0.0};
+            cplx uu, vv;
+            if (w == 0.0) {
+                uu.re = ss.re * t * t / 2.0 + gg.re * t + ff.re;
+                uu.im = ss.im * t * t / 2.0 + gg.im * t + ff.im;
+                vv.re = ss.re * t + gg.re;
+                vv.im = ss.im * t + gg.im;
+            } else {
+                double cs = cos(w * t), sn = sin(w * t), w2 = w * w;
+                cplx h = {ff.re - ss.re / w2, ff.im - ss.im / w2};
+                uu.re = h.re * cs + gg.re * sn / w + ss.re / w2;
+                uu.im = h.im * cs + gg.im * sn / w + ss.im / w2;
+                vv.re = -w * h.re * sn + gg.re * cs;
+                vv.im = -w * h.im * sn + gg.im * cs;
+            }
+            F[i] = uu;
+            if (V) V[i] = vv;
+        }
+    }
+    rc = oracle_ifft2d((double *)F, u, nx, ny, threads);
+    if (!rc && v) rc = oracle_ifft2d((double *)V, v, nx, ny, threads);
+done:
+    free(F);
+    free(G);
+    free(S);
     free(V);
     return rc;
 }
