@@ -150,6 +150,45 @@ def run_leg(fp, torch, host_fields, dtype_name: str, steps: int, warmup: int):
     }
 
 
+def source_leg(fp, torch, host_fields, steps: int, warmup: int, check: bool):
+    """The wave problem with an initial velocity and a source constant in time
+    (u_tt = c^2 lap(u) + s): f = the pulse fields, g and s seeded random
+    fields, FP32 complex.  Algorithmic bytes per solve: three fields read and
+    three spectra written by the row passes, three read and one written by the
+    column pass, one read and one written by the inverse row pass: 12 b P."""
+    import numpy as np
+
+    import workloads as W
+    dev = torch.device("cuda:0")
+    batch, ny, nx = host_fields.shape
+    f = torch.from_numpy(host_fields).to(torch.complex64).to(dev)
+    g = torch.from_numpy(W.random_field((batch, ny, nx), seed=71)).to(torch.complex64).to(dev)
+    s = torch.from_numpy(W.random_field((batch, ny, nx), seed=72)).to(torch.complex64).to(dev)
+    out = torch.empty_like(f)
+    for w in range(warmup):
+        fp.solve_wave_source(f, g, s, C_SPEED, (w + 1) * DT, 1.0, 1.0, out=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(steps):
+        fp.solve_wave_source(f, g, s, C_SPEED, (k + 1) * DT, 1.0, 1.0, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    alg = 12.0 * 8 * nx * ny * batch * steps
+    res = {"workload": "wave2d_2048 with u_t(0) and a source constant in time, FP32 complex",
+           "batch": batch, "solves_per_s": round(batch * steps / (ms * 1e-3), 2),
+           "ms_per_step": round(ms / steps, 4), "alg_gbs": round(alg / (ms * 1e-3) / 1e9, 1),
+           "alg_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    if check:
+        import oracle
+        t = steps * DT
+        x = lambda a: a.cpu().numpy()[0].astype(np.complex128)  # noqa: E731
+        ref, _ = oracle.solve_wave_source(x(f), x(g), x(s), 1.0, 1.0, C_SPEED, t, threads=oracle.default_threads())
+        res["err_vs_oracle"] = oracle.rel_l2(out.cpu().numpy()[0].astype(np.complex128), ref)
+    return res
+
+
 def oracle_check(out_dev, host_field, dtype_name, t):
     """Relative L2 error of one GPU result against the FP64 oracle."""
     import numpy as np
@@ -336,6 +375,7 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=16, help="FP32 batch (FP64 uses half)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-real", action="store_true", help="skip the real-field legs")
+    ap.add_argument("--no-source", action="store_true", help="skip the constant-source leg")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-probe", action="store_true",
@@ -395,6 +435,10 @@ def main(argv=None):
                                        "avg_us": round(k["avg_us"], 2), "gbs": round(k["gbs"], 1)}
                                       for k in rr["kernels"]]}
             del rr
+    source = None
+    if not a.no_source:
+        print("# wave with a constant source leg", file=sys.stderr, flush=True)
+        source = source_leg(fp, torch, fields[: max(1, a.batch // 2)], a.steps, a.warmup, not a.no_check)
     batch = None
     if not a.no_batch:
         print("# uneven batch leg", file=sys.stderr, flush=True)
@@ -451,6 +495,8 @@ def main(argv=None):
         line["real_fields"] = {"workload": "the same wave problems with u0 stored as real fields, solved two "
                                            "per complex transform (S(u1 + i u2) = S(u1) + i S(u2): the symbol "
                                            "is real and even)", **real}
+    if source:
+        line["wave_source"] = source
     if batch:
         line["batch"] = batch
     if serve:

@@ -225,6 +225,35 @@ int solve_wave(fftpde_ctx *ctx, const void *u0, const void *v0, void *u, void *v
                int batch, double lx, double ly, double c, double t, int dtype,
                fftpde_stream stream);
 
+/* ---- sources constant in time ------------------------------------------
+ * solve_diffusion_source: u(t) for u_t = kappa lap(u) + s, u(0) = f, with s
+ *   independent of t (Sec. III.B, Eq. (DiffusionIVPFS) with diffusivity
+ *   kappa): per coefficient, with q = kappa |k|^2,
+ *     u^ = f^ exp(-q t) + s^ (1 - exp(-q t))/q,   and f^ + s^ t at q = 0.
+ *   kappa >= 0, t >= 0 finite.
+ * solve_wave_source: u(t) (and u_t(t)) for u_tt = c^2 lap(u) + s, u(0) = f,
+ *   u_t(0) = g, s independent of t (Sec. III.C): per coefficient the forced
+ *   oscillator, w = c|k|,
+ *     u^ = (f^ - s^/w^2) cos(w t) + g^ sin(w t)/w + s^/w^2,
+ *     v^ = -w (f^ - s^/w^2) sin(w t) + g^ cos(w t),
+ *   and s^ t^2/2 + g^ t + f^ (Eq. (OmegaZero)), v^ = s^ t + g^ at w = 0.  The
+ *   constant particular solution s^/w^2 completes Eq. (OmegaNonZero), which
+ *   prints the solution without it.  g = NULL means g = 0; v = NULL means
+ *   the velocity is not written; v must differ from u.  c >= 0, t finite.
+ * Both: complex or real dtypes (real fields in pairs, see FFTPDE_R32); the
+ *   oscillator's cos, sin and (1 - cos(w t))/w^2 = 2 sin^2(w t/2)/w^2, and
+ *   the decay's exp(-q t) and its expm1 form, take FP64 arguments for every
+ *   dtype.  Three row passes in (two without g), one column pass, one or two
+ *   out; the spectra between them live in the context's per-stream scratch
+ *   (two or three fields per 256 MiB chunk of fields).  An output may be the
+ *   same buffer as an input. */
+int solve_diffusion_source(fftpde_ctx *ctx, const void *f, const void *s, void *u, int nx, int ny,
+                           int batch, double lx, double ly, double kappa, double t, int dtype,
+                           fftpde_stream stream);
+int solve_wave_source(fftpde_ctx *ctx, const void *f, const void *g, const void *s, void *u, void *v,
+                      int nx, int ny, int batch, double lx, double ly, double c, double t, int dtype,
+                      fftpde_stream stream);
+
 /* ---- time evolution with resident spectra -------------------------------
  * The diffusion and wave solutions are closed forms in time
  * (Eq. (solCalorFourier); Eq. (OmegaNonZero), (OmegaZero) with s = 0), so a

@@ -113,6 +113,8 @@ def _declare(L):
     L.solve_poisson.argtypes = [vp, vp, vp, i, i, i, d, d, i, vp]
     L.solve_diffusion.argtypes = [vp, vp, vp, i, i, i, d, d, d, d, i, vp]
     L.solve_wave.argtypes = [vp, vp, vp, vp, vp, i, i, i, d, d, d, d, i, vp]
+    L.solve_diffusion_source.argtypes = [vp, vp, vp, vp, i, i, i, d, d, d, d, i, vp]
+    L.solve_wave_source.argtypes = [vp, vp, vp, vp, vp, vp, i, i, i, d, d, d, d, i, vp]
     L.fftpde_profile.argtypes = [vp, i]
     L.fftpde_profile_read.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t,
                                       ctypes.POINTER(ctypes.c_size_t)]
@@ -152,7 +154,7 @@ def _declare(L):
               "fftpde_batch_create", "fftpde_batch_run", "fftpde_batch_status", "fftpde_batch_info",
               "fftpde_batch_destroy", "fftpde_plan_small", "fftpde_plan_tiled", "fftpde_plan_chunk", "fftpde_evolve_create", "fftpde_evolve_step", "fftpde_evolve_destroy", "fftpde_autotune", "fftpde_plan_save", "fftpde_plan_load", "fftpde_plan_variants",
               "fftpde_plan_select", "fftpde_profile", "fftpde_profile_read", "fftpde_create", "fftpde_destroy", "fft2d_forward", "fft2d_inverse", "solve_poisson",
-              "solve_diffusion", "solve_wave"):
+              "solve_diffusion", "solve_wave", "solve_diffusion_source", "solve_wave_source"):
         getattr(L, f).restype = i
 
 
@@ -380,6 +382,37 @@ def solve_wave(u0, v0=None, c: float = 1.0, t: float = 0.0, lx: float = 1.0, ly:
     _check(lib().solve_wave(context(u0.device.index), _ptr(u0), _ptr(v0), _ptr(out), _ptr(v_out),
                             nx, ny, batch, float(lx), float(ly), float(c), float(t), dt,
                             _stream(u0)), "solve_wave")
+    return out, v_out
+
+
+def solve_diffusion_source(f, s, kappa: float, t: float, lx: float = 1.0, ly: float = 1.0, out=None):
+    """u(t) for u_t = kappa lap(u) + s, u(0) = f, with s constant in time."""
+    nx, ny, batch, dt = _field(f, "f", True)
+    if _field(s, "s", True) != (nx, ny, batch, dt) or s.device != f.device:
+        raise ValueError("s must match f")
+    out = _like(f, out)
+    _check(lib().solve_diffusion_source(context(f.device.index), _ptr(f), _ptr(s), _ptr(out), nx, ny, batch,
+                                        float(lx), float(ly), float(kappa), float(t), dt, _stream(f)),
+           "solve_diffusion_source")
+    return out
+
+
+def solve_wave_source(f, g, s, c: float = 1.0, t: float = 0.0, lx: float = 1.0, ly: float = 1.0,
+                      out=None, v_out=None, want_v: bool = False) -> Tuple:
+    """(u(t), u_t(t) or None) for u_tt = c^2 lap(u) + s, u(0) = f, u_t(0) = g (None => 0),
+    s constant in time."""
+    nx, ny, batch, dt = _field(f, "f", True)
+    for name, x in (("g", g), ("s", s)):
+        if x is not None and (_field(x, name, True) != (nx, ny, batch, dt) or x.device != f.device):
+            raise ValueError(f"{name} must match f")
+    if s is None:
+        raise ValueError("s is required (use solve_wave without a source)")
+    out = _like(f, out)
+    if want_v or v_out is not None:
+        v_out = _like(f, v_out, "v_out")
+    _check(lib().solve_wave_source(context(f.device.index), _ptr(f), _ptr(g), _ptr(s), _ptr(out), _ptr(v_out),
+                                   nx, ny, batch, float(lx), float(ly), float(c), float(t), dt, _stream(f)),
+           "solve_wave_source")
     return out, v_out
 
 

@@ -107,8 +107,9 @@ const ColVariant* Context::col_variant(int dtype, int logn, int nf) const {
   const int k = plan_key(dtype, 1, logn, nf);
   if (col_choice[k]) return col_choice[k];
   int n = 0;
-  const ColVariant* t = dtype == FFTPDE_C64 ? (nf == 1 ? col_variants_f32_nf1(&n) : col_variants_f32_nf2(&n))
-                                            : (nf == 1 ? col_variants_f64_nf1(&n) : col_variants_f64_nf2(&n));
+  const ColVariant* t = dtype == FFTPDE_C64
+                           ? (nf == 1 ? col_variants_f32_nf1(&n) : nf == 2 ? col_variants_f32_nf2(&n) : col_variants_f32_nf3(&n))
+                           : (nf == 1 ? col_variants_f64_nf1(&n) : nf == 2 ? col_variants_f64_nf2(&n) : col_variants_f64_nf3(&n));
   for (int i = 0; i < n; i++)
     if (t[i].logn == logn) return &t[i];
   return nullptr;
@@ -320,12 +321,12 @@ void for_each_variant(F&& f) {
   for (int i = 0; i < n; i++) f(VariantRef{r32[i].name, FFTPDE_C64, 0, r32[i].logn, 1, &r32[i], nullptr});
   const RowVariant* r64 = row_variants_f64(&n);
   for (int i = 0; i < n; i++) f(VariantRef{r64[i].name, FFTPDE_C128, 0, r64[i].logn, 1, &r64[i], nullptr});
-  const ColVariant* (*tabs[4])(int*) = {col_variants_f32_nf1, col_variants_f32_nf2, col_variants_f64_nf1,
-                                        col_variants_f64_nf2};
-  for (int k = 0; k < 4; k++) {
+  const ColVariant* (*tabs[6])(int*) = {col_variants_f32_nf1, col_variants_f32_nf2, col_variants_f32_nf3,
+                                        col_variants_f64_nf1, col_variants_f64_nf2, col_variants_f64_nf3};
+  for (int k = 0; k < 6; k++) {
     const ColVariant* t = tabs[k](&n);
     for (int i = 0; i < n; i++)
-      f(VariantRef{t[i].name, k < 2 ? FFTPDE_C64 : FFTPDE_C128, 1, t[i].logn, t[i].nf, nullptr, &t[i]});
+      f(VariantRef{t[i].name, k < 3 ? FFTPDE_C64 : FFTPDE_C128, 1, t[i].logn, t[i].nf, nullptr, &t[i]});
   }
 }
 
@@ -518,6 +519,41 @@ int solve_diffusion(fftpde_ctx* ctx, const void* u0, void* u, int nx, int ny, in
   DeviceGuard g(c->device);
   return run_solve(c, dtype, FFTPDE_DIFFUSION, u0, nullptr, u, nullptr, nx, ny, batch, lx, ly, kappa, t,
                    static_cast<hipStream_t>(stream));
+}
+
+int solve_diffusion_source(fftpde_ctx* ctx, const void* f, const void* src, void* u, int nx, int ny, int batch,
+                           double lx, double ly, double kappa, double t, int dtype, fftpde_stream stream) {
+  int rc = check_common(ctx, nx, ny, batch, dtype, true);
+  if (rc == FFTPDE_OK) rc = check_field(f, dtype);
+  if (rc == FFTPDE_OK) rc = check_field(src, dtype);
+  if (rc == FFTPDE_OK) rc = check_field(u, dtype);
+  if (rc == FFTPDE_OK && !(finite_pos(lx) && finite_pos(ly))) rc = FFTPDE_EINVAL;
+  if (rc == FFTPDE_OK && !(std::isfinite(kappa) && kappa >= 0.0 && std::isfinite(t) && t >= 0.0))
+    rc = FFTPDE_EINVAL;
+  if (rc != FFTPDE_OK) return rc;
+  Context* c = reinterpret_cast<Context*>(ctx);
+  DeviceGuard g(c->device);
+  return run_source(c, dtype, FFTPDE_DIFFUSION, f, nullptr, src, u, nullptr, nx, ny, batch, lx, ly, kappa, t,
+                    static_cast<hipStream_t>(stream));
+}
+
+int solve_wave_source(fftpde_ctx* ctx, const void* f, const void* g0, const void* src, void* u, void* v, int nx,
+                      int ny, int batch, double lx, double ly, double c_speed, double t, int dtype,
+                      fftpde_stream stream) {
+  int rc = check_common(ctx, nx, ny, batch, dtype, true);
+  if (rc == FFTPDE_OK) rc = check_field(f, dtype);
+  if (rc == FFTPDE_OK && g0) rc = check_field(g0, dtype);
+  if (rc == FFTPDE_OK) rc = check_field(src, dtype);
+  if (rc == FFTPDE_OK) rc = check_field(u, dtype);
+  if (rc == FFTPDE_OK && v) rc = check_field(v, dtype);
+  if (rc == FFTPDE_OK && !(finite_pos(lx) && finite_pos(ly))) rc = FFTPDE_EINVAL;
+  if (rc == FFTPDE_OK && !(std::isfinite(c_speed) && c_speed >= 0.0 && std::isfinite(t))) rc = FFTPDE_EINVAL;
+  if (rc == FFTPDE_OK && v && v == u) rc = FFTPDE_EINVAL;
+  if (rc != FFTPDE_OK) return rc;
+  Context* c = reinterpret_cast<Context*>(ctx);
+  DeviceGuard g(c->device);
+  return run_source(c, dtype, FFTPDE_WAVE, f, g0, src, u, v, nx, ny, batch, lx, ly, c_speed, t,
+                    static_cast<hipStream_t>(stream));
 }
 
 int solve_wave(fftpde_ctx* ctx, const void* u0, const void* v0, void* u, void* v, int nx, int ny, int batch,

@@ -16,9 +16,9 @@ namespace fftpde {
 
 // index of a (dtype, pass kind, log2 length, fields per pass) plan slot
 constexpr int plan_key(int dtype, int kind, int logn, int nf) {
-  return ((dtype * 2 + kind) * 13 + logn) * 2 + (nf - 1);
+  return ((dtype * 2 + kind) * 13 + logn) * 3 + (nf - 1);
 }
-constexpr int kPlanSlots = 2 * 2 * 13 * 2;
+constexpr int kPlanSlots = 2 * 2 * 13 * 3;
 
 struct Context {
   int device = 0;

@@ -33,6 +33,8 @@ enum SymOp : int {
   kSymPoisson = 1,    // -1/|k|^2, k = 0 -> 0           (Eq. (SolutionPoisson))
   kSymDiffusion = 2,  // exp(-kappa |k|^2 t)           (Eq. (solCalorFourier))
   kSymWave = 3,       // cos(w t); with a velocity field the full propagator
+  kSymDiffSource = 4, // diffusion with a source constant in time (three-field pass)
+  kSymWaveSource = 5, // wave with a source constant in time (three-field pass)
 };
 
 // Where the passes read their twiddles (see Engine::TwSrc).
@@ -44,7 +46,7 @@ struct SymParams {
   double kxs, kys;  // 2 pi / lx, 2 pi / ly
   double kt;        // diffusion: kappa * t
   double hx, hy;    // wave: 2 c t / lx, 2 c t / ly, so w t / pi = sqrt((hx a')^2 + (hy b')^2)
-  double c, t;      // wave: speed and time (for sin(w t)/w and w)
+  double c, t;      // wave: speed and time (for sin(w t)/w and w); diffusion with a source: kappa and time
   double scale;     // 1 / (nx ny) for modes that end with the inverse
 };
 
@@ -82,6 +84,7 @@ template <typename T>
 struct ColArgs {
   const cx<T>* in0;   // field (or spectrum) u0
   const cx<T>* in1;   // second field (wave velocity), may be null => 0
+  const cx<T>* in2;   // third field (NF = 3: the source)
   cx<T>* out0;
   cx<T>* out1;        // second output (wave velocity), may be null
   const cx<T>* tw;
@@ -275,6 +278,69 @@ struct WaveCoeffs {
   }
 };
 
+// Sources constant in time, per coefficient (the forced decay and the
+// forced oscillator of Sec. III.B and III.C, with the oscillator's constant
+// particular solution s^/w^2):
+//   diffusion  U = e F + m S,  e = exp(-q t), m = (1 - e)/q (t at q = 0), q = kappa|k|^2
+//   wave       U = cos(w t) F + sin(w t)/w G + p S,  V = -w sin(w t) F + cos(w t) G + sin(w t)/w S,
+//              p = (1 - cos(w t))/w^2 = 2 sin^2(w t/2)/w^2 (t^2/2 at w = 0)
+// The half-angle form and expm1 keep p and m accurate where w t or q t is
+// small; all arguments are formed in FP64.
+template <typename T>
+struct SourceCoeffs {
+  int op, logny;
+  double kx2, kys, hx2, hy, c, t;
+  __device__ __forceinline__ SourceCoeffs(const SymParams& p, int a) {
+    const int ai = signed_index(a, p.lognx);
+    const double kx = p.kxs * ai, hx = p.hx * ai;
+    op = p.op;
+    logny = p.logny;
+    kx2 = kx * kx;
+    kys = p.kys;
+    hx2 = hx * hx;
+    hy = p.hy;
+    c = p.c;
+    t = p.t;
+  }
+  // (uf, ug, us): U's weights of F, G, S; (vf, vg, vs): V's
+  __device__ __forceinline__ void operator()(int b, T& uf, T& ug, T& us, T& vf, T& vg, T& vs) const {
+    const int bi = signed_index(b, logny);
+    const double ky = kys * bi;
+    const double k2 = fma(ky, ky, kx2);
+    if (op == kSymDiffSource) {
+      const double q = c * k2;  // c carries kappa
+      const double em1 = expm1(-q * t);
+      uf = T(1.0 + em1);
+      us = q > 0.0 ? T(-em1 / q) : T(t);
+      ug = vf = vg = vs = T(0);
+      return;
+    }
+    const double w = c * sqrt(k2);
+    const double hyb = hy * bi;
+    double h = sqrt(fma(hyb, hyb, hx2));  // |w t| / pi
+    if (t < 0) h = -h;
+    double cw, sw, hs;
+    if constexpr (sizeof(T) == 4) {
+      h = fma(-2.0, rint(0.5 * h), h);  // reduction to [-1, 1], exact
+      float s1, c1;
+      sincospif(float(h), &s1, &c1);
+      cw = c1;
+      sw = s1;
+      hs = sinpif(float(0.5 * h));  // sin(w t/2) up to sign
+    } else {
+      sincospi(h, &sw, &cw);
+      hs = sinpi(0.5 * h);
+    }
+    const double sow = w == 0.0 ? t : sw / w;
+    uf = T(cw);
+    ug = T(sow);
+    us = w == 0.0 ? T(0.5 * t * t) : T(2.0 * hs * hs / (w * w));
+    vf = T(-w * sw);
+    vg = T(cw);
+    vs = T(sow);
+  }
+};
+
 // ---------------------------------------------------------------------------
 // Row pass: LINES = E*TH/N rows per tile, x contiguous.  Workgroups walk
 // tiles persistently; with PF the next tile's rows are loaded into registers
@@ -445,7 +511,8 @@ __global__ void __launch_bounds__(TH) row_kernel(RowArgs<T> a) {
 // ---------------------------------------------------------------------------
 // Column pass: a tile of T = 2^LOGT adjacent columns of one field; columns
 // are numbered C = field * nx + x over the whole batch.  NF = 2 carries a
-// second field (the wave's velocity) through the pass.  SPLIT exchanges the
+// second field (the wave's velocity) through the pass; NF = 3 a third (a
+// source constant in time).  SPLIT exchanges the
 // real and imaginary parts through LDS one after the other (half the LDS, so
 // two workgroups fit per CU at the large sizes); PF prefetches the next tile;
 // FUSED compiles the [forward, symbol, inverse] mode alone.
@@ -511,16 +578,18 @@ __global__ void __launch_bounds__(TH) col_kernel(ColArgs<T> a) {
   };
   // Loads are clamped to the last column (padding columns are reread and never
   // stored), so loads carry no branches and prefetches stay in flight.
-  auto load = [&](long long tile, cx<T>(&dx)[E], cx<T>(&dy)[NF == 2 ? E : 1]) {
+  auto load = [&](long long tile, cx<T>(&dx)[E], cx<T>(&dy)[NF >= 2 ? E : 1], cx<T>(&dz)[NF == 3 ? E : 1]) {
     const long long col0 = tile << LOGT;
     if (whole) {
       const long long cb = col_base(col0);
       const cx<T>* b0 = a.in0 + cb;
       const cx<T>* b1 = has_in1 ? a.in1 + cb : a.in0;
+      const cx<T>* b2 = NF == 3 ? a.in2 + cb : a.in0;
       auto g = [&](int i, int line, int j, int d) {
         const unsigned off = row_off(j, line);
         dx[i] = *at_row(b0, off, d);
-        if constexpr (NF == 2) dy[i] = has_in1 ? *at_row(b1, off, d) : cx<T>{T(0), T(0)};
+        if constexpr (NF >= 2) dy[i] = has_in1 ? *at_row(b1, off, d) : cx<T>{T(0), T(0)};
+        if constexpr (NF == 3) dz[i] = *at_row(b2, off, d);
       };
       if (spec_in) Inv::for_each_input_split(tid, g);
       else Fwd::for_each_input_split(tid, g);
@@ -533,7 +602,8 @@ __global__ void __launch_bounds__(TH) col_kernel(ColArgs<T> a) {
       if constexpr (kOneCol) p = cb + ((long long)n << ts);
       else p = col_base(min(col0 + line, a.ncols - 1)) + ((long long)n << ts);
       dx[i] = a.in0[p];
-      if constexpr (NF == 2) dy[i] = has_in1 ? a.in1[p] : cx<T>{T(0), T(0)};
+      if constexpr (NF >= 2) dy[i] = has_in1 ? a.in1[p] : cx<T>{T(0), T(0)};
+      if constexpr (NF == 3) dz[i] = a.in2[p];
     };
     if (spec_in) Inv::for_each_input(tid, f);
     else Fwd::for_each_input(tid, f);
@@ -591,17 +661,19 @@ __global__ void __launch_bounds__(TH) col_kernel(ColArgs<T> a) {
   };
 
   cx<T> x[E];
-  cx<T> y[NF == 2 ? E : 1];
+  cx<T> y[NF >= 2 ? E : 1];
+  cx<T> z[NF == 3 ? E : 1];
   cx<T> nx_[PF ? E : 1];
-  cx<T> ny_[(PF && NF == 2) ? E : 1];
+  cx<T> ny_[(PF && NF >= 2) ? E : 1];
+  cx<T> nz_[(PF && NF == 3) ? E : 1];
   long long tile = walk.first;
-  load(tile, x, y);
+  load(tile, x, y, z);
   while (true) {
     tid = opaque(tid);
     const long long nt = walk.next(tile);
     const bool more = nt >= 0;
     if constexpr (PF) {
-      if (more) load(nt, nx_, ny_);
+      if (more) load(nt, nx_, ny_, nz_);
     }
 #pragma unroll
     for (int i = 0; i < E; i++) x[i].im *= sgn;
@@ -615,9 +687,10 @@ __global__ void __launch_bounds__(TH) col_kernel(ColArgs<T> a) {
     } else {
       if (!spec_in) {
         fwd(x, tid);
-        if constexpr (NF == 2) {
+        if constexpr (NF >= 2) {
           if (has_in1) fwd(y, tid);
         }
+        if constexpr (NF == 3) fwd(z, tid);
       }
       // Pointwise symbol at (a = column x index, b = n).  The forward
       // engine's last radix is the inverse engine's first, so positions line
@@ -629,6 +702,21 @@ __global__ void __launch_bounds__(TH) col_kernel(ColArgs<T> a) {
           case kSymWave: apply_real(std::integral_constant<int, kSymWave>(), col0, x); break;
           default: apply_real(std::integral_constant<int, kSymScale>(), col0, x); break;
         }
+      } else if constexpr (NF == 3) {
+        const bool want_v = a.out1 != nullptr;
+        const T sc = T(a.sym.scale);
+        Inv::for_each_input(tid, [&](int i, int line, int n) {
+          const SourceCoeffs<T> k(a.sym, int((col0 + line) & fmask));
+          T uf, ug, us, vf, vg, vs;
+          k(n, uf, ug, us, vf, vg, vs);
+          const cx<T> F = x[i], G = y[i], S = z[i];
+          const cx<T> U = {uf * F.re + ug * G.re + us * S.re, uf * F.im + ug * G.im + us * S.im};
+          x[i] = {U.re * sc, -U.im * sc};
+          if (want_v) {
+            const cx<T> V = {vf * F.re + vg * G.re + vs * S.re, vf * F.im + vg * G.im + vs * S.im};
+            y[i] = {V.re * sc, -V.im * sc};
+          }
+        });
       } else {
         const bool want_v = a.out1 != nullptr;
         const T sc = T(a.sym.scale);
@@ -648,7 +736,7 @@ __global__ void __launch_bounds__(TH) col_kernel(ColArgs<T> a) {
       }
       inv(x, tid);
       store(col0, a.out0, [&](int i) { return conjg(x[i]); });
-      if constexpr (NF == 2) {
+      if constexpr (NF >= 2) {
         if (a.out1) {
           inv(y, tid);
           store(col0, a.out1, [&](int i) { return conjg(y[i]); });
@@ -659,12 +747,16 @@ __global__ void __launch_bounds__(TH) col_kernel(ColArgs<T> a) {
     if constexpr (PF) {
 #pragma unroll
       for (int i = 0; i < E; i++) x[i] = nx_[i];
-      if constexpr (NF == 2) {
+      if constexpr (NF >= 2) {
 #pragma unroll
         for (int i = 0; i < E; i++) y[i] = ny_[i];
       }
+      if constexpr (NF == 3) {
+#pragma unroll
+        for (int i = 0; i < E; i++) z[i] = nz_[i];
+      }
     } else {
-      load(nt, x, y);
+      load(nt, x, y, z);
     }
     tile = nt;
   }
@@ -779,5 +871,7 @@ const ColVariant* col_variants_f32_nf1(int* count);
 const ColVariant* col_variants_f32_nf2(int* count);
 const ColVariant* col_variants_f64_nf1(int* count);
 const ColVariant* col_variants_f64_nf2(int* count);
+const ColVariant* col_variants_f32_nf3(int* count);
+const ColVariant* col_variants_f64_nf3(int* count);
 
 }  // namespace fftpde

@@ -55,7 +55,7 @@ int col_pass(Context* c, const void* in0, const void* in1, void* out0, void* out
   if (!v) return FFTPDE_EINVAL;
   // a block holds whole tiles and never spans fields
   if (layout_t >= 0 && (layout_t < v->logt || layout_t > lognx)) return FFTPDE_EINVAL;
-  ColArgs<T> a{static_cast<const cx<T>*>(in0), static_cast<const cx<T>*>(in1), static_cast<cx<T>*>(out0),
+  ColArgs<T> a{static_cast<const cx<T>*>(in0), static_cast<const cx<T>*>(in1), nullptr, static_cast<cx<T>*>(out0),
                static_cast<cx<T>*>(out1), twiddles<T>(c), batch << lognx, lognx, mode, sym, layout_t,
                c->stage_tw<T>(logny, v->maxlr, false), c->stage_tw<T>(logny, v->maxlr, true)};
   const double field = sizeof(cx<T>) * (double)batch * (double)(1ll << (lognx + logny));
@@ -276,6 +276,75 @@ int solve_real_pairs(Context* c, const void* in, const void* in2, void* out, voi
     if (rc != FFTPDE_OK) return rc;
   }
   return FFTPDE_OK;
+}
+
+// Solves with a source constant in time: forward row passes of f, g (if
+// given) and s into per-stream scratch spectra, one three-field column pass
+// (forward, coefficients, inverse), inverse row passes of u (and v).  Complex
+// fields, or real fields in pairs (real: see solve_real_pairs).
+template <typename T>
+int solve_source(Context* c, const void* f, const void* g, const void* src, void* u, void* v, int nx, int ny,
+                 int batch, const SymParams& sym, bool real, hipStream_t s) {
+  const int dt = sizeof(T) == 4 ? FFTPDE_C64 : FFTPDE_C128;
+  const int lx = ilog2(nx), ly = ilog2(ny);
+  const long long pts = (long long)nx * ny;
+  const size_t cfield = sizeof(cx<T>) * (size_t)pts;     // one complex (or pair) field
+  const long long units = real ? (batch + 1) / 2 : batch;  // complex fields to transform
+  const long long cb = c->chunk_bytes_for(dt, lx, ly);
+  long long chunk = cb > 0 ? std::max<long long>(1, cb / (long long)cfield) : units;
+  chunk = std::min<long long>(chunk, units);
+  if (!c->col_variant(dt, ly, 3)) return FFTPDE_EINVAL;
+  const bool two = g != nullptr || v != nullptr;  // a second spectrum (G in, V out)
+  void* w = nullptr;
+  const int rcw = c->workspace(cfield * (size_t)chunk * (two ? 3 : 2), s, &w);
+  if (rcw != FFTPDE_OK) return rcw;
+  void* mF = w;
+  void* mS = static_cast<char*>(w) + cfield * (size_t)chunk;
+  void* mG = two ? static_cast<char*>(w) + 2 * cfield * (size_t)chunk : nullptr;
+  const size_t elem = real ? sizeof(T) : sizeof(cx<T>);
+  for (long long q0 = 0; q0 < units; q0 += chunk) {
+    const long long nq = std::min<long long>(chunk, units - q0);
+    const long long nrows = (long long)ny * nq;
+    const long long f0 = real ? 2 * q0 : q0;
+    const long long nreal = real ? std::min<long long>(2 * nq, batch - f0) : 0;
+    const size_t off = elem * (size_t)(f0 * pts);
+    const int ri = real ? 1 : 0;
+    int rc = row_pass<T>(c, at<T>(f, off), mF, lx, ly, nrows, false, 1.0, s, -1, -1, ri, 0, nreal);
+    if (rc == FFTPDE_OK && g) rc = row_pass<T>(c, at<T>(g, off), mG, lx, ly, nrows, false, 1.0, s, -1, -1, ri, 0, nreal);
+    if (rc == FFTPDE_OK) rc = row_pass<T>(c, at<T>(src, off), mS, lx, ly, nrows, false, 1.0, s, -1, -1, ri, 0, nreal);
+    if (rc == FFTPDE_OK) {
+      const int dtc = sizeof(T) == 4 ? FFTPDE_C64 : FFTPDE_C128;
+      const ColVariant* cv = c->col_variant(dtc, ly, 3);
+      ColArgs<T> a{static_cast<const cx<T>*>(mF), g ? static_cast<const cx<T>*>(mG) : nullptr,
+                   static_cast<const cx<T>*>(mS), static_cast<cx<T>*>(mF), v ? static_cast<cx<T>*>(mG) : nullptr,
+                   twiddles<T>(c), nq << lx, lx, kColFwdMulInv, sym, -1,
+                   c->stage_tw<T>(ly, cv->maxlr, false), c->stage_tw<T>(ly, cv->maxlr, true)};
+      const double bytes = (double)cfield * (double)nq * ((g ? 1 : 0) + 2 + 1 + (v ? 1 : 0));
+      const long long maxb = cv->pf ? c->max_blocks(reinterpret_cast<const void*>(cv->occupancy_fused),
+                                                   cv->occupancy_fused) : 0;
+      hipError_t e = timed_launch(c, cv->name, bytes, s, [&] { return cv->launch_fused(&a, nq << lx, maxb, s); });
+      if (e != hipSuccess) {
+        set_last_error(cv->name, e);
+        rc = FFTPDE_EDEVICE;
+      }
+    }
+    if (rc == FFTPDE_OK) rc = row_pass<T>(c, mF, at<T>(u, off), lx, ly, nrows, true, 1.0, s, -1, -1, 0, ri, nreal);
+    if (rc == FFTPDE_OK && v) rc = row_pass<T>(c, mG, at<T>(v, off), lx, ly, nrows, true, 1.0, s, -1, -1, 0, ri, nreal);
+    if (rc != FFTPDE_OK) return rc;
+  }
+  return FFTPDE_OK;
+}
+
+int run_source(Context* c, int dtype, int op, const void* f, const void* g, const void* src, void* u, void* v, int nx,
+               int ny, int batch, double lx, double ly, double coef, double t, hipStream_t s) {
+  SymParams sym = make_sym(op == FFTPDE_DIFFUSION ? kSymDiffusion : kSymWave, nx, ny, lx, ly, coef, t);
+  sym.op = op == FFTPDE_DIFFUSION ? kSymDiffSource : kSymWaveSource;
+  sym.c = coef;  // kappa or the wave speed
+  sym.t = t;
+  const bool real = dtype == FFTPDE_R32 || dtype == FFTPDE_R64;
+  const bool fp32 = dtype == FFTPDE_C64 || dtype == FFTPDE_R32;
+  return fp32 ? solve_source<float>(c, f, g, src, u, v, nx, ny, batch, sym, real, s)
+              : solve_source<double>(c, f, g, src, u, v, nx, ny, batch, sym, real, s);
 }
 
 int run_transform(Context* c, int dtype, bool inverse, const void* in, void* out, int nx, int ny, int batch,

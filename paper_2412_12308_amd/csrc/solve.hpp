@@ -50,6 +50,12 @@ int run_transform(Context* c, int dtype, bool inverse, const void* in, void* out
 int run_solve(Context* c, int dtype, int op, const void* in, const void* in2, void* out, void* out2, int nx, int ny,
               int batch, double lx, double ly, double coef, double t, hipStream_t s);
 
+// A solve with a source constant in time (op = FFTPDE_DIFFUSION: f, src ->
+// u; FFTPDE_WAVE: f, g (may be null), src -> u, v (may be null)); coef is
+// kappa or the wave speed.  Complex dtypes, or real ones in pairs.
+int run_source(Context* c, int dtype, int op, const void* f, const void* g, const void* src, void* u, void* v, int nx,
+               int ny, int batch, double lx, double ly, double coef, double t, hipStream_t s);
+
 // u(t) (and u_t(t)) of an evolving field from its resident spectra F (and G):
 // the inverse column pass with the propagator at time t applied on load, then
 // the inverse row pass (kind = FFTPDE_DIFFUSION or FFTPDE_WAVE).

@@ -259,3 +259,17 @@ def test_plan_chunk_rejects_negative_sizes():
     fp, L = _lib()
     assert L.fftpde_plan_chunk(DUMMY, -1) == fp.EINVAL
     assert L.fftpde_plan_chunk(None, 1 << 20) == fp.EINVAL
+
+
+def test_source_solves_reject_bad_arguments():
+    fp, L = _lib()
+    # bad shape, bad box, backward diffusion, negative speed, v == u
+    assert L.solve_diffusion_source(DUMMY, P, P, P, 3, 4, 1, 1.0, 1.0, 0.1, 0.5, 0, None) == fp.EINVAL
+    assert L.solve_diffusion_source(DUMMY, P, P, P, 4, 4, 1, 0.0, 1.0, 0.1, 0.5, 0, None) == fp.EINVAL
+    assert L.solve_diffusion_source(DUMMY, P, P, P, 4, 4, 1, 1.0, 1.0, 0.1, -0.5, 0, None) == fp.EINVAL
+    assert L.solve_diffusion_source(DUMMY, P, None, P, 4, 4, 1, 1.0, 1.0, 0.1, 0.5, 0, None) == fp.EINVAL
+    assert L.solve_wave_source(DUMMY, P, None, P, P, None, 4, 4, 1, 1.0, 1.0, -1.0, 0.5, 0, None) == fp.EINVAL
+    assert L.solve_wave_source(DUMMY, P, None, None, P, None, 4, 4, 1, 1.0, 1.0, 1.0, 0.5, 0, None) == fp.EINVAL
+    assert L.solve_wave_source(DUMMY, P, None, P, P, P, 4, 4, 1, 1.0, 1.0, 1.0, 0.5, 0, None) == fp.EINVAL
+    assert L.solve_wave_source(None, P, None, P, P, None, 4, 4, 1, 1.0, 1.0, 1.0, 0.5, 0, None) == fp.EINVAL
+    assert L.solve_wave_source(DUMMY, P, None, P, P, None, 4, 4, 1, 1.0, 1.0, 1.0, 0.5, 5, None) == fp.EINVAL

@@ -92,6 +92,21 @@ def test_variant_matches_oracle(fp, v):
                 assert oracle.rel_l2(u[b], ref) <= tol(dt, nx, ny, 2)
             X = to_host(fp.fft2d_forward(to_dev(s, dt)))
             assert oracle.rel_l2(X[batch - 1], oracle.fft2d(as_oracle_input(s[batch - 1], dt))) <= tol(dt, nx, ny, 1)
+        elif v["fields"] == 3:
+            f = W.random_field((batch, ny, nx), seed=13)
+            g = W.random_field((batch, ny, nx), seed=14)
+            s = W.random_field((batch, ny, nx), seed=15)
+            u, vv = fp.solve_wave_source(to_dev(f, dt), to_dev(g, dt), to_dev(s, dt), 0.9, 0.3, 1.0, 1.0,
+                                         want_v=True)
+            u, vv = to_host(u), to_host(vv)
+            for b in range(batch):
+                fb, gb, sb = (as_oracle_input(a[b], dt) for a in (f, g, s))
+                ru, rv = oracle.solve_wave_source(fb, gb, sb, 1.0, 1.0, 0.9, 0.3, want_v=True)
+                scale = max(np.linalg.norm(ru), np.linalg.norm(fb), np.linalg.norm(sb) * 0.09)
+                assert np.linalg.norm(u[b] - ru) / scale <= tol(dt, nx, ny, 2)
+                wmax = 0.9 * 2 * np.pi * np.hypot(nx / 2, ny / 2)
+                vscale = max(np.linalg.norm(rv), wmax * np.linalg.norm(fb))
+                assert np.linalg.norm(vv[b] - rv) / vscale <= tol(dt, nx, ny, 2)
         else:
             u0 = W.random_field((batch, ny, nx), seed=11)
             v0 = W.random_field((batch, ny, nx), seed=12)
