@@ -48,6 +48,7 @@ class FakeDevice:
         self.log = []
         self.lock = threading.Lock()
         self.gates = {}       # id -> threading.Event to wait on before working
+        self.default_gate = None  # gate for ids without one (set before a submission)
         self.fail = set()     # ids whose final phase fails
         self.inputs = {}      # address -> numpy input (kept alive by the test)
         self.active = 0
@@ -59,7 +60,7 @@ class FakeDevice:
             if phase == 0:
                 self.active += 1
                 self.max_active = max(self.max_active, self.active)
-        gate = self.gates.get(rid)
+        gate = self.gates.get(rid, self.default_gate)
         if gate is not None and phase == 0:
             assert gate.wait(20), "test gate never opened"
         if phase == 1 and req.diag:
@@ -140,8 +141,9 @@ def test_budget_admission_waits_and_is_first_come_first_served(dev):
         ra, xa = _req(dev, POISSON, 64, 64, out=outs[0], seed=1)
         rb, xb = _req(dev, POISSON, 64, 64, out=outs[1], seed=2)
         rc, xc = _req(dev, POISSON, 16, 16, out=outs[2], seed=3)
+        dev.default_gate = threading.Event()
         a = srv.submit_raw(ra)
-        dev.gates[a] = threading.Event()
+        dev.gates[a], dev.default_gate = dev.default_gate, None
         time.sleep(0.05)
         b, c = srv.submit_raw(rb), srv.submit_raw(rc)
         time.sleep(0.2)
@@ -161,11 +163,11 @@ def test_slots_bound_concurrency(dev):
     with fp.Server.host(1 << 24, 2, dev) as srv:
         gate = threading.Event()
         ids = []
+        dev.default_gate = gate   # every request below holds until the gate opens
         for k in range(5):
             out = np.zeros((16, 16), np.complex128)
             r, x = _req(dev, POISSON, 16, 16, out=out, seed=k)
             rid = srv.submit_raw(r, keep=(out,))
-            dev.gates[rid] = gate
             ids.append(rid)
         time.sleep(0.2)
         st = srv.stats()
@@ -195,8 +197,11 @@ def test_rejection_cancellation_deadline_and_failure(dev):
         # a blocking request holds the only slot
         o1 = np.zeros((32, 32), np.complex128)
         r1, _ = _req(dev, POISSON, 32, 32, out=o1, seed=1)
+        # the gate is in place before the submission, so the scheduler cannot
+        # start the request before it holds
+        dev.default_gate = threading.Event()
         a = srv.submit_raw(r1)
-        dev.gates[a] = threading.Event()
+        dev.gates[a], dev.default_gate = dev.default_gate, None
         time.sleep(0.05)
         # queued requests: one cancelled, one past its deadline, one that fails
         o2, o3, o4, o5 = (np.zeros((32, 32), np.complex128) for _ in range(4))
@@ -221,8 +226,9 @@ def test_rejection_cancellation_deadline_and_failure(dev):
         # cancelling a running request: no further work is issued
         o6, d6 = np.zeros((32, 32), np.complex128), np.zeros(300)   # alive until the request ends
         r6, _ = _req(dev, WAVE, 32, 32, out=o6, steps=100, dt=1e-3, coef=1.0, diag=d6, seed=6)
+        dev.default_gate = threading.Event()
         g = srv.submit_raw(r6)
-        dev.gates[g] = threading.Event()
+        dev.gates[g], dev.default_gate = dev.default_gate, None
         time.sleep(0.05)
         srv.cancel(g)
         dev.gates[g].set()
