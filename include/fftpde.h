@@ -254,6 +254,37 @@ int solve_wave_source(fftpde_ctx *ctx, const void *f, const void *g, const void 
                       int nx, int ny, int batch, double lx, double ly, double c, double t, int dtype,
                       fftpde_stream stream);
 
+/* ---- a source that depends on time: RK4 in Fourier space ----------------
+ * fftpde_wave_rk4: (u, u_t) at t0 + steps*dt for u_tt = c^2 lap(u) + s(t),
+ *   u(t0) = f, u_t(t0) = g (NULL => 0), with the orbiting Gaussian source of
+ *   Sec. III.C,
+ *     s(t, x, y) = A exp(-d^2/sigma^2) cos(gamma t),
+ *   d the periodic (minimum-image) distance from (x, y) to the centre
+ *   (cx + r cos(Omega t), cy + r sin(Omega t)).  The grid is
+ *   x_j = x0 + j lx/nx, y_k = y0 + k ly/ny (the origin matters here: the
+ *   source sits at absolute positions).  Every Fourier coefficient of the
+ *   first-order system u^' = v^, v^' = -w^2 u^ + s^(t) (w = c|k|) advances
+ *   by the classical fourth-order Runge-Kutta method with step dt; the
+ *   source is sampled on the grid and transformed at t, t + dt/2 and t + dt
+ *   of each step (the transform at t + dt serves the next step).  The
+ *   spectra live in the context's per-stream scratch ((2 batch + 3) fields)
+ *   between the calls' kernels; the batch shares the source.  Complex
+ *   dtypes.  sigma > 0; A, r, Omega, gamma, cx, cy, x0, y0, t0, dt finite;
+ *   c >= 0; steps >= 0; v may be NULL (not written) and must differ from u.
+ *   The method is stable for c |k|_max |dt| below about 2.8. */
+typedef struct {
+  double amplitude; /* A */
+  double sigma;     /* width sigma_s */
+  double radius;    /* orbit radius r_s */
+  double omega;     /* orbit angular frequency Omega */
+  double gamma;     /* angular frequency gamma of the amplitude */
+  double cx, cy;    /* orbit centre */
+} fftpde_orbit_source;
+int fftpde_wave_rk4(fftpde_ctx *ctx, const fftpde_orbit_source *src, const void *f, const void *g,
+                    void *u, void *v, int nx, int ny, int batch, double x0, double y0, double lx,
+                    double ly, double c, double t0, double dt, int steps, int dtype,
+                    fftpde_stream stream);
+
 /* ---- time evolution with resident spectra -------------------------------
  * The diffusion and wave solutions are closed forms in time
  * (Eq. (solCalorFourier); Eq. (OmegaNonZero), (OmegaZero) with s = 0), so a

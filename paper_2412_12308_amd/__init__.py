@@ -65,6 +65,13 @@ def lib() -> ctypes.CDLL:
     return _lib
 
 
+class FftpdeOrbitSource(ctypes.Structure):
+    """fftpde_orbit_source: the orbiting Gaussian source of fftpde_wave_rk4."""
+    _fields_ = [("amplitude", ctypes.c_double), ("sigma", ctypes.c_double), ("radius", ctypes.c_double),
+                ("omega", ctypes.c_double), ("gamma", ctypes.c_double), ("cx", ctypes.c_double),
+                ("cy", ctypes.c_double)]
+
+
 class FftpdeJob(ctypes.Structure):
     """struct fftpde_job of the C ABI."""
     _fields_ = [("op", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int),
@@ -115,6 +122,8 @@ def _declare(L):
     L.solve_wave.argtypes = [vp, vp, vp, vp, vp, i, i, i, d, d, d, d, i, vp]
     L.solve_diffusion_source.argtypes = [vp, vp, vp, vp, i, i, i, d, d, d, d, i, vp]
     L.solve_wave_source.argtypes = [vp, vp, vp, vp, vp, vp, i, i, i, d, d, d, d, i, vp]
+    L.fftpde_wave_rk4.argtypes = [vp, ctypes.POINTER(FftpdeOrbitSource), vp, vp, vp, vp, i, i, i, d, d, d, d, d,
+                                  d, d, i, i, vp]
     L.fftpde_profile.argtypes = [vp, i]
     L.fftpde_profile_read.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t,
                                       ctypes.POINTER(ctypes.c_size_t)]
@@ -154,7 +163,7 @@ def _declare(L):
               "fftpde_batch_create", "fftpde_batch_run", "fftpde_batch_status", "fftpde_batch_info",
               "fftpde_batch_destroy", "fftpde_plan_small", "fftpde_plan_tiled", "fftpde_plan_chunk", "fftpde_evolve_create", "fftpde_evolve_step", "fftpde_evolve_destroy", "fftpde_autotune", "fftpde_plan_save", "fftpde_plan_load", "fftpde_plan_variants",
               "fftpde_plan_select", "fftpde_profile", "fftpde_profile_read", "fftpde_create", "fftpde_destroy", "fft2d_forward", "fft2d_inverse", "solve_poisson",
-              "solve_diffusion", "solve_wave", "solve_diffusion_source", "solve_wave_source"):
+              "solve_diffusion", "solve_wave", "solve_diffusion_source", "solve_wave_source", "fftpde_wave_rk4"):
         getattr(L, f).restype = i
 
 
@@ -413,6 +422,27 @@ def solve_wave_source(f, g, s, c: float = 1.0, t: float = 0.0, lx: float = 1.0, 
     _check(lib().solve_wave_source(context(f.device.index), _ptr(f), _ptr(g), _ptr(s), _ptr(out), _ptr(v_out),
                                    nx, ny, batch, float(lx), float(ly), float(c), float(t), dt, _stream(f)),
            "solve_wave_source")
+    return out, v_out
+
+
+def wave_rk4(f, g=None, *, amplitude: float, sigma: float, radius: float, omega: float, gamma: float,
+             cx: float = 0.0, cy: float = 0.0, x0: float = 0.0, y0: float = 0.0, lx: float = 1.0,
+             ly: float = 1.0, c: float = 1.0, t0: float = 0.0, dt: float, steps: int, out=None, v_out=None,
+             want_v: bool = False) -> Tuple:
+    """(u, u_t) at t0 + steps*dt for u_tt = c^2 lap(u) + s(t) with the orbiting
+    Gaussian source s = A exp(-d^2/sigma^2) cos(gamma t) (centre cx + r cos(Omega t),
+    cy + r sin(Omega t)), RK4 in Fourier space (fftpde_wave_rk4)."""
+    nx, ny, batch, dt_code = _field(f, "f")
+    if g is not None and (_field(g, "g") != (nx, ny, batch, dt_code) or g.device != f.device):
+        raise ValueError("g must match f")
+    out = _like(f, out)
+    if want_v or v_out is not None:
+        v_out = _like(f, v_out, "v_out")
+    src = FftpdeOrbitSource(float(amplitude), float(sigma), float(radius), float(omega), float(gamma),
+                            float(cx), float(cy))
+    _check(lib().fftpde_wave_rk4(context(f.device.index), ctypes.byref(src), _ptr(f), _ptr(g), _ptr(out),
+                                 _ptr(v_out), nx, ny, batch, float(x0), float(y0), float(lx), float(ly), float(c),
+                                 float(t0), float(dt), int(steps), dt_code, _stream(f)), "fftpde_wave_rk4")
     return out, v_out
 
 

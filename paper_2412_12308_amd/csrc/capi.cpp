@@ -17,6 +17,7 @@
 #include "../../include/fftpde.h"
 #include "context.hpp"
 #include "kernels.hpp"
+#include "rk4.hpp"
 #include "solve.hpp"
 
 using namespace fftpde;
@@ -554,6 +555,31 @@ int solve_wave_source(fftpde_ctx* ctx, const void* f, const void* g0, const void
   DeviceGuard g(c->device);
   return run_source(c, dtype, FFTPDE_WAVE, f, g0, src, u, v, nx, ny, batch, lx, ly, c_speed, t,
                     static_cast<hipStream_t>(stream));
+}
+
+int fftpde_wave_rk4(fftpde_ctx* ctx, const fftpde_orbit_source* src, const void* f, const void* g0, void* u, void* v,
+                    int nx, int ny, int batch, double x0, double y0, double lx, double ly, double c_speed, double t0,
+                    double dt, int steps, int dtype, fftpde_stream stream) {
+  int rc = check_common(ctx, nx, ny, batch, dtype);
+  if (rc == FFTPDE_OK) rc = check_field(f, dtype);
+  if (rc == FFTPDE_OK && g0) rc = check_field(g0, dtype);
+  if (rc == FFTPDE_OK) rc = check_field(u, dtype);
+  if (rc == FFTPDE_OK && v) rc = check_field(v, dtype);
+  if (rc == FFTPDE_OK && (!src || !(std::isfinite(src->sigma) && src->sigma > 0.0))) rc = FFTPDE_EINVAL;
+  if (rc == FFTPDE_OK) {
+    const double fin[] = {src->amplitude, src->radius, src->omega, src->gamma, src->cx, src->cy, x0, y0, t0, dt};
+    for (double x : fin)
+      if (!std::isfinite(x)) rc = FFTPDE_EINVAL;
+  }
+  if (rc == FFTPDE_OK && !(finite_pos(lx) && finite_pos(ly))) rc = FFTPDE_EINVAL;
+  if (rc == FFTPDE_OK && !(std::isfinite(c_speed) && c_speed >= 0.0) ) rc = FFTPDE_EINVAL;
+  if (rc == FFTPDE_OK && (steps < 0 || (v && v == u))) rc = FFTPDE_EINVAL;
+  if (rc != FFTPDE_OK) return rc;
+  Context* c = reinterpret_cast<Context*>(ctx);
+  DeviceGuard g(c->device);
+  const OrbitSource os{src->amplitude, src->sigma, src->radius, src->omega, src->gamma, src->cx, src->cy};
+  return run_wave_rk4(c, dtype, os, f, g0, u, v, nx, ny, batch, x0, y0, lx, ly, c_speed, t0, dt, steps,
+                      static_cast<hipStream_t>(stream));
 }
 
 int solve_wave(fftpde_ctx* ctx, const void* u0, const void* v0, void* u, void* v, int nx, int ny, int batch,

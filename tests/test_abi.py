@@ -273,3 +273,21 @@ def test_source_solves_reject_bad_arguments():
     assert L.solve_wave_source(DUMMY, P, None, P, P, P, 4, 4, 1, 1.0, 1.0, 1.0, 0.5, 0, None) == fp.EINVAL
     assert L.solve_wave_source(None, P, None, P, P, None, 4, 4, 1, 1.0, 1.0, 1.0, 0.5, 0, None) == fp.EINVAL
     assert L.solve_wave_source(DUMMY, P, None, P, P, None, 4, 4, 1, 1.0, 1.0, 1.0, 0.5, 5, None) == fp.EINVAL
+
+
+def test_wave_rk4_rejects_bad_arguments():
+    fp, L = _lib()
+    ok = fp.FftpdeOrbitSource(1.0, 0.1, 1.0, 5.0, 10.0, 0.0, 0.0)
+    bad_sigma = fp.FftpdeOrbitSource(1.0, 0.0, 1.0, 5.0, 10.0, 0.0, 0.0)
+    bad_nan = fp.FftpdeOrbitSource(math.nan, 0.1, 1.0, 5.0, 10.0, 0.0, 0.0)
+    args = lambda src, steps=4, dt=0.01, c=1.0, v=None, dtype=0: (  # noqa: E731
+        DUMMY, src, P, None, P, v, 4, 4, 1, -2.0, -2.0, 4.0, 4.0, c, 0.0, dt, steps, dtype, None)
+    assert ctypes.sizeof(fp.FftpdeOrbitSource) == 7 * 8
+    assert L.fftpde_wave_rk4(*args(None)) == fp.EINVAL
+    assert L.fftpde_wave_rk4(*args(ctypes.byref(bad_sigma))) == fp.EINVAL
+    assert L.fftpde_wave_rk4(*args(ctypes.byref(bad_nan))) == fp.EINVAL
+    assert L.fftpde_wave_rk4(*args(ctypes.byref(ok), steps=-1)) == fp.EINVAL
+    assert L.fftpde_wave_rk4(*args(ctypes.byref(ok), dt=math.inf)) == fp.EINVAL
+    assert L.fftpde_wave_rk4(*args(ctypes.byref(ok), c=-1.0)) == fp.EINVAL
+    assert L.fftpde_wave_rk4(*args(ctypes.byref(ok), v=P)) == fp.EINVAL
+    assert L.fftpde_wave_rk4(*args(ctypes.byref(ok), dtype=2)) == fp.EINVAL   # complex only
