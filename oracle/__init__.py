@@ -24,7 +24,10 @@ the equations checked by finite differences in time, the source-free limit,
 the long-time diffusion limit against the Poisson solve.  The RK4 wave
 integrator with a time-dependent source (tests/test_oracle_rk4.py): fourth-
 order convergence to the exact source-free and constant-source solutions,
-and the self-convergence factor of Sec. III.C on the orbiting source.
+and the self-convergence factor of Sec. III.C on the orbiting source.  3D
+(tests/test_oracle_3d.py): brute-force 3D DFT, numpy.fft.fftn, inverse,
+Parseval, manufactured Poisson modes, single-mode diffusion and standing
+waves in closed form.
 """
 from __future__ import annotations
 
@@ -72,7 +75,11 @@ def _load():
         lib.oracle_solve_wave.argtypes = [dp, dp, dp, dp, i, i, d, d, d, d, i]
         lib.oracle_solve_diffusion_source.argtypes = [dp, dp, dp, i, i, d, d, d, d, i]
         lib.oracle_solve_wave_source.argtypes = [dp, dp, dp, dp, dp, i, i, d, d, d, d, i]
-        for f in (lib.oracle_fft1d, lib.oracle_fft2d, lib.oracle_ifft2d, lib.oracle_solve_poisson,
+        lib.oracle_fft3d.argtypes = [dp, dp, i, i, i, i, i]
+        lib.oracle_ifft3d.argtypes = [dp, dp, i, i, i, i]
+        lib.oracle_solve3d.argtypes = [dp, dp, i, i, i, d, d, d, i, d, d, i]
+        for f in (lib.oracle_fft3d, lib.oracle_ifft3d, lib.oracle_solve3d,
+                  lib.oracle_fft1d, lib.oracle_fft2d, lib.oracle_ifft2d, lib.oracle_solve_poisson,
                   lib.oracle_solve_diffusion, lib.oracle_wave_spectra, lib.oracle_solve_wave,
                   lib.oracle_solve_diffusion_source, lib.oracle_solve_wave_source):
             f.restype = ctypes.c_int
@@ -192,6 +199,36 @@ def solve_wave_source(f, g, s, lx: float, ly: float, c: float, t: float, want_v:
     _check(_load().oracle_solve_wave_source(_ptr(f), _ptr(g), _ptr(s), _ptr(u), _ptr(v), nx, ny, lx, ly,
                                             c, t, threads), "wave_source")
     return u, v
+
+
+def fft3d(x, sign: int = FORWARD, threads: int = 1) -> np.ndarray:
+    """Unnormalised 3D transform of an [nz][ny][nx] field: x lines, y lines, z lines."""
+    x = _c128(x)
+    nz, ny, nx = x.shape
+    out = np.empty_like(x)
+    _check(_load().oracle_fft3d(_ptr(x), _ptr(out), nx, ny, nz, sign, threads), "fft3d")
+    return out
+
+
+def ifft3d(x, threads: int = 1) -> np.ndarray:
+    """Inverse 3D transform: exp(+) sum times 1/(nx*ny*nz)."""
+    x = _c128(x)
+    nz, ny, nx = x.shape
+    out = np.empty_like(x)
+    _check(_load().oracle_ifft3d(_ptr(x), _ptr(out), nx, ny, nz, threads), "ifft3d")
+    return out
+
+
+def solve3d(u0, lx: float, ly: float, lz: float, op: int, coef: float = 0.0, t: float = 0.0,
+            threads: int = 1) -> np.ndarray:
+    """The three solves on a periodic box in 3D: op 0 Poisson (zero-mean u with
+    lap(u) = s - mean(s)), op 1 diffusion (kappa = coef), op 2 wave with zero
+    initial velocity (c = coef)."""
+    u0 = _c128(u0)
+    nz, ny, nx = u0.shape
+    out = np.empty_like(u0)
+    _check(_load().oracle_solve3d(_ptr(u0), _ptr(out), nx, ny, nz, lx, ly, lz, op, coef, t, threads), "solve3d")
+    return out
 
 
 def orbiting_source(nx: int, ny: int, x0: float, y0: float, lx: float, ly: float, t: float, amplitude: float,

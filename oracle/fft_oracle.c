@@ -198,8 +198,9 @@ int oracle_ifft2d(const double *in, double *out, int nx, int ny, int threads)
 /* Wavenumbers and the three spectral solves                               */
 /* ---------------------------------------------------------------------- */
 
-/* Signed index of frequency slot a on an n-point axis. */
-static double signed_index(int a, int n) { return (double)(a < n / 2 ? a : a - n); }
+/* Signed index of frequency slot a on an n-point axis: a for a < n/2, else
+ * a - n (2a < n also gives 0 on a one-point axis). */
+static double signed_index(int a, int n) { return (double)(2 * a < n ? a : a - n); }
 
 /* Angular wavenumber 2 pi a'/L. */
 static double wavenumber(int a, int n, double len) { return 2.0 * PI * signed_index(a, n) / len; }
@@ -428,5 +429,73 @@ done:
     free(G);
     free(S);
     free(V);
+    return rc;
+}
+
+/* ---------------------------------------------------------------------- */
+/* 3D (the n-dimensional extension of Sec. II.D): x lines, y lines, z lines */
+/* ---------------------------------------------------------------------- */
+
+/* Unnormalised 3D transform of a [nz][ny][nx] field, exponent sign `sign`:
+ * the 2D transform of every z plane, then every z line, the latter seen as
+ * the columns of an [nz][nx*ny] array. */
+int oracle_fft3d(const double *in, double *out, int nx, int ny, int nz, int sign, int threads)
+{
+    if (!is_pow2(nx) || !is_pow2(ny) || !is_pow2(nz) || (sign != 1 && sign != -1)) return -1;
+    size_t plane = (size_t)nx * ny, p = plane * nz;
+    if (out != in) memmove(out, in, sizeof(cplx) * p);
+    for (int z = 0; z < nz; z++) {
+        cplx *pl = (cplx *)out + plane * z;
+        int rc = run_lines(pl, nx, ny, sign, 0, threads);
+        if (!rc) rc = run_lines(pl, nx, ny, sign, 1, threads);
+        if (rc) return rc;
+    }
+    return run_lines((cplx *)out, nx * ny, nz, sign, 1, threads);
+}
+
+int oracle_ifft3d(const double *in, double *out, int nx, int ny, int nz, int threads)
+{
+    int rc = oracle_fft3d(in, out, nx, ny, nz, +1, threads);
+    if (rc) return rc;
+    size_t p = (size_t)nx * ny * nz;
+    double s = 1.0 / (double)p;
+    for (size_t i = 0; i < 2 * p; i++) out[i] *= s;
+    return 0;
+}
+
+/* The three solves on a periodic lx-by-ly-by-lz box, |k|^2 = kx^2 + ky^2 +
+ * kz^2: op 0 Poisson (-1/|k|^2, k = 0 -> 0), op 1 diffusion
+ * (exp(-kappa |k|^2 t)), op 2 wave with zero initial velocity (cos(c|k|t)). */
+int oracle_solve3d(const double *in, double *out, int nx, int ny, int nz, double lx, double ly, double lz,
+                   int op, double coef, double t, int threads)
+{
+    if (lx <= 0 || ly <= 0 || lz <= 0 || op < 0 || op > 2) return -1;
+    size_t plane = (size_t)nx * ny, p = plane * nz;
+    cplx *f = (cplx *)malloc(sizeof(cplx) * p);
+    if (!f) return -2;
+    int rc = oracle_fft3d(in, (double *)f, nx, ny, nz, -1, threads);
+    if (rc) {
+        free(f);
+        return rc;
+    }
+    for (int z = 0; z < nz; z++) {
+        double kz = wavenumber(z, nz, lz);
+        for (int b = 0; b < ny; b++) {
+            double ky = wavenumber(b, ny, ly);
+            for (int a = 0; a < nx; a++) {
+                double kx = wavenumber(a, nx, lx);
+                double k2 = kx * kx + ky * ky + kz * kz;
+                double m;
+                if (op == 0) m = (a == 0 && b == 0 && z == 0) ? 0.0 : -1.0 / k2;
+                else if (op == 1) m = exp(-coef * k2 * t);
+                else m = cos(coef * sqrt(k2) * t);
+                cplx *c = &f[plane * z + (size_t)b * nx + a];
+                c->re *= m;
+                c->im *= m;
+            }
+        }
+    }
+    rc = oracle_ifft3d((double *)f, out, nx, ny, nz, threads);
+    free(f);
     return rc;
 }
