@@ -189,6 +189,40 @@ def source_leg(fp, torch, host_fields, steps: int, warmup: int, check: bool):
     return res
 
 
+def leg_3d(fp, torch, steps: int, warmup: int, check: bool):
+    """3D wave solves, 256^3 FP32 complex, batch 4 (512 MiB): five passes,
+    algorithmic bytes 10 b P per solve."""
+    import numpy as np
+
+    import workloads as W
+    n, batch = 256, 4
+    host = W.random_field((batch, n, n, n), seed=81).astype(np.complex64)
+    u0 = torch.from_numpy(host).to("cuda:0")
+    del host
+    out = torch.empty_like(u0)
+    for w in range(warmup):
+        fp.solve_wave_3d(u0, C_SPEED, (w + 1) * DT, out=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(steps):
+        fp.solve_wave_3d(u0, C_SPEED, (k + 1) * DT, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    alg = 10.0 * 8 * n ** 3 * batch * steps
+    res = {"workload": "wave3d_256^3_periodic_unit_cube, FP32 complex, random initial data", "batch": batch,
+           "solves_per_s": round(batch * steps / (ms * 1e-3), 2), "ms_per_step": round(ms / steps, 4),
+           "alg_gbs": round(alg / (ms * 1e-3) / 1e9, 1), "alg_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    if check:
+        import oracle
+        x = u0[0].cpu().numpy().astype(np.complex128)
+        ref = oracle.solve3d(x, 1.0, 1.0, 1.0, 2, C_SPEED, steps * DT, threads=oracle.default_threads())
+        res["err_vs_oracle"] = oracle.rel_l2(out[0].cpu().numpy().astype(np.complex128), ref)
+    del u0, out
+    return res
+
+
 def oracle_check(out_dev, host_field, dtype_name, t):
     """Relative L2 error of one GPU result against the FP64 oracle."""
     import numpy as np
@@ -376,6 +410,7 @@ def main(argv=None):
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-real", action="store_true", help="skip the real-field legs")
     ap.add_argument("--no-source", action="store_true", help="skip the constant-source leg")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3D leg")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-probe", action="store_true",
@@ -435,6 +470,10 @@ def main(argv=None):
                                        "avg_us": round(k["avg_us"], 2), "gbs": round(k["gbs"], 1)}
                                       for k in rr["kernels"]]}
             del rr
+    three = None
+    if not a.no_3d:
+        print("# 3d leg", file=sys.stderr, flush=True)
+        three = leg_3d(fp, torch, a.steps, a.warmup, not a.no_check)
     source = None
     if not a.no_source:
         print("# wave with a constant source leg", file=sys.stderr, flush=True)
@@ -495,6 +534,8 @@ def main(argv=None):
         line["real_fields"] = {"workload": "the same wave problems with u0 stored as real fields, solved two "
                                            "per complex transform (S(u1 + i u2) = S(u1) + i S(u2): the symbol "
                                            "is real and even)", **real}
+    if three:
+        line["wave3d"] = three
     if source:
         line["wave_source"] = source
     if batch:

@@ -254,6 +254,28 @@ int solve_wave_source(fftpde_ctx *ctx, const void *f, const void *g, const void 
                       int nx, int ny, int batch, double lx, double ly, double c, double t, int dtype,
                       fftpde_stream stream);
 
+/* ---- 3D ------------------------------------------------------------------
+ * Fields [nz][ny][nx] (x contiguous, then y, then z), nx, ny, nz powers of
+ * two in [2, 4096] with nx*ny <= 2^24; batch fields back to back; complex
+ * dtypes.  The transform is the n-dimensional extension of the row-column
+ * scheme of Sec. II.D: x rows, then the y columns of every z plane, then the
+ * z columns.  fft3d_inverse scales by 1/(nx ny nz).  The solves are those of
+ * the 2D entry points with |k|^2 = kx^2 + ky^2 + kz^2 (the wave without an
+ * initial velocity), five passes: x, y, z with the symbol fused between its
+ * forward and inverse transforms, y, x.  In place allowed. */
+int fft3d_forward(fftpde_ctx *ctx, const void *in, void *out, int nx, int ny, int nz, int batch,
+                  int dtype, fftpde_stream stream);
+int fft3d_inverse(fftpde_ctx *ctx, const void *in, void *out, int nx, int ny, int nz, int batch,
+                  int dtype, fftpde_stream stream);
+int solve_poisson_3d(fftpde_ctx *ctx, const void *s, void *u, int nx, int ny, int nz, int batch,
+                     double lx, double ly, double lz, int dtype, fftpde_stream stream);
+int solve_diffusion_3d(fftpde_ctx *ctx, const void *u0, void *u, int nx, int ny, int nz, int batch,
+                       double lx, double ly, double lz, double kappa, double t, int dtype,
+                       fftpde_stream stream);
+int solve_wave_3d(fftpde_ctx *ctx, const void *u0, void *u, int nx, int ny, int nz, int batch,
+                  double lx, double ly, double lz, double c, double t, int dtype,
+                  fftpde_stream stream);
+
 /* ---- a source that depends on time: RK4 in Fourier space ----------------
  * fftpde_wave_rk4: (u, u_t) at t0 + steps*dt for u_tt = c^2 lap(u) + s(t),
  *   u(t0) = f, u_t(t0) = g (NULL => 0), with the orbiting Gaussian source of

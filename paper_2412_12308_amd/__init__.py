@@ -122,6 +122,11 @@ def _declare(L):
     L.solve_wave.argtypes = [vp, vp, vp, vp, vp, i, i, i, d, d, d, d, i, vp]
     L.solve_diffusion_source.argtypes = [vp, vp, vp, vp, i, i, i, d, d, d, d, i, vp]
     L.solve_wave_source.argtypes = [vp, vp, vp, vp, vp, vp, i, i, i, d, d, d, d, i, vp]
+    L.fft3d_forward.argtypes = [vp, vp, vp, i, i, i, i, i, vp]
+    L.fft3d_inverse.argtypes = [vp, vp, vp, i, i, i, i, i, vp]
+    L.solve_poisson_3d.argtypes = [vp, vp, vp, i, i, i, i, d, d, d, i, vp]
+    L.solve_diffusion_3d.argtypes = [vp, vp, vp, i, i, i, i, d, d, d, d, d, i, vp]
+    L.solve_wave_3d.argtypes = [vp, vp, vp, i, i, i, i, d, d, d, d, d, i, vp]
     L.fftpde_wave_rk4.argtypes = [vp, ctypes.POINTER(FftpdeOrbitSource), vp, vp, vp, vp, i, i, i, d, d, d, d, d,
                                   d, d, i, i, vp]
     L.fftpde_profile.argtypes = [vp, i]
@@ -163,7 +168,8 @@ def _declare(L):
               "fftpde_batch_create", "fftpde_batch_run", "fftpde_batch_status", "fftpde_batch_info",
               "fftpde_batch_destroy", "fftpde_plan_small", "fftpde_plan_tiled", "fftpde_plan_chunk", "fftpde_evolve_create", "fftpde_evolve_step", "fftpde_evolve_destroy", "fftpde_autotune", "fftpde_plan_save", "fftpde_plan_load", "fftpde_plan_variants",
               "fftpde_plan_select", "fftpde_profile", "fftpde_profile_read", "fftpde_create", "fftpde_destroy", "fft2d_forward", "fft2d_inverse", "solve_poisson",
-              "solve_diffusion", "solve_wave", "solve_diffusion_source", "solve_wave_source", "fftpde_wave_rk4"):
+              "solve_diffusion", "solve_wave", "solve_diffusion_source", "solve_wave_source", "fftpde_wave_rk4",
+              "fft3d_forward", "fft3d_inverse", "solve_poisson_3d", "solve_diffusion_3d", "solve_wave_3d"):
         getattr(L, f).restype = i
 
 
@@ -444,6 +450,65 @@ def wave_rk4(f, g=None, *, amplitude: float, sigma: float, radius: float, omega:
                                  _ptr(v_out), nx, ny, batch, float(x0), float(y0), float(lx), float(ly), float(c),
                                  float(t0), float(dt), int(steps), dt_code, _stream(f)), "fftpde_wave_rk4")
     return out, v_out
+
+
+def _field3d(t, name: str):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ValueError(f"{name} must be a torch.Tensor on a ROCm device (there is no CPU path)")
+    if t.dim() < 3:
+        raise ValueError(f"{name} must have shape [..., nz, ny, nx]")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    nz, ny, nx = t.shape[-3], t.shape[-2], t.shape[-1]
+    pts = nx * ny * nz
+    return nx, ny, nz, (t.numel() // pts if pts else 0), _dtype_code(t)
+
+
+def fft3d_forward(x, out=None):
+    """Unnormalised forward 3D FFT of [..., nz, ny, nx] fields."""
+    nx, ny, nz, batch, dt = _field3d(x, "x")
+    out = _like(x, out)
+    _check(lib().fft3d_forward(context(x.device.index), _ptr(x), _ptr(out), nx, ny, nz, batch, dt, _stream(x)),
+           "fft3d_forward")
+    return out
+
+
+def fft3d_inverse(x, out=None):
+    """Inverse 3D FFT, exponent exp(+...) times 1/(nx ny nz)."""
+    nx, ny, nz, batch, dt = _field3d(x, "x")
+    out = _like(x, out)
+    _check(lib().fft3d_inverse(context(x.device.index), _ptr(x), _ptr(out), nx, ny, nz, batch, dt, _stream(x)),
+           "fft3d_inverse")
+    return out
+
+
+def solve_poisson_3d(s, lx: float = 1.0, ly: float = 1.0, lz: float = 1.0, out=None):
+    """Zero-mean u with lap(u) = s - mean(s) on a periodic 3D box."""
+    nx, ny, nz, batch, dt = _field3d(s, "s")
+    out = _like(s, out)
+    _check(lib().solve_poisson_3d(context(s.device.index), _ptr(s), _ptr(out), nx, ny, nz, batch, float(lx),
+                                  float(ly), float(lz), dt, _stream(s)), "solve_poisson_3d")
+    return out
+
+
+def solve_diffusion_3d(u0, kappa: float, t: float, lx: float = 1.0, ly: float = 1.0, lz: float = 1.0, out=None):
+    """u(t) for u_t = kappa lap(u) on a periodic 3D box."""
+    nx, ny, nz, batch, dt = _field3d(u0, "u0")
+    out = _like(u0, out)
+    _check(lib().solve_diffusion_3d(context(u0.device.index), _ptr(u0), _ptr(out), nx, ny, nz, batch, float(lx),
+                                    float(ly), float(lz), float(kappa), float(t), dt, _stream(u0)),
+           "solve_diffusion_3d")
+    return out
+
+
+def solve_wave_3d(u0, c: float = 1.0, t: float = 0.0, lx: float = 1.0, ly: float = 1.0, lz: float = 1.0, out=None):
+    """u(t) for u_tt = c^2 lap(u), u(0) = u0, u_t(0) = 0, on a periodic 3D box."""
+    nx, ny, nz, batch, dt = _field3d(u0, "u0")
+    out = _like(u0, out)
+    _check(lib().solve_wave_3d(context(u0.device.index), _ptr(u0), _ptr(out), nx, ny, nz, batch, float(lx),
+                               float(ly), float(lz), float(c), float(t), dt, _stream(u0)), "solve_wave_3d")
+    return out
 
 
 class Evolution:

@@ -557,6 +557,69 @@ int solve_wave_source(fftpde_ctx* ctx, const void* f, const void* g0, const void
                     static_cast<hipStream_t>(stream));
 }
 
+namespace {
+int check3d(fftpde_ctx* ctx, int nx, int ny, int nz, int batch, int dtype, const void* a, const void* b) {
+  int rc = check_common(ctx, nx, ny, batch, dtype);
+  if (rc == FFTPDE_OK && (!pow2_side(nz) || (long long)nx * ny > (1ll << 24))) rc = FFTPDE_EINVAL;
+  if (rc == FFTPDE_OK) rc = check_field(a, dtype);
+  if (rc == FFTPDE_OK) rc = check_field(b, dtype);
+  return rc;
+}
+}  // namespace
+
+int fft3d_forward(fftpde_ctx* ctx, const void* in, void* out, int nx, int ny, int nz, int batch, int dtype,
+                  fftpde_stream stream) {
+  const int rc = check3d(ctx, nx, ny, nz, batch, dtype, in, out);
+  if (rc != FFTPDE_OK) return rc;
+  Context* c = reinterpret_cast<Context*>(ctx);
+  DeviceGuard g(c->device);
+  return run_transform3d(c, dtype, false, in, out, nx, ny, nz, batch, static_cast<hipStream_t>(stream));
+}
+
+int fft3d_inverse(fftpde_ctx* ctx, const void* in, void* out, int nx, int ny, int nz, int batch, int dtype,
+                  fftpde_stream stream) {
+  const int rc = check3d(ctx, nx, ny, nz, batch, dtype, in, out);
+  if (rc != FFTPDE_OK) return rc;
+  Context* c = reinterpret_cast<Context*>(ctx);
+  DeviceGuard g(c->device);
+  return run_transform3d(c, dtype, true, in, out, nx, ny, nz, batch, static_cast<hipStream_t>(stream));
+}
+
+int solve_poisson_3d(fftpde_ctx* ctx, const void* s_in, void* u, int nx, int ny, int nz, int batch, double lx,
+                     double ly, double lz, int dtype, fftpde_stream stream) {
+  int rc = check3d(ctx, nx, ny, nz, batch, dtype, s_in, u);
+  if (rc == FFTPDE_OK && !(finite_pos(lx) && finite_pos(ly) && finite_pos(lz))) rc = FFTPDE_EINVAL;
+  if (rc != FFTPDE_OK) return rc;
+  Context* c = reinterpret_cast<Context*>(ctx);
+  DeviceGuard g(c->device);
+  return run_solve3d(c, dtype, FFTPDE_POISSON, s_in, u, nx, ny, nz, batch, lx, ly, lz, 0.0, 0.0,
+                     static_cast<hipStream_t>(stream));
+}
+
+int solve_diffusion_3d(fftpde_ctx* ctx, const void* u0, void* u, int nx, int ny, int nz, int batch, double lx,
+                       double ly, double lz, double kappa, double t, int dtype, fftpde_stream stream) {
+  int rc = check3d(ctx, nx, ny, nz, batch, dtype, u0, u);
+  if (rc == FFTPDE_OK && !(finite_pos(lx) && finite_pos(ly) && finite_pos(lz))) rc = FFTPDE_EINVAL;
+  if (rc == FFTPDE_OK && !(std::isfinite(kappa) && kappa >= 0.0 && std::isfinite(t) && t >= 0.0)) rc = FFTPDE_EINVAL;
+  if (rc != FFTPDE_OK) return rc;
+  Context* c = reinterpret_cast<Context*>(ctx);
+  DeviceGuard g(c->device);
+  return run_solve3d(c, dtype, FFTPDE_DIFFUSION, u0, u, nx, ny, nz, batch, lx, ly, lz, kappa, t,
+                     static_cast<hipStream_t>(stream));
+}
+
+int solve_wave_3d(fftpde_ctx* ctx, const void* u0, void* u, int nx, int ny, int nz, int batch, double lx, double ly,
+                  double lz, double c_speed, double t, int dtype, fftpde_stream stream) {
+  int rc = check3d(ctx, nx, ny, nz, batch, dtype, u0, u);
+  if (rc == FFTPDE_OK && !(finite_pos(lx) && finite_pos(ly) && finite_pos(lz))) rc = FFTPDE_EINVAL;
+  if (rc == FFTPDE_OK && !(std::isfinite(c_speed) && c_speed >= 0.0 && std::isfinite(t))) rc = FFTPDE_EINVAL;
+  if (rc != FFTPDE_OK) return rc;
+  Context* c = reinterpret_cast<Context*>(ctx);
+  DeviceGuard g(c->device);
+  return run_solve3d(c, dtype, FFTPDE_WAVE, u0, u, nx, ny, nz, batch, lx, ly, lz, c_speed, t,
+                     static_cast<hipStream_t>(stream));
+}
+
 int fftpde_wave_rk4(fftpde_ctx* ctx, const fftpde_orbit_source* src, const void* f, const void* g0, void* u, void* v,
                     int nx, int ny, int batch, double x0, double y0, double lx, double ly, double c_speed, double t0,
                     double dt, int steps, int dtype, fftpde_stream stream) {

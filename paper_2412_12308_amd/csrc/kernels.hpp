@@ -48,6 +48,12 @@ struct SymParams {
   double hx, hy;    // wave: 2 c t / lx, 2 c t / ly, so w t / pi = sqrt((hx a')^2 + (hy b')^2)
   double c, t;      // wave: speed and time (for sin(w t)/w and w); diffusion with a source: kappa and time
   double scale;     // 1 / (nx ny) for modes that end with the inverse
+  // 3D solves (the pass along z, whose columns are the nx*ny points of a z
+  // plane): lx3 = log2 nx > 0 splits the column index a into x = a mod nx and
+  // y = a / nx; ky3s = 2 pi / ly and hy3 = 2 c t / ly scale y, while kxs, hx
+  // scale x and kys, hy scale z.  lx3 = 0: 2D.
+  int lx3;
+  double ky3s, hy3;
 };
 
 // A load of streamed data read once: the non-temporal hint keeps it from
@@ -157,12 +163,19 @@ struct Symbol<T, kSymPoisson> {
   bool a0;
   int logny;
   __device__ __forceinline__ Symbol(const SymParams& p, int a) {
-    const int ai = signed_index(a, p.lognx);
-    const T kx = T(p.kxs) * T(ai);
-    kx2 = kx * kx;
+    if (p.lx3 > 0) {
+      const int xi = signed_index(a & ((1 << p.lx3) - 1), p.lx3), yi = signed_index(a >> p.lx3, p.lognx - p.lx3);
+      const T kx = T(p.kxs) * T(xi), ky = T(p.ky3s) * T(yi);
+      kx2 = kx * kx + ky * ky;
+      a0 = xi == 0 && yi == 0;
+    } else {
+      const int ai = signed_index(a, p.lognx);
+      const T kx = T(p.kxs) * T(ai);
+      kx2 = kx * kx;
+      a0 = ai == 0;
+    }
     kys = T(p.kys);
     nscale = -T(p.scale);
-    a0 = ai == 0;
     logny = p.logny;
   }
   __device__ __forceinline__ T operator()(int b) const {
@@ -183,9 +196,15 @@ struct Symbol<T, kSymDiffusion> {
   T scale;
   int logny;
   __device__ __forceinline__ Symbol(const SymParams& p, int a) {
-    const double kx = p.kxs * signed_index(a, p.lognx);
     kt = p.kt;
-    ex = kt * kx * kx;
+    if (p.lx3 > 0) {
+      const double kx = p.kxs * signed_index(a & ((1 << p.lx3) - 1), p.lx3);
+      const double ky = p.ky3s * signed_index(a >> p.lx3, p.lognx - p.lx3);
+      ex = kt * fma(kx, kx, ky * ky);
+    } else {
+      const double kx = p.kxs * signed_index(a, p.lognx);
+      ex = kt * kx * kx;
+    }
     kys = p.kys;
     scale = T(p.scale);
     logny = p.logny;
@@ -206,8 +225,14 @@ struct Symbol<T, kSymWave> {
   T scale;
   int logny;
   __device__ __forceinline__ Symbol(const SymParams& p, int a) {
-    const double hx = p.hx * signed_index(a, p.lognx);
-    hx2 = hx * hx;
+    if (p.lx3 > 0) {
+      const double hx = p.hx * signed_index(a & ((1 << p.lx3) - 1), p.lx3);
+      const double hyy = p.hy3 * signed_index(a >> p.lx3, p.lognx - p.lx3);
+      hx2 = fma(hx, hx, hyy * hyy);
+    } else {
+      const double hx = p.hx * signed_index(a, p.lognx);
+      hx2 = hx * hx;
+    }
     hy = p.hy;
     scale = T(p.scale);
     logny = p.logny;

@@ -278,6 +278,84 @@ int solve_real_pairs(Context* c, const void* in, const void* in2, void* out, voi
   return FFTPDE_OK;
 }
 
+// ---------------------------------------------------------------------------
+// 3D: x rows, then y columns of every z plane, then z columns (the field seen
+// as nz rows of nx*ny columns); a solve fuses its symbol into the z pass and
+// runs the y and x passes back.  Five passes, all row-major.
+// ---------------------------------------------------------------------------
+SymParams make_sym3d(int op, int nx, int ny, int nz, double lx, double ly, double lz, double coef, double t) {
+  SymParams p = make_sym(op, nx * ny, nz, lx, lz, coef, t);
+  p.lx3 = ilog2(nx);
+  p.kxs = 2.0 * kPi / lx;
+  p.ky3s = 2.0 * kPi / ly;
+  p.kys = 2.0 * kPi / lz;
+  if (op == kSymWave) {
+    p.hx = 2.0 * coef * t / lx;
+    p.hy3 = 2.0 * coef * t / ly;
+    p.hy = 2.0 * coef * t / lz;
+  }
+  p.scale = 1.0 / ((double)nx * (double)ny * (double)nz);
+  return p;
+}
+
+template <typename T>
+int pass3d(Context* c, const void* in, void* out, int nx, int ny, int nz, int batch, const SymParams* sym, bool inverse,
+           hipStream_t s) {
+  const int lx = ilog2(nx), ly = ilog2(ny), lz = ilog2(nz);
+  const long long pts = (long long)nx * ny * nz;
+  const size_t field = sizeof(cx<T>) * (size_t)pts;
+  const int dt = sizeof(T) == 4 ? FFTPDE_C64 : FFTPDE_C128;
+  const long long cb = c->chunk_bytes_for(dt, lx, ly);
+  long long chunk = cb > 0 ? std::max<long long>(1, cb / (long long)field) : batch;
+  chunk = std::min<long long>(chunk, batch);
+  SymParams unit = make_sym(kSymScale, nx, ny, 1.0, 1.0, 0.0, 0.0);  // plain transforms, scale 1
+  unit.scale = 1.0;
+  for (long long b0 = 0; b0 < batch; b0 += chunk) {
+    const long long nb = std::min<long long>(chunk, batch - b0);
+    const void* ib = static_cast<const char*>(in) + field * b0;
+    void* ob = static_cast<char*>(out) + field * b0;
+    const long long rows = (long long)ny * nz * nb;
+    int rc = FFTPDE_OK;
+    if (!inverse || sym) {
+      // forward x, forward y per plane
+      rc = row_pass<T>(c, ib, ob, lx, ly + lz, rows, false, 1.0, s);
+      if (rc == FFTPDE_OK) rc = col_pass<T>(c, ob, nullptr, ob, nullptr, lx, ly, nb * nz, kColForward, unit, 1, s);
+    }
+    if (rc == FFTPDE_OK) {
+      if (sym) {
+        rc = col_pass<T>(c, ob, nullptr, ob, nullptr, lx + ly, lz, nb, kColFwdMulInv, *sym, 1, s);
+      } else if (!inverse) {
+        rc = col_pass<T>(c, ob, nullptr, ob, nullptr, lx + ly, lz, nb, kColForward, unit, 1, s);
+      } else {
+        SymParams inv = unit;
+        inv.scale = 1.0 / (double)pts;
+        rc = col_pass<T>(c, ib, nullptr, ob, nullptr, lx + ly, lz, nb, kColInverse, inv, 1, s);
+      }
+    }
+    if (rc == FFTPDE_OK && (inverse || sym)) {
+      // inverse y per plane, inverse x
+      rc = col_pass<T>(c, ob, nullptr, ob, nullptr, lx, ly, nb * nz, kColInverse, unit, 1, s);
+      if (rc == FFTPDE_OK) rc = row_pass<T>(c, ob, ob, lx, ly + lz, rows, true, 1.0, s);
+    }
+    if (rc != FFTPDE_OK) return rc;
+  }
+  return FFTPDE_OK;
+}
+
+int run_transform3d(Context* c, int dtype, bool inverse, const void* in, void* out, int nx, int ny, int nz, int batch,
+                    hipStream_t s) {
+  return dtype == FFTPDE_C64 ? pass3d<float>(c, in, out, nx, ny, nz, batch, nullptr, inverse, s)
+                             : pass3d<double>(c, in, out, nx, ny, nz, batch, nullptr, inverse, s);
+}
+
+int run_solve3d(Context* c, int dtype, int op, const void* in, void* out, int nx, int ny, int nz, int batch, double lx,
+                double ly, double lz, double coef, double t, hipStream_t s) {
+  const int sop = op == FFTPDE_POISSON ? kSymPoisson : op == FFTPDE_DIFFUSION ? kSymDiffusion : kSymWave;
+  const SymParams sym = make_sym3d(sop, nx, ny, nz, lx, ly, lz, coef, t);
+  return dtype == FFTPDE_C64 ? pass3d<float>(c, in, out, nx, ny, nz, batch, &sym, false, s)
+                             : pass3d<double>(c, in, out, nx, ny, nz, batch, &sym, false, s);
+}
+
 // Solves with a source constant in time: forward row passes of f, g (if
 // given) and s into per-stream scratch spectra, one three-field column pass
 // (forward, coefficients, inverse), inverse row passes of u (and v).  Complex

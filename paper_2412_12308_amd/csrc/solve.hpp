@@ -50,6 +50,12 @@ int run_transform(Context* c, int dtype, bool inverse, const void* in, void* out
 int run_solve(Context* c, int dtype, int op, const void* in, const void* in2, void* out, void* out2, int nx, int ny,
               int batch, double lx, double ly, double coef, double t, hipStream_t s);
 
+// 3D fields [nz][ny][nx]: transforms and the three solves (no velocity).
+int run_transform3d(Context* c, int dtype, bool inverse, const void* in, void* out, int nx, int ny, int nz, int batch,
+                    hipStream_t s);
+int run_solve3d(Context* c, int dtype, int op, const void* in, void* out, int nx, int ny, int nz, int batch, double lx,
+                double ly, double lz, double coef, double t, hipStream_t s);
+
 // A solve with a source constant in time (op = FFTPDE_DIFFUSION: f, src ->
 // u; FFTPDE_WAVE: f, g (may be null), src -> u, v (may be null)); coef is
 // kappa or the wave speed.  Complex dtypes, or real ones in pairs.

@@ -291,3 +291,20 @@ def test_wave_rk4_rejects_bad_arguments():
     assert L.fftpde_wave_rk4(*args(ctypes.byref(ok), c=-1.0)) == fp.EINVAL
     assert L.fftpde_wave_rk4(*args(ctypes.byref(ok), v=P)) == fp.EINVAL
     assert L.fftpde_wave_rk4(*args(ctypes.byref(ok), dtype=2)) == fp.EINVAL   # complex only
+
+
+@pytest.mark.parametrize("nx,ny,nz", [(3, 4, 4), (4, 4, 1), (4, 4, 8192), (4096, 8192, 2), (4096, 4096, 0)])
+def test_3d_entry_points_reject_bad_shapes(nx, ny, nz):
+    fp, L = _lib()
+    assert L.fft3d_forward(DUMMY, P, P, nx, ny, nz, 1, 0, None) == fp.EINVAL
+    assert L.fft3d_inverse(DUMMY, P, P, nx, ny, nz, 1, 1, None) == fp.EINVAL
+    assert L.solve_poisson_3d(DUMMY, P, P, nx, ny, nz, 1, 1.0, 1.0, 1.0, 0, None) == fp.EINVAL
+
+
+def test_3d_solves_reject_bad_coefficients_and_real_dtypes():
+    fp, L = _lib()
+    assert L.solve_poisson_3d(DUMMY, P, P, 4, 4, 4, 1, 1.0, 1.0, 0.0, 0, None) == fp.EINVAL
+    assert L.solve_diffusion_3d(DUMMY, P, P, 4, 4, 4, 1, 1.0, 1.0, 1.0, 0.1, -1.0, 0, None) == fp.EINVAL
+    assert L.solve_wave_3d(DUMMY, P, P, 4, 4, 4, 1, 1.0, 1.0, 1.0, -1.0, 0.5, 0, None) == fp.EINVAL
+    assert L.fft3d_forward(DUMMY, P, P, 4, 4, 4, 1, 2, None) == fp.EINVAL
+    assert L.fft3d_forward(None, P, P, 4, 4, 4, 1, 0, None) == fp.EINVAL
