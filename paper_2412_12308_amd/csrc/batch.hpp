@@ -7,10 +7,12 @@
 // job's symbol and run the y inverse (out -> out), and row tiles of x inverse
 // transforms (out -> out).  All tiles of all jobs sit in one queue, first
 // every row-forward tile, then every column tile, then every row-inverse
-// tile, largest jobs first.  Workgroups pop items with an atomic counter; an
-// item of step s waits until its job's step s-1 tiles are all published (a
-// per-job counter).  An item only ever waits on items earlier in the queue, so
-// the queue drains whatever the number of resident workgroups (see the
+// tile, largest jobs first.  Workgroups claim a few consecutive items at a
+// time with one atomic counter (the next claim travels while the current one
+// is worked on) and work through them in queue order; an item of step s
+// waits until its job's step s-1 tiles are all published (a per-job
+// counter).  An item only ever waits on items earlier in the queue, so the
+// queue drains whatever the number of resident workgroups (see the
 // publication rule in batch.hip).  Each wait is still bounded and reports a
 // timeout through an error flag instead of spinning forever.
 #pragma once
