@@ -11,6 +11,10 @@
  *     even/odd split and the butterfly pair Eq. (FFTpairodd) and
  *     Eq. (FFTpairodd_2)), recursing down to length 1.  Twiddles
  *     w^k = exp(sign * 2 pi i k / N) come straight from libm cos/sin.
+ *   - Lengths that are not powers of two (Sec. II.D restricts the method to
+ *     N = 2^m; other lengths are an extension): the sum of Eq. (DFT)
+ *     evaluated term by term, O(N^2) per line, with the product j k reduced
+ *     modulo N in integers before the angle 2 pi (j k mod N)/N is formed.
  *   - Sign convention: the forward transform uses exp(-2 pi i ...), the sign
  *     of the row-column derivation in Sec. II.D; the inverse uses
  *     exp(+2 pi i ...) and the 1/N factor of the iDFT in Sec. II.B.  (The
@@ -88,14 +92,43 @@ static void fft_rec(const cplx *in, size_t stride, cplx *out, int n, int sign)
 
 static int is_pow2(int n) { return n >= 1 && (n & (n - 1)) == 0; }
 
+/* The DFT sum itself for any length n: out[k] = sum_j in[j stride]
+ * exp(sign 2 pi i (j k mod n) / n). */
+static void dft_direct(const cplx *in, size_t stride, cplx *out, int n, int sign)
+{
+    for (int k = 0; k < n; k++) {
+        double re = 0.0, im = 0.0;
+        for (int j = 0; j < n; j++) {
+            long long m = ((long long)j * k) % n;
+            double ang = sign * 2.0 * PI * (double)m / (double)n;
+            double wr = cos(ang), wi = sin(ang);
+            cplx x = in[(size_t)j * stride];
+            re += wr * x.re - wi * x.im;
+            im += wr * x.im + wi * x.re;
+        }
+        out[k].re = re;
+        out[k].im = im;
+    }
+}
+
+/* One line: the radix-2 recursion for powers of two, the plain sum else. */
+static void transform_line(const cplx *in, size_t stride, cplx *out, int n, int sign)
+{
+    if (is_pow2(n))
+        fft_rec(in, stride, out, n, sign);
+    else
+        dft_direct(in, stride, out, n, sign);
+}
+
 /* Unnormalised 1D transform with exponent sign `sign` (-1 forward, +1 for
- * the unscaled inverse sum).  Returns 0, or -1 for a bad length. */
+ * the unscaled inverse sum), any length n >= 1.  Returns 0, or -1 for a bad
+ * argument. */
 int oracle_fft1d(const double *in, double *out, int n, int sign)
 {
-    if (!is_pow2(n) || (sign != 1 && sign != -1)) return -1;
+    if (n < 1 || (sign != 1 && sign != -1)) return -1;
     cplx *tmp = (cplx *)malloc(sizeof(cplx) * (size_t)n);
     if (!tmp) return -2;
-    fft_rec((const cplx *)in, 1, tmp, n, sign);
+    transform_line((const cplx *)in, 1, tmp, n, sign);
     memcpy(out, tmp, sizeof(cplx) * (size_t)n);
     free(tmp);
     return 0;
@@ -126,11 +159,11 @@ static void *line_worker(void *arg)
     for (int line = jb->begin; line < jb->end; line++) {
         if (jb->axis == 0) {
             cplx *row = jb->data + (size_t)line * jb->nx;
-            fft_rec(row, 1, dst, len, jb->sign);
+            transform_line(row, 1, dst, len, jb->sign);
             memcpy(row, dst, sizeof(cplx) * (size_t)len);
         } else {
             for (int k = 0; k < len; k++) src[k] = jb->data[(size_t)k * jb->nx + line];
-            fft_rec(src, 1, dst, len, jb->sign);
+            transform_line(src, 1, dst, len, jb->sign);
             for (int k = 0; k < len; k++) jb->data[(size_t)k * jb->nx + line] = dst[k];
         }
     }
@@ -172,10 +205,11 @@ static int run_lines(cplx *data, int nx, int ny, int sign, int axis, int threads
     return rc;
 }
 
-/* Unnormalised 2D transform, exponent sign `sign`, in -> out (may alias). */
+/* Unnormalised 2D transform, exponent sign `sign`, in -> out (may alias);
+ * any nx, ny >= 1. */
 int oracle_fft2d(const double *in, double *out, int nx, int ny, int sign, int threads)
 {
-    if (!is_pow2(nx) || !is_pow2(ny) || (sign != 1 && sign != -1)) return -1;
+    if (nx < 1 || ny < 1 || (sign != 1 && sign != -1)) return -1;
     size_t p = (size_t)nx * ny;
     if (out != in) memmove(out, in, sizeof(cplx) * p);
     int rc = run_lines((cplx *)out, nx, ny, sign, 0, threads);
