@@ -180,8 +180,12 @@ def test_threads_do_not_change_results():
     assert np.array_equal(a, b)
 
 
-def test_rejects_non_power_of_two():
+def test_rejects_empty_lengths_and_bad_signs():
+    # any length >= 1 is accepted (lengths that are not powers of two have
+    # their own pins); empty axes and exponent signs other than +-1 are not
     with pytest.raises(ValueError):
-        oracle.fft1d(np.ones(12))
+        oracle.fft1d(np.ones(0))
     with pytest.raises(ValueError):
-        oracle.fft2d(np.ones((6, 8)))
+        oracle.fft2d(np.ones((0, 8)))
+    with pytest.raises(ValueError):
+        oracle.fft1d(np.ones(8), sign=2)
