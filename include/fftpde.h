@@ -14,7 +14,14 @@
  *    follows Sec. II.B/II.D: x_j = x0 + j*lx/nx, j = 0..nx-1 (periodic,
  *    endpoint excluded); the origin x0 never enters a solve.
  *  Sizes.  nx and ny are powers of two in [2, 4096] (the FFT's 2^m
- *    restriction, Sec. II.C); batch >= 1.
+ *    restriction, Sec. II.C); batch >= 1.  fft2d_forward, fft2d_inverse,
+ *    solve_poisson, solve_diffusion and solve_wave also take sides that are
+ *    not powers of two, for complex dtypes: any side in [2, 4096] whose prime
+ *    factors are 2, 3, 5 and 7 (the mixed-radix path: Stockham stages of
+ *    radix 2, 3, 4, 5, 7 and 8, an extension of Sec. II.D; EINVAL for other
+ *    sides and for real dtypes).  The first call for a new side allocates
+ *    and uploads that length's twiddle table (kept until the context is
+ *    destroyed).  Every other entry point takes powers of two only.
  *  Pointers.  Every field pointer is a DEVICE pointer on the context's GPU,
  *    aligned to the element size.  The caller owns every field buffer.
  *    in == out (in place) is allowed wherever an input and an output have the
@@ -28,8 +35,9 @@
  *    row-column derivation of Sec. II.D; the paper's Eq. (DFT) writes the
  *    opposite sign, which only reverses the frequency index and leaves every
  *    solve below unchanged (their symbols are even in k).
- *  Wavenumbers.  k_x = 2 pi a'/lx with a' = a for a < nx/2, else a - nx
- *    (the shifted frequencies of Sec. II.B and II.D); likewise k_y;
+ *  Wavenumbers.  k_x = 2 pi a'/lx with a' = a for 2a < nx, else a - nx
+ *    (the shifted frequencies of Sec. II.B and II.D; a = nx/2 gives -nx/2
+ *    on even sides, odd sides have no such slot); likewise k_y;
  *    |k|^2 = k_x^2 + k_y^2.
  *  Status.  Every function returns an int status (FFTPDE_OK = 0, negative =
  *    error); no C++ exception crosses this boundary.  Arguments are checked

@@ -440,6 +440,7 @@ int fftpde_destroy(fftpde_ctx* ctx) {
   if (c->tw32) (void)hipFree(c->tw32);
   for (auto& w : c->work)
     if (w.second.p) (void)hipFree(w.second.p);
+  for (auto& t : c->mr_tw) (void)hipFree(t.second.f64);
   for (auto& t : c->timed) {
     (void)hipEventDestroy(t.start);
     (void)hipEventDestroy(t.stop);
@@ -456,13 +457,18 @@ int fftpde_destroy(fftpde_ctx* ctx) {
 // ---------------------------------------------------------------------------
 namespace {
 
-int check_common(fftpde_ctx* ctx, int nx, int ny, int batch, int dtype, bool real_ok = false) {
-  if (!ctx) return FFTPDE_EINVAL;
-  if (!pow2_side(nx) || !pow2_side(ny) || batch < 1) return FFTPDE_EINVAL;
+// mixed_ok: sides may also be 7-smooth (the mixed-radix path; complex
+// dtypes only).
+int check_common(fftpde_ctx* ctx, int nx, int ny, int batch, int dtype, bool real_ok = false, bool mixed_ok = false) {
+  if (!ctx || batch < 1) return FFTPDE_EINVAL;
   const bool real = dtype == FFTPDE_R32 || dtype == FFTPDE_R64;
   if (dtype != FFTPDE_C64 && dtype != FFTPDE_C128 && !(real_ok && real)) return FFTPDE_EINVAL;
-  return FFTPDE_OK;
+  if (pow2_side(nx) && pow2_side(ny)) return FFTPDE_OK;
+  if (mixed_ok && !real && mixed_side(nx) && mixed_side(ny)) return FFTPDE_OK;
+  return FFTPDE_EINVAL;
 }
+
+bool is_mixed(int nx, int ny) { return !pow2_side(nx) || !pow2_side(ny); }
 
 int check_field(const void* p, int dtype) { return (p && aligned(p, dtype)) ? FFTPDE_OK : FFTPDE_EINVAL; }
 
@@ -474,42 +480,49 @@ extern "C" {
 
 int fft2d_forward(fftpde_ctx* ctx, const void* in, void* out, int nx, int ny, int batch, int dtype,
                   fftpde_stream stream) {
-  int rc = check_common(ctx, nx, ny, batch, dtype);
+  int rc = check_common(ctx, nx, ny, batch, dtype, false, true);
   if (rc == FFTPDE_OK) rc = check_field(in, dtype);
   if (rc == FFTPDE_OK) rc = check_field(out, dtype);
   if (rc != FFTPDE_OK) return rc;
   Context* c = reinterpret_cast<Context*>(ctx);
   DeviceGuard g(c->device);
+  if (is_mixed(nx, ny))
+    return run_mixed_transform(c, dtype, false, in, out, nx, ny, batch, static_cast<hipStream_t>(stream));
   return run_transform(c, dtype, false, in, out, nx, ny, batch, static_cast<hipStream_t>(stream));
 }
 
 int fft2d_inverse(fftpde_ctx* ctx, const void* in, void* out, int nx, int ny, int batch, int dtype,
                   fftpde_stream stream) {
-  int rc = check_common(ctx, nx, ny, batch, dtype);
+  int rc = check_common(ctx, nx, ny, batch, dtype, false, true);
   if (rc == FFTPDE_OK) rc = check_field(in, dtype);
   if (rc == FFTPDE_OK) rc = check_field(out, dtype);
   if (rc != FFTPDE_OK) return rc;
   Context* c = reinterpret_cast<Context*>(ctx);
   DeviceGuard g(c->device);
+  if (is_mixed(nx, ny))
+    return run_mixed_transform(c, dtype, true, in, out, nx, ny, batch, static_cast<hipStream_t>(stream));
   return run_transform(c, dtype, true, in, out, nx, ny, batch, static_cast<hipStream_t>(stream));
 }
 
 int solve_poisson(fftpde_ctx* ctx, const void* s_in, void* u, int nx, int ny, int batch, double lx, double ly,
                   int dtype, fftpde_stream stream) {
-  int rc = check_common(ctx, nx, ny, batch, dtype, true);
+  int rc = check_common(ctx, nx, ny, batch, dtype, true, true);
   if (rc == FFTPDE_OK) rc = check_field(s_in, dtype);
   if (rc == FFTPDE_OK) rc = check_field(u, dtype);
   if (rc == FFTPDE_OK && !(finite_pos(lx) && finite_pos(ly))) rc = FFTPDE_EINVAL;
   if (rc != FFTPDE_OK) return rc;
   Context* c = reinterpret_cast<Context*>(ctx);
   DeviceGuard g(c->device);
+  if (is_mixed(nx, ny))
+    return run_mixed_solve(c, dtype, FFTPDE_POISSON, s_in, nullptr, u, nullptr, nx, ny, batch, lx, ly, 0.0, 0.0,
+                           static_cast<hipStream_t>(stream));
   return run_solve(c, dtype, FFTPDE_POISSON, s_in, nullptr, u, nullptr, nx, ny, batch, lx, ly, 0.0, 0.0,
                    static_cast<hipStream_t>(stream));
 }
 
 int solve_diffusion(fftpde_ctx* ctx, const void* u0, void* u, int nx, int ny, int batch, double lx, double ly,
                     double kappa, double t, int dtype, fftpde_stream stream) {
-  int rc = check_common(ctx, nx, ny, batch, dtype, true);
+  int rc = check_common(ctx, nx, ny, batch, dtype, true, true);
   if (rc == FFTPDE_OK) rc = check_field(u0, dtype);
   if (rc == FFTPDE_OK) rc = check_field(u, dtype);
   if (rc == FFTPDE_OK && !(finite_pos(lx) && finite_pos(ly))) rc = FFTPDE_EINVAL;
@@ -518,6 +531,9 @@ int solve_diffusion(fftpde_ctx* ctx, const void* u0, void* u, int nx, int ny, in
   if (rc != FFTPDE_OK) return rc;
   Context* c = reinterpret_cast<Context*>(ctx);
   DeviceGuard g(c->device);
+  if (is_mixed(nx, ny))
+    return run_mixed_solve(c, dtype, FFTPDE_DIFFUSION, u0, nullptr, u, nullptr, nx, ny, batch, lx, ly, kappa, t,
+                           static_cast<hipStream_t>(stream));
   return run_solve(c, dtype, FFTPDE_DIFFUSION, u0, nullptr, u, nullptr, nx, ny, batch, lx, ly, kappa, t,
                    static_cast<hipStream_t>(stream));
 }
@@ -647,7 +663,7 @@ int fftpde_wave_rk4(fftpde_ctx* ctx, const fftpde_orbit_source* src, const void*
 
 int solve_wave(fftpde_ctx* ctx, const void* u0, const void* v0, void* u, void* v, int nx, int ny, int batch,
                double lx, double ly, double c_speed, double t, int dtype, fftpde_stream stream) {
-  int rc = check_common(ctx, nx, ny, batch, dtype, true);
+  int rc = check_common(ctx, nx, ny, batch, dtype, true, true);
   if (rc == FFTPDE_OK) rc = check_field(u0, dtype);
   if (rc == FFTPDE_OK) rc = check_field(u, dtype);
   if (rc == FFTPDE_OK && v0) rc = check_field(v0, dtype);
@@ -659,6 +675,9 @@ int solve_wave(fftpde_ctx* ctx, const void* u0, const void* v0, void* u, void* v
   if (rc != FFTPDE_OK) return rc;
   Context* c = reinterpret_cast<Context*>(ctx);
   DeviceGuard g(c->device);
+  if (is_mixed(nx, ny))
+    return run_mixed_solve(c, dtype, FFTPDE_WAVE, u0, v0, u, v, nx, ny, batch, lx, ly, c_speed, t,
+                           static_cast<hipStream_t>(stream));
   return run_solve(c, dtype, FFTPDE_WAVE, u0, v0, u, v, nx, ny, batch, lx, ly, c_speed, t,
                    static_cast<hipStream_t>(stream));
 }

@@ -92,6 +92,14 @@ struct Context {
     return it == tiled_for.end() ? tiled_bytes : it->second;
   }
 
+  // Twiddle tables of the mixed-radix path, exp(-2 pi i e/n) for e < n, per
+  // line length n (made on first use; one allocation, f64 at its start).
+  struct MrTables {
+    cx<double>* f64;
+    cx<float>* f32;
+  };
+  std::unordered_map<int, MrTables> mr_tw;
+
   const RowVariant* row_variant(int dtype, int logn) const;
   const ColVariant* col_variant(int dtype, int logn, int nf) const;
   int workspace(size_t bytes, hipStream_t s, void** p);

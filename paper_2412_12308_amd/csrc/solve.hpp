@@ -73,4 +73,13 @@ int run_materialize(Context* c, int dtype, int kind, const void* F, const void* 
 int run_diag(Context* c, int dtype, int kind, const void* F, const void* G, int nx, int ny, int batch, double lx,
              double ly, double coef, long long n0, double dt, int nt, double* scratch, double* out, hipStream_t s);
 
+// Sides of the mixed-radix path: 7-smooth, 2..4096.  Transforms and the
+// three solves (the wave with or without velocity) on complex fields whose
+// sides are not both powers of two.
+bool mixed_side(int n);
+int run_mixed_transform(Context* c, int dtype, bool inverse, const void* in, void* out, int nx, int ny, int batch,
+                        hipStream_t s);
+int run_mixed_solve(Context* c, int dtype, int op, const void* in, const void* in2, void* out, void* out2, int nx,
+                    int ny, int batch, double lx, double ly, double coef, double t, hipStream_t s);
+
 }  // namespace fftpde

@@ -1,0 +1,153 @@
+"""GPU transforms and solves on sides that are not powers of two (7-smooth
+sides, the mixed-radix path) against the FP64 oracle, which evaluates the
+sum of Eq. (DFT) directly for such lengths.
+
+Shapes cover every radix (2, 3, 4, 5, 7, 8), odd and even sides, rows and
+columns of one point short of a tile, ragged last column tiles, one power-
+of-two side with one other side, the largest 7-smooth sides below 4096, and
+batches; the three solves include the wave with an initial velocity and the
+velocity output."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_helpers import TOL_FP64, as_oracle_input, rel_err_vs_input, say, to_dev, to_host, tol
+
+pytestmark = pytest.mark.gpu
+THREADS = oracle.default_threads()
+
+SHAPES = [(12, 20), (30, 96), (96, 64), (64, 45), (105, 7), (3, 2), (2, 3), (100, 100), (343, 6),
+          (6, 343), (1000, 24), (125, 81), (49, 1536)]
+
+
+@pytest.fixture(scope="module")
+def fp():
+    import paper_2412_12308_amd as fp
+    return fp
+
+
+def _field(nx, ny, batch, seed):
+    shape = (batch, ny, nx) if batch > 1 else (ny, nx)
+    return W.random_field(shape, seed=seed)
+
+
+def _fields(x):
+    return [x] if x.ndim == 2 else list(x)
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("nx,ny", SHAPES)
+def test_fft2d_forward_and_inverse_vs_oracle(fp, nx, ny, dt):
+    say(f"mixed fft2d {nx}x{ny} {dt}")
+    x = _field(nx, ny, 1, nx * 7 + ny)
+    X = to_host(fp.fft2d_forward(to_dev(x, dt)))
+    ref = oracle.fft2d(as_oracle_input(x, dt), threads=THREADS)
+    assert oracle.rel_l2(X, ref) <= tol(dt, nx, ny, 1)
+    y = to_host(fp.fft2d_inverse(to_dev(ref, dt)))
+    ref_i = oracle.ifft2d(as_oracle_input(ref, dt), threads=THREADS)
+    assert oracle.rel_l2(y, ref_i) <= tol(dt, nx, ny, 1)
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("nx,ny", [(4032, 5), (5, 4032), (4050, 3), (3, 3969)])
+def test_largest_sides_vs_oracle(fp, nx, ny, dt):
+    say(f"mixed large side {nx}x{ny} {dt}")
+    x = _field(nx, ny, 1, nx + 3 * ny)
+    X = to_host(fp.fft2d_forward(to_dev(x, dt)))
+    ref = oracle.fft2d(as_oracle_input(x, dt), threads=THREADS)
+    assert oracle.rel_l2(X, ref) <= tol(dt, nx, ny, 1)
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_batched_and_in_place(fp, dt):
+    nx, ny, b = 60, 35, 3
+    say(f"mixed batch {nx}x{ny}x{b} {dt}")
+    x = _field(nx, ny, b, 11)
+    d = to_dev(x, dt)
+    fp.fft2d_forward(d, out=d)
+    X = to_host(d)
+    for k, f in enumerate(_fields(x)):
+        ref = oracle.fft2d(as_oracle_input(f, dt), threads=THREADS)
+        assert oracle.rel_l2(X[k], ref) <= tol(dt, nx, ny, 1)
+    s = W.random_field((b, ny, nx), seed=12)
+    d = to_dev(s, dt)
+    fp.solve_poisson(d, 1.3, 0.7, out=d)
+    u = to_host(d)
+    for k in range(b):
+        ref = oracle.solve_poisson(as_oracle_input(s[k], dt), 1.3, 0.7, threads=THREADS)
+        assert oracle.rel_l2(u[k], ref) <= tol(dt, nx, ny, 2)
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("nx,ny,lx,ly", [(96, 30, 1.0, 2.0), (45, 64, 0.5, 1.0), (210, 125, 3.0, 1.0)])
+def test_solves_vs_oracle(fp, nx, ny, lx, ly, dt):
+    say(f"mixed solves {nx}x{ny} {dt}")
+    k = max(1, min(8, nx // 2 - 1, ny // 2 - 1))
+    ms = W.poisson_source(nx, ny, seed=nx + ny, lx=lx, ly=ly, kmax=k)
+    s = ms.field
+    u = to_host(fp.solve_poisson(to_dev(s, dt), lx, ly))
+    ref = oracle.solve_poisson(as_oracle_input(s, dt), lx, ly, threads=THREADS)
+    assert oracle.rel_l2(u, ref) <= tol(dt, nx, ny, 2)
+    u0 = W.random_field((ny, nx), seed=3)
+    kappa, t = 0.01, 0.3
+    d = to_host(fp.solve_diffusion(to_dev(u0, dt), kappa, t, lx, ly))
+    ref = oracle.solve_diffusion(as_oracle_input(u0, dt), lx, ly, kappa, t, threads=THREADS)
+    assert rel_err_vs_input(d, ref, np.linalg.norm(u0)) <= tol(dt, nx, ny, 2)
+    c, tw = 0.8, 0.45
+    w, _ = fp.solve_wave(to_dev(u0, dt), None, c, tw, lx, ly)
+    ref, _ = oracle.solve_wave(as_oracle_input(u0, dt), None, lx, ly, c, tw, threads=THREADS)
+    assert rel_err_vs_input(to_host(w), ref, np.linalg.norm(u0)) <= tol(dt, nx, ny, 2)
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("with_v0,want_v,t", [(True, True, 0.37), (True, False, 0.37), (False, True, 0.37),
+                                              (True, True, -0.2), (True, True, 0.0)])
+def test_wave_with_velocity_vs_oracle(fp, dt, with_v0, want_v, t):
+    nx, ny, lx, ly, c = 75, 36, 1.5, 1.0, 1.2
+    say(f"mixed wave velocity {nx}x{ny} {dt} v0={with_v0} v={want_v} t={t}")
+    u0 = W.random_field((ny, nx), seed=21)
+    v0 = W.random_field((ny, nx), seed=22) if with_v0 else None
+    u, v = fp.solve_wave(to_dev(u0, dt), None if v0 is None else to_dev(v0, dt), c, t, lx, ly, want_v=want_v)
+    ref_u, ref_v = oracle.solve_wave(as_oracle_input(u0, dt), None if v0 is None else as_oracle_input(v0, dt),
+                                     lx, ly, c, t, want_v=True, threads=THREADS)
+    norm = np.linalg.norm(u0) + (np.linalg.norm(v0) if v0 is not None else 0.0)
+    assert rel_err_vs_input(to_host(u), ref_u, norm) <= tol(dt, nx, ny, 2)
+    if want_v:
+        # the velocity carries w = c|k| up to c k_max ~ 2 pi c n / (2 L)
+        wmax = c * math.pi * max(nx / lx, ny / ly)
+        assert rel_err_vs_input(to_host(v), ref_v, norm * max(1.0, wmax)) <= tol(dt, nx, ny, 2)
+    else:
+        assert v is None
+
+
+def test_single_modes_on_an_odd_grid(fp):
+    """Closed forms, independent of the oracle: a cosine mode through the
+    three solves on a 45 x 35 grid, FP64."""
+    nx, ny, lx, ly, m, n = 45, 35, 1.0, 1.4, 4, -3
+    say(f"mixed single modes {nx}x{ny}")
+    X, Y = np.meshgrid(W.grid(nx, lx), W.grid(ny, ly))
+    mode = np.cos(2 * math.pi * (m * X / lx + n * Y / ly)).astype(np.complex128)
+    k2 = (2 * math.pi) ** 2 * ((m / lx) ** 2 + (n / ly) ** 2)
+    u = to_host(fp.solve_poisson(to_dev(mode + 0.5, "c128"), lx, ly))
+    assert np.abs(u + mode / k2).max() <= 1e-13 / k2 * 10
+    d = to_host(fp.solve_diffusion(to_dev(mode, "c128"), 0.02, 0.5, lx, ly))
+    assert np.abs(d - math.exp(-0.02 * k2 * 0.5) * mode).max() <= 1e-13
+    w, _ = fp.solve_wave(to_dev(mode, "c128"), None, 0.7, 0.9, lx, ly)
+    assert np.abs(to_host(w) - math.cos(0.7 * math.sqrt(k2) * 0.9) * mode).max() <= 1e-13
+
+
+def test_rejects_sizes_outside_the_mixed_path(fp):
+    import torch
+    for nx, ny in ((11, 8), (8, 13), (4097, 2), (8192, 3), (22, 7 * 11)):
+        x = torch.zeros((ny, nx), dtype=torch.complex64, device="cuda:0")
+        with pytest.raises(Exception):
+            fp.fft2d_forward(x)
+        with pytest.raises(Exception):
+            fp.solve_poisson(x)
+    # real fields and the 3D path stay on powers of two
+    r = torch.zeros((30, 12), dtype=torch.float32, device="cuda:0")
+    with pytest.raises(Exception):
+        fp.solve_poisson(r)
