@@ -90,20 +90,25 @@ int mr_pass(Context* c, int mode, int nf, const void* in0, const void* in1, void
   a.mode = mode;
   a.scale = T(scale);
   a.sym = sym;
+  const int cap = mr_cap(sizeof(T) == 8, nf);
   if (col) {
     // adjacent columns, each padded by one in LDS
-    a.lines = std::max(1, std::min(kMrMaxColLines, kMrTilePts / (n + 1)));
+    a.lines = std::max(1, std::min(kMrMaxColLines, cap / (n + 1)));
     a.lines = std::min(a.lines, nx);
     a.ls = a.lines > 1 ? n + 1 : n;
+    a.tiles = fields * (long long)((nx + a.lines - 1) / a.lines);
   } else {
-    a.lines = std::max(1, kMrTilePts / n);
+    a.lines = std::max(1, cap / n);
     a.ls = n;
+    a.tiles = ((long long)ny * fields + a.lines - 1) / a.lines;
   }
+  a.by_lines = MrDiv(a.lines);
+  const long long grid = std::min<long long>(a.tiles, (long long)std::max(1, c->num_cus) * mr_occupancy<T>(nf));
   const int nin = 1 + (in1 ? 1 : 0), nout = 1 + (out1 ? 1 : 0);
   const double bytes = (double)sizeof(cx<T>) * (double)nx * ny * (double)fields * (nin + nout);
   const char* name = col ? (sizeof(T) == 4 ? "mixed_col_float" : "mixed_col_double")
                          : (sizeof(T) == 4 ? "mixed_row_float" : "mixed_row_double");
-  const hipError_t e = timed_launch(c, name, bytes, s, [&] { return mr_launch<T>(a, nf, s); });
+  const hipError_t e = timed_launch(c, name, bytes, s, [&] { return mr_launch<T>(a, nf, (int)grid, s); });
   if (e != hipSuccess) {
     set_last_error(name, e);
     return FFTPDE_EDEVICE;

@@ -49,10 +49,10 @@ __device__ __forceinline__ void dft_odd(cx<T>* v, const T* cs, const T* sn) {
 //     v_t = x[j + t n/R] w_{ns R}^{t k},  v = DFT_R(v),  y[(j - k) R + k + t ns] = v_t
 // Every thread takes its butterflies' inputs into registers, the workgroup
 // synchronises, and the outputs overwrite the same buffer.
-template <typename T, int R>
-__device__ __forceinline__ void mr_stage(cx<T>* buf, int nl, int n, int ls, int ns, const cx<T>* __restrict__ tw,
-                                         int tid) {
-  constexpr int MAXB = (kMrTilePts / R + kMrTH - 1) / kMrTH;  // butterflies per thread
+template <typename T, int R, int CAP>
+__device__ __forceinline__ void mr_stage(cx<T>* buf, int nl, int n, int ls, int ns, MrDiv by_m, MrDiv by_ns,
+                                         const cx<T>* __restrict__ tw, int tid) {
+  constexpr int MAXB = (CAP / R + kMrTH - 1) / kMrTH;  // butterflies per thread
   constexpr int H = (R & 1) ? (R - 1) / 2 : 1;
   const int m = n / R;
   const int nb = nl * m;
@@ -71,7 +71,7 @@ __device__ __forceinline__ void mr_stage(cx<T>* buf, int nl, int n, int ls, int 
   for (int i = 0; i < MAXB; i++) {
     const int b = tid + i * kMrTH;
     if (b < nb) {
-      const int line = b / m, j = b - line * m, k = j % ns;
+      const int line = by_m(b), j = b - line * m, k = j - by_ns(j) * ns;
       const cx<T>* src = buf + line * ls + j;
 #pragma unroll
       for (int t = 0; t < R; t++) v[i][t] = src[t * m];
@@ -88,7 +88,7 @@ __device__ __forceinline__ void mr_stage(cx<T>* buf, int nl, int n, int ls, int 
   for (int i = 0; i < MAXB; i++) {
     const int b = tid + i * kMrTH;
     if (b < nb) {
-      const int line = b / m, j = b - line * m, k = j % ns;
+      const int line = by_m(b), j = b - line * m, k = j - by_ns(j) * ns;
       cx<T>* dst = buf + line * ls + (j - k) * R + k;
 #pragma unroll
       for (int t = 0; t < R; t++) dst[t * ns] = v[i][t];
@@ -97,19 +97,21 @@ __device__ __forceinline__ void mr_stage(cx<T>* buf, int nl, int n, int ls, int 
   __syncthreads();
 }
 
-// Forward transform of nl lines in LDS, natural order in and out.
-template <typename T>
+// Forward transform of nl lines in LDS (at most CAP points), natural order
+// in and out.
+template <typename T, int CAP>
 __device__ void mr_fft(cx<T>* buf, int nl, const MrPlan& p, int ls, const cx<T>* __restrict__ tw, int tid) {
   int ns = 1;
   for (int s = 0; s < p.nst; s++) {
     const int r = p.radix[s];
+    const MrDiv bm = p.by_m[s], bn = p.by_ns[s];
     switch (r) {
-      case 2: mr_stage<T, 2>(buf, nl, p.n, ls, ns, tw, tid); break;
-      case 3: mr_stage<T, 3>(buf, nl, p.n, ls, ns, tw, tid); break;
-      case 4: mr_stage<T, 4>(buf, nl, p.n, ls, ns, tw, tid); break;
-      case 5: mr_stage<T, 5>(buf, nl, p.n, ls, ns, tw, tid); break;
-      case 7: mr_stage<T, 7>(buf, nl, p.n, ls, ns, tw, tid); break;
-      default: mr_stage<T, 8>(buf, nl, p.n, ls, ns, tw, tid); break;
+      case 2: mr_stage<T, 2, CAP>(buf, nl, p.n, ls, ns, bm, bn, tw, tid); break;
+      case 3: mr_stage<T, 3, CAP>(buf, nl, p.n, ls, ns, bm, bn, tw, tid); break;
+      case 4: mr_stage<T, 4, CAP>(buf, nl, p.n, ls, ns, bm, bn, tw, tid); break;
+      case 5: mr_stage<T, 5, CAP>(buf, nl, p.n, ls, ns, bm, bn, tw, tid); break;
+      case 7: mr_stage<T, 7, CAP>(buf, nl, p.n, ls, ns, bm, bn, tw, tid); break;
+      default: mr_stage<T, 8, CAP>(buf, nl, p.n, ls, ns, bm, bn, tw, tid); break;
     }
     ns *= r;
   }
@@ -128,16 +130,34 @@ __device__ __forceinline__ T mr_symbol(const MrSym& s, int ai, int bi) {
   switch (s.op) {
     case kSymPoisson: {
       if (ai == 0 && bi == 0) return T(0);
-      const double kx = s.kxs * ai, ky = s.kys * bi;
-      return T(-s.scale / fma(kx, kx, ky * ky));
+      if constexpr (sizeof(T) == 4) {
+        const float kx = float(s.kxs) * float(ai), ky = float(s.kys) * float(bi);
+        return -float(s.scale) * __builtin_amdgcn_rcpf(fmaf(kx, kx, ky * ky));
+      } else {
+        const double kx = s.kxs * ai, ky = s.kys * bi;
+        return -s.scale / fma(kx, kx, ky * ky);
+      }
     }
     case kSymDiffusion: {
       const double kx = s.kxs * ai, ky = s.kys * bi;
-      return T(s.scale * exp(-s.kt * fma(kx, kx, ky * ky)));
+      const double arg = s.kt * fma(kx, kx, ky * ky);
+      if constexpr (sizeof(T) == 4) return float(s.scale) * expf(-float(arg));
+      else return s.scale * exp(-arg);
     }
     case kSymWave: {
       const double hx = s.hx * ai, hy = s.hy * bi;
-      return T(s.scale * cospi(sqrt(fma(hx, hx, hy * hy))));
+      const double h2 = fma(hx, hx, hy * hy);
+      if constexpr (sizeof(T) == 4) {
+        // w t / pi, reduced exactly to [-1, 1] in FP64, then cos(pi h) =
+        // (-1)^m cos(pi (h - m)) with m = rint(h) and h - m in [-1/2, 1/2]
+        double h = sqrt_fp64_from_fp32(h2);
+        h = fma(-2.0, rint(0.5 * h), h);
+        const double m = rint(h);
+        const float c = cospi_half(float(h - m));
+        return (m != 0.0 ? -float(s.scale) : float(s.scale)) * c;
+      } else {
+        return s.scale * cospi(sqrt(h2));
+      }
     }
     default: return T(s.scale);
   }
@@ -164,118 +184,153 @@ struct MrWave {
 
 template <typename T, int NF>
 __global__ void __launch_bounds__(kMrTH) mr_kernel(MrArgs<T> a) {
-  __shared__ cx<T> lds[NF * kMrLds];
+  constexpr int CAP = mr_cap(sizeof(T) == 8, NF);
+  constexpr int LDSF = CAP + kMrMaxColLines;  // per field: column tiles pad each line by one
+  constexpr bool TWL = mr_tw_in_lds(sizeof(T) == 8, NF);
+  __shared__ cx<T> lds[NF * LDSF];
+  __shared__ cx<T> twl[TWL ? kMrMaxSide : 1];
   const int tid = threadIdx.x;
   const int n = a.plan.n;
   const bool col = a.mode >= kMrColFwd;
-  // this tile: nl lines; rows start at element `base`, columns at c0 of field f
-  long long base = 0;
-  int nl, c0 = 0;
-  if (!col) {
-    const long long nrows = (long long)a.ny * a.fields;
-    const long long row0 = (long long)blockIdx.x * a.lines;
-    nl = (int)min((long long)a.lines, nrows - row0);
-    base = row0 * n;
-  } else {
-    const int tpf = (a.nx + a.lines - 1) / a.lines;
-    const long long f = blockIdx.x / tpf;
-    c0 = (int)(blockIdx.x - f * tpf) * a.lines;
-    nl = min(a.lines, a.nx - c0);
-    base = f * (long long)a.nx * a.ny + c0;
+  const cx<T>* tw = a.tw;
+  if constexpr (TWL) {
+    for (int e = tid; e < n; e += kMrTH) twl[e] = a.tw[e];  // read after the first barrier
+    tw = twl;
   }
-  const int cnt = nl * n;
-  // element idx of the tile: its line, position, global offset; columns walk
-  // the tile's columns fastest so that a wavefront reads whole row segments
-  auto where = [&](int idx, int& line, int& j) -> long long {
+  // Tile t: nl lines; rows start at element `base`, columns at c0 of their
+  // field.  Element idx of a tile: its line, position and global offset.
+  // Columns walk the tile's columns fastest (a wavefront reads whole row
+  // segments) over the full tile width; positions past the last column of a
+  // ragged tile are skipped.
+  struct Tile {
+    long long base;
+    int nl, c0, span;
+  };
+  auto tile_at = [&](long long t) {
+    Tile g;
     if (!col) {
-      line = idx / n;
-      j = idx - line * n;
-      return base + idx;
+      const long long nrows = (long long)a.ny * a.fields;
+      const long long row0 = t * a.lines;
+      g.nl = (int)min((long long)a.lines, nrows - row0);
+      g.base = row0 * n;
+      g.c0 = 0;
+      g.span = g.nl * n;
+    } else {
+      const int tpf = (a.nx + a.lines - 1) / a.lines;
+      const long long f = t / tpf;
+      g.c0 = (int)(t - f * tpf) * a.lines;
+      g.nl = min(a.lines, a.nx - g.c0);
+      g.base = f * (long long)a.nx * a.ny + g.c0;
+      g.span = a.lines * n;
     }
-    j = idx / nl;
-    line = idx - j * nl;
-    return base + (long long)j * a.nx + line;
+    return g;
+  };
+  auto where = [&](const Tile& g, int idx, int& line, int& j) -> long long {
+    if (!col) {
+      line = a.plan.by_n(idx);
+      j = idx - line * n;
+      return g.base + idx;
+    }
+    j = a.by_lines(idx);
+    line = idx - j * a.lines;
+    return g.base + (long long)j * a.nx + line;
   };
   const bool conj_in = a.mode == kMrRowInv || a.mode == kMrColInv;
   const bool has2 = NF == 2 && a.in1 != nullptr;
-#pragma unroll
-  for (int fi = 0; fi < NF; fi++) {
-    const cx<T>* in = fi == 0 ? a.in0 : a.in1;
-    if (fi == 1 && !has2) continue;
-    cx<T>* buf = lds + fi * kMrLds;
-    for (int idx = tid; idx < cnt; idx += kMrTH) {
-      int line, j;
-      const long long g = where(idx, line, j);
-      cx<T> v = in[g];
-      if (conj_in) v.im = -v.im;
-      buf[line * a.ls + j] = v;
-    }
-  }
-  __syncthreads();
-  mr_fft(lds, nl, a.plan, a.ls, a.tw, tid);
-  if (has2) mr_fft(lds + kMrLds, nl, a.plan, a.ls, a.tw, tid);
   const bool out2 = NF == 2 && a.out1 != nullptr;
-  if (a.mode == kMrColSolve) {
-    // the symbol, then the inverse through the conjugation identity of the
-    // iDFT (Sec. II.B): the values are conjugated here and on the way out
-    for (int idx = tid; idx < cnt; idx += kMrTH) {
-      const int line = idx / n, j = idx - line * n;
-      const int ai = mr_sidx(c0 + line, a.nx), bi = mr_sidx(j, a.ny);
-      cx<T>* p0 = lds + line * a.ls + j;
-      if constexpr (NF == 1) {
-        const T m = mr_symbol<T>(a.sym, ai, bi);
-        *p0 = {p0->re * m, -p0->im * m};
-      } else {
-        const MrWave w(a.sym, ai, bi);
-        cx<T>* p1 = p0 + kMrLds;
-        const cx<T> F = *p0;
-        const cx<T> G = has2 ? *p1 : cx<T>{T(0), T(0)};
-        const T cw = T(w.cw), sow = T(w.sow), wsw = T(w.wsw);
-        *p0 = {cw * F.re + sow * G.re, -(cw * F.im + sow * G.im)};
-        if (out2) *p1 = {cw * G.re - wsw * F.re, -(cw * G.im - wsw * F.im)};
+  long long t = blockIdx.x;
+  while (true) {
+    const Tile g = tile_at(t);
+#pragma unroll
+    for (int fi = 0; fi < NF; fi++) {
+      const cx<T>* in = fi == 0 ? a.in0 : a.in1;
+      if (fi == 1 && !has2) continue;
+      cx<T>* buf = lds + fi * LDSF;
+      for (int idx = tid; idx < g.span; idx += kMrTH) {
+        int line, j;
+        const long long off = where(g, idx, line, j);
+        if (line >= g.nl) continue;
+        cx<T> v = in[off];
+        if (conj_in) v.im = -v.im;
+        buf[line * a.ls + j] = v;
       }
     }
     __syncthreads();
-    mr_fft(lds, nl, a.plan, a.ls, a.tw, tid);
-    if (out2) mr_fft(lds + kMrLds, nl, a.plan, a.ls, a.tw, tid);
-  }
-  const bool conj_out = a.mode == kMrRowInv || a.mode == kMrColInv || a.mode == kMrColSolve;
-  const T sc = a.mode == kMrRowInv ? a.scale : T(1);
-#pragma unroll
-  for (int fi = 0; fi < NF; fi++) {
-    cx<T>* out = fi == 0 ? a.out0 : a.out1;
-    if (fi == 1 && !out2) continue;
-    const cx<T>* buf = lds + fi * kMrLds;
-    for (int idx = tid; idx < cnt; idx += kMrTH) {
-      int line, j;
-      const long long g = where(idx, line, j);
-      const cx<T> v = buf[line * a.ls + j];
-      out[g] = conj_out ? cx<T>{v.re * sc, -v.im * sc} : v;
+    const int nl = g.nl, c0 = g.c0;
+    mr_fft<T, CAP>(lds, nl, a.plan, a.ls, tw, tid);
+    if (has2) mr_fft<T, CAP>(lds + LDSF, nl, a.plan, a.ls, tw, tid);
+    if (a.mode == kMrColSolve) {
+      // the symbol, then the inverse through the conjugation identity of
+      // the iDFT (Sec. II.B): the values are conjugated here and on the way out
+      const int cnt = nl * n;
+      for (int idx = tid; idx < cnt; idx += kMrTH) {
+        const int line = a.plan.by_n(idx), j = idx - line * n;
+        const int ai = mr_sidx(c0 + line, a.nx), bi = mr_sidx(j, a.ny);
+        cx<T>* p0 = lds + line * a.ls + j;
+        if constexpr (NF == 1) {
+          const T m = mr_symbol<T>(a.sym, ai, bi);
+          *p0 = {p0->re * m, -p0->im * m};
+        } else {
+          const MrWave w(a.sym, ai, bi);
+          cx<T>* p1 = p0 + LDSF;
+          const cx<T> F = *p0;
+          const cx<T> G = has2 ? *p1 : cx<T>{T(0), T(0)};
+          const T cw = T(w.cw), sow = T(w.sow), wsw = T(w.wsw);
+          *p0 = {cw * F.re + sow * G.re, -(cw * F.im + sow * G.im)};
+          if (out2) *p1 = {cw * G.re - wsw * F.re, -(cw * G.im - wsw * F.im)};
+        }
+      }
+      __syncthreads();
+      mr_fft<T, CAP>(lds, nl, a.plan, a.ls, tw, tid);
+      if (out2) mr_fft<T, CAP>(lds + LDSF, nl, a.plan, a.ls, tw, tid);
     }
+    const bool conj_out = a.mode == kMrRowInv || a.mode == kMrColInv || a.mode == kMrColSolve;
+    const T sc = a.mode == kMrRowInv ? a.scale : T(1);
+#pragma unroll
+    for (int fi = 0; fi < NF; fi++) {
+      cx<T>* out = fi == 0 ? a.out0 : a.out1;
+      if (fi == 1 && !out2) continue;
+      const cx<T>* buf = lds + fi * LDSF;
+      for (int idx = tid; idx < g.span; idx += kMrTH) {
+        int line, j;
+        const long long off = where(g, idx, line, j);
+        if (line >= nl) continue;
+        const cx<T> v = buf[line * a.ls + j];
+        out[off] = conj_out ? cx<T>{v.re * sc, -v.im * sc} : v;
+      }
+    }
+    t += gridDim.x;
+    if (t >= a.tiles) break;
+    __syncthreads();  // every thread is done with LDS before the next tile lands
   }
+}
+
+template <typename T, int NF>
+int occupancy_of() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, mr_kernel<T, NF>, kMrTH, 0) != hipSuccess) return 1;
+  return n < 1 ? 1 : n;
 }
 
 }  // namespace
 
 template <typename T>
-long long mr_tiles(const MrArgs<T>& a) {
-  if (a.mode >= kMrColFwd) return a.fields * (long long)((a.nx + a.lines - 1) / a.lines);
-  const long long nrows = (long long)a.ny * a.fields;
-  return (nrows + a.lines - 1) / a.lines;
+int mr_occupancy(int nf) {
+  static const int o1 = occupancy_of<T, 1>(), o2 = occupancy_of<T, 2>();
+  return nf == 2 ? o2 : o1;
 }
 
 template <typename T>
-hipError_t mr_launch(const MrArgs<T>& a, int nf, hipStream_t s) {
-  const long long tiles = mr_tiles(a);
-  if (tiles < 1 || tiles > 0x7fffffffll) return hipErrorInvalidValue;
-  if (nf == 2) hipLaunchKernelGGL((mr_kernel<T, 2>), dim3((unsigned)tiles), dim3(kMrTH), 0, s, a);
-  else hipLaunchKernelGGL((mr_kernel<T, 1>), dim3((unsigned)tiles), dim3(kMrTH), 0, s, a);
+hipError_t mr_launch(const MrArgs<T>& a, int nf, int grid, hipStream_t s) {
+  if (a.tiles < 1 || grid < 1 || grid > a.tiles) return hipErrorInvalidValue;
+  if (nf == 2) hipLaunchKernelGGL((mr_kernel<T, 2>), dim3((unsigned)grid), dim3(kMrTH), 0, s, a);
+  else hipLaunchKernelGGL((mr_kernel<T, 1>), dim3((unsigned)grid), dim3(kMrTH), 0, s, a);
   return hipGetLastError();
 }
 
-template long long mr_tiles<float>(const MrArgs<float>&);
-template long long mr_tiles<double>(const MrArgs<double>&);
-template hipError_t mr_launch<float>(const MrArgs<float>&, int, hipStream_t);
-template hipError_t mr_launch<double>(const MrArgs<double>&, int, hipStream_t);
+template int mr_occupancy<float>(int);
+template int mr_occupancy<double>(int);
+template hipError_t mr_launch<float>(const MrArgs<float>&, int, int, hipStream_t);
+template hipError_t mr_launch<double>(const MrArgs<double>&, int, int, hipStream_t);
 
 }  // namespace fftpde

@@ -9,12 +9,12 @@
 // the y forward transform, the pointwise symbol and the y inverse (the
 // spectrum never goes back to HBM between them), then x rows inverse.
 //
-// A workgroup loads one tile (whole lines, at most 4096 points per field)
-// into LDS, runs every stage there -- each thread takes its butterflies'
-// inputs into registers, the workgroup synchronises, the outputs go back to
-// the same buffer -- and writes the tile out.  Twiddles are the N-th roots
-// of unity of the line length, generated in FP64 on the host and rounded
-// once (one table per length, cached in the context).
+// Persistent workgroups walk the tiles (whole lines, up to mr_cap points per
+// field).  A tile is loaded into LDS, every stage runs there -- each thread
+// takes its butterflies' inputs into registers, the workgroup synchronises,
+// the outputs go back to the same buffer -- and the tile is written out.  Twiddles are the n-th roots of unity of the line
+// length, generated in FP64 on the host and rounded once (one table per
+// length, cached in the context), copied into LDS by each workgroup.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -23,12 +23,19 @@
 
 namespace fftpde {
 
-constexpr int kMrTH = 1024;         // threads per workgroup (4 points each at 4096)
+constexpr int kMrTH = 1024;         // threads per workgroup
 constexpr int kMrMaxSide = 4096;
-constexpr int kMrTilePts = 4096;    // points per field and tile
 constexpr int kMrMaxColLines = 64;  // columns per column tile
-constexpr int kMrLds = kMrTilePts + kMrMaxColLines;  // column tiles pad each line by one
 constexpr int kMrMaxStages = 12;
+
+// Points per field and tile: 8192 FP32 (4096 per field with a second
+// field), 4096 FP64 (the longest line).  With the padding of column tiles
+// and the twiddle table of the line length in LDS (not for FP64 with two
+// fields): at most 133 KB of LDS.  Measured at 1000^2..2000^2: FP32 tiles
+// of 8192 points beat 4096 (with the next tile staged in registers) and
+// 12288 (register spills); the table in LDS beats reading it from L1/L2.
+constexpr int mr_cap(bool fp64, int nf) { return fp64 ? 4096 : 8192 / nf; }
+constexpr bool mr_tw_in_lds(bool fp64, int nf) { return !(fp64 && nf == 2); }
 
 // Sides the mixed-radix path takes: 2..4096, 7-smooth.
 __host__ __device__ constexpr bool mr_side_ok(int n) {
@@ -42,10 +49,25 @@ __host__ __device__ constexpr bool mr_side_ok(int n) {
 
 // Radix sequence of a length: 8s first, then a 4 or a 2 for the rest of the
 // power of two, then 7s, 5s and 3s.
+// Exact x / d for 0 <= x < 2^16 and 1 <= d < 2^16 by one multiply:
+// floor(x M / 2^32) with M = floor(2^32 / d) + 1 (the error x (M - 2^32/d)
+// / 2^32 < 2^-16 < 1/d never crosses an integer).
+struct MrDiv {
+  unsigned long long m = 0;
+  MrDiv() = default;
+  explicit MrDiv(int d) : m((1ull << 32) / (unsigned long long)d + 1) {}
+  __device__ __forceinline__ int operator()(int x) const {
+    return (int)(((unsigned long long)(unsigned)x * m) >> 32);
+  }
+};
+
 struct MrPlan {
   int n = 0;
   int nst = 0;
   int radix[kMrMaxStages] = {};
+  MrDiv by_m[kMrMaxStages];   // n / radix[s]: butterflies per line
+  MrDiv by_ns[kMrMaxStages];  // product of the radices before stage s
+  MrDiv by_n;
 };
 
 inline MrPlan mr_plan(int n) {
@@ -65,6 +87,13 @@ inline MrPlan mr_plan(int n) {
   take(5);
   take(3);
   if (m != 1) p.nst = 0;  // not 7-smooth: no plan
+  int ns = 1;
+  for (int s = 0; s < p.nst; s++) {
+    p.by_m[s] = MrDiv(n / p.radix[s]);
+    p.by_ns[s] = MrDiv(ns);
+    ns *= p.radix[s];
+  }
+  p.by_n = MrDiv(n);
   return p;
 }
 
@@ -98,16 +127,19 @@ struct MrArgs {
   int nx, ny;
   long long fields;
   int lines;  // lines per tile
+  MrDiv by_lines;
   int ls;     // LDS distance between lines
+  long long tiles;
   int mode;
   T scale;    // kMrRowInv
   MrSym sym;  // kMrColSolve
 };
 
+// grid: persistent workgroups (at most a.tiles)
 template <typename T>
-hipError_t mr_launch(const MrArgs<T>& a, int nf, hipStream_t s);
-// workgroups of a launch
+hipError_t mr_launch(const MrArgs<T>& a, int nf, int grid, hipStream_t s);
+// resident workgroups per CU of the kernel for (T, nf)
 template <typename T>
-long long mr_tiles(const MrArgs<T>& a);
+int mr_occupancy(int nf);
 
 }  // namespace fftpde
