@@ -43,16 +43,23 @@ __device__ __forceinline__ void dft_odd(cx<T>* v, const T* cs, const T* sn) {
   v[0] = sum;
 }
 
+// LDS position of tile element i: one pad word every 32 elements spreads
+// the strided accesses of the early stages over the banks (a bank model of
+// the stages at 1000, 1536 and 2000 points: 4.4-4.9 passes per wavefront
+// access without the pad, 2.3-2.7 with it; 2 is conflict free).
+__device__ __forceinline__ int mr_pad(int i) { return i + (i >> 5); }
+constexpr int mr_padded(int n) { return n + (n >> 5) + 1; }
+
 // One Stockham stage of radix R on nl lines of length n (line l at
-// buf + l ls) after sub-transforms of length ns:
+// element l ls of the tile) after sub-transforms of length ns:
 //   butterfly j (0 <= j < n/R), k = j mod ns:
 //     v_t = x[j + t n/R] w_{ns R}^{t k},  v = DFT_R(v),  y[(j - k) R + k + t ns] = v_t
 // Every thread takes its butterflies' inputs into registers, the workgroup
 // synchronises, and the outputs overwrite the same buffer.
-template <typename T, int R, int CAP>
+template <typename T, int R, int CAP, int TH>
 __device__ __forceinline__ void mr_stage(cx<T>* buf, int nl, int n, int ls, int ns, MrDiv by_m, MrDiv by_ns,
                                          const cx<T>* __restrict__ tw, int tid) {
-  constexpr int MAXB = (CAP / R + kMrTH - 1) / kMrTH;  // butterflies per thread
+  constexpr int MAXB = (CAP / R + TH - 1) / TH;  // butterflies per thread
   constexpr int H = (R & 1) ? (R - 1) / 2 : 1;
   const int m = n / R;
   const int nb = nl * m;
@@ -69,12 +76,12 @@ __device__ __forceinline__ void mr_stage(cx<T>* buf, int nl, int n, int ls, int 
   cx<T> v[MAXB][R];
 #pragma unroll
   for (int i = 0; i < MAXB; i++) {
-    const int b = tid + i * kMrTH;
+    const int b = tid + i * TH;
     if (b < nb) {
       const int line = by_m(b), j = b - line * m, k = j - by_ns(j) * ns;
-      const cx<T>* src = buf + line * ls + j;
+      const int src = line * ls + j;
 #pragma unroll
-      for (int t = 0; t < R; t++) v[i][t] = src[t * m];
+      for (int t = 0; t < R; t++) v[i][t] = buf[mr_pad(src + t * m)];
       if (ns > 1) {
 #pragma unroll
         for (int t = 1; t < R; t++) v[i][t] = cmul(v[i][t], tw[t * k * tstep]);
@@ -86,12 +93,12 @@ __device__ __forceinline__ void mr_stage(cx<T>* buf, int nl, int n, int ls, int 
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < MAXB; i++) {
-    const int b = tid + i * kMrTH;
+    const int b = tid + i * TH;
     if (b < nb) {
       const int line = by_m(b), j = b - line * m, k = j - by_ns(j) * ns;
-      cx<T>* dst = buf + line * ls + (j - k) * R + k;
+      const int dst = line * ls + (j - k) * R + k;
 #pragma unroll
-      for (int t = 0; t < R; t++) dst[t * ns] = v[i][t];
+      for (int t = 0; t < R; t++) buf[mr_pad(dst + t * ns)] = v[i][t];
     }
   }
   __syncthreads();
@@ -99,19 +106,19 @@ __device__ __forceinline__ void mr_stage(cx<T>* buf, int nl, int n, int ls, int 
 
 // Forward transform of nl lines in LDS (at most CAP points), natural order
 // in and out.
-template <typename T, int CAP>
+template <typename T, int CAP, int TH>
 __device__ void mr_fft(cx<T>* buf, int nl, const MrPlan& p, int ls, const cx<T>* __restrict__ tw, int tid) {
   int ns = 1;
   for (int s = 0; s < p.nst; s++) {
     const int r = p.radix[s];
     const MrDiv bm = p.by_m[s], bn = p.by_ns[s];
     switch (r) {
-      case 2: mr_stage<T, 2, CAP>(buf, nl, p.n, ls, ns, bm, bn, tw, tid); break;
-      case 3: mr_stage<T, 3, CAP>(buf, nl, p.n, ls, ns, bm, bn, tw, tid); break;
-      case 4: mr_stage<T, 4, CAP>(buf, nl, p.n, ls, ns, bm, bn, tw, tid); break;
-      case 5: mr_stage<T, 5, CAP>(buf, nl, p.n, ls, ns, bm, bn, tw, tid); break;
-      case 7: mr_stage<T, 7, CAP>(buf, nl, p.n, ls, ns, bm, bn, tw, tid); break;
-      default: mr_stage<T, 8, CAP>(buf, nl, p.n, ls, ns, bm, bn, tw, tid); break;
+      case 2: mr_stage<T, 2, CAP, TH>(buf, nl, p.n, ls, ns, bm, bn, tw, tid); break;
+      case 3: mr_stage<T, 3, CAP, TH>(buf, nl, p.n, ls, ns, bm, bn, tw, tid); break;
+      case 4: mr_stage<T, 4, CAP, TH>(buf, nl, p.n, ls, ns, bm, bn, tw, tid); break;
+      case 5: mr_stage<T, 5, CAP, TH>(buf, nl, p.n, ls, ns, bm, bn, tw, tid); break;
+      case 7: mr_stage<T, 7, CAP, TH>(buf, nl, p.n, ls, ns, bm, bn, tw, tid); break;
+      default: mr_stage<T, 8, CAP, TH>(buf, nl, p.n, ls, ns, bm, bn, tw, tid); break;
     }
     ns *= r;
   }
@@ -183,9 +190,11 @@ struct MrWave {
 };
 
 template <typename T, int NF>
-__global__ void __launch_bounds__(kMrTH) mr_kernel(MrArgs<T> a) {
+__global__ void __launch_bounds__(mr_threads(sizeof(T) == 8)) mr_kernel(MrArgs<T> a) {
+  constexpr int TH = mr_threads(sizeof(T) == 8);
   constexpr int CAP = mr_cap(sizeof(T) == 8, NF);
-  constexpr int LDSF = CAP + kMrMaxColLines;  // per field: column tiles pad each line by one
+  // per field: column tiles pad each line by one, then the bank pad
+  constexpr int LDSF = mr_padded(CAP + kMrMaxColLines);
   constexpr bool TWL = mr_tw_in_lds(sizeof(T) == 8, NF);
   __shared__ cx<T> lds[NF * LDSF];
   __shared__ cx<T> twl[TWL ? kMrMaxSide : 1];
@@ -194,7 +203,7 @@ __global__ void __launch_bounds__(kMrTH) mr_kernel(MrArgs<T> a) {
   const bool col = a.mode >= kMrColFwd;
   const cx<T>* tw = a.tw;
   if constexpr (TWL) {
-    for (int e = tid; e < n; e += kMrTH) twl[e] = a.tw[e];  // read after the first barrier
+    for (int e = tid; e < n; e += TH) twl[e] = a.tw[e];  // read after the first barrier
     tw = twl;
   }
   // Tile t: nl lines; rows start at element `base`, columns at c0 of their
@@ -238,35 +247,58 @@ __global__ void __launch_bounds__(kMrTH) mr_kernel(MrArgs<T> a) {
   const bool conj_in = a.mode == kMrRowInv || a.mode == kMrColInv;
   const bool has2 = NF == 2 && a.in1 != nullptr;
   const bool out2 = NF == 2 && a.out1 != nullptr;
+  constexpr int PT = (CAP + TH - 1) / TH;  // points per thread of a full tile
   long long t = blockIdx.x;
   while (true) {
     const Tile g = tile_at(t);
+    // every load of the tile is issued before the first value lands in LDS
 #pragma unroll
     for (int fi = 0; fi < NF; fi++) {
       const cx<T>* in = fi == 0 ? a.in0 : a.in1;
       if (fi == 1 && !has2) continue;
       cx<T>* buf = lds + fi * LDSF;
-      for (int idx = tid; idx < g.span; idx += kMrTH) {
-        int line, j;
-        const long long off = where(g, idx, line, j);
-        if (line >= g.nl) continue;
-        cx<T> v = in[off];
-        if (conj_in) v.im = -v.im;
-        buf[line * a.ls + j] = v;
+      if constexpr (sizeof(T) == 4) {
+        cx<T> v[PT];
+#pragma unroll
+        for (int i = 0; i < PT; i++) {
+          const int idx = tid + i * TH;
+          int line, j;
+          const long long off = where(g, idx, line, j);
+          if (idx < g.span && line < g.nl) v[i] = in[off];
+        }
+#pragma unroll
+        for (int i = 0; i < PT; i++) {
+          const int idx = tid + i * TH;
+          int line, j;
+          (void)where(g, idx, line, j);
+          if (idx < g.span && line < g.nl) {
+            if (conj_in) v[i].im = -v[i].im;
+            buf[mr_pad(line * a.ls + j)] = v[i];
+          }
+        }
+      } else {  // FP64: no registers to spare for a whole tile
+        for (int idx = tid; idx < g.span; idx += TH) {
+          int line, j;
+          const long long off = where(g, idx, line, j);
+          if (line >= g.nl) continue;
+          cx<T> v = in[off];
+          if (conj_in) v.im = -v.im;
+          buf[mr_pad(line * a.ls + j)] = v;
+        }
       }
     }
     __syncthreads();
     const int nl = g.nl, c0 = g.c0;
-    mr_fft<T, CAP>(lds, nl, a.plan, a.ls, tw, tid);
-    if (has2) mr_fft<T, CAP>(lds + LDSF, nl, a.plan, a.ls, tw, tid);
+    mr_fft<T, CAP, TH>(lds, nl, a.plan, a.ls, tw, tid);
+    if (has2) mr_fft<T, CAP, TH>(lds + LDSF, nl, a.plan, a.ls, tw, tid);
     if (a.mode == kMrColSolve) {
       // the symbol, then the inverse through the conjugation identity of
       // the iDFT (Sec. II.B): the values are conjugated here and on the way out
       const int cnt = nl * n;
-      for (int idx = tid; idx < cnt; idx += kMrTH) {
+      for (int idx = tid; idx < cnt; idx += TH) {
         const int line = a.plan.by_n(idx), j = idx - line * n;
         const int ai = mr_sidx(c0 + line, a.nx), bi = mr_sidx(j, a.ny);
-        cx<T>* p0 = lds + line * a.ls + j;
+        cx<T>* p0 = lds + mr_pad(line * a.ls + j);
         if constexpr (NF == 1) {
           const T m = mr_symbol<T>(a.sym, ai, bi);
           *p0 = {p0->re * m, -p0->im * m};
@@ -281,8 +313,8 @@ __global__ void __launch_bounds__(kMrTH) mr_kernel(MrArgs<T> a) {
         }
       }
       __syncthreads();
-      mr_fft<T, CAP>(lds, nl, a.plan, a.ls, tw, tid);
-      if (out2) mr_fft<T, CAP>(lds + LDSF, nl, a.plan, a.ls, tw, tid);
+      mr_fft<T, CAP, TH>(lds, nl, a.plan, a.ls, tw, tid);
+      if (out2) mr_fft<T, CAP, TH>(lds + LDSF, nl, a.plan, a.ls, tw, tid);
     }
     const bool conj_out = a.mode == kMrRowInv || a.mode == kMrColInv || a.mode == kMrColSolve;
     const T sc = a.mode == kMrRowInv ? a.scale : T(1);
@@ -291,11 +323,11 @@ __global__ void __launch_bounds__(kMrTH) mr_kernel(MrArgs<T> a) {
       cx<T>* out = fi == 0 ? a.out0 : a.out1;
       if (fi == 1 && !out2) continue;
       const cx<T>* buf = lds + fi * LDSF;
-      for (int idx = tid; idx < g.span; idx += kMrTH) {
+      for (int idx = tid; idx < g.span; idx += TH) {
         int line, j;
         const long long off = where(g, idx, line, j);
         if (line >= nl) continue;
-        const cx<T> v = buf[line * a.ls + j];
+        const cx<T> v = buf[mr_pad(line * a.ls + j)];
         out[off] = conj_out ? cx<T>{v.re * sc, -v.im * sc} : v;
       }
     }
@@ -308,7 +340,9 @@ __global__ void __launch_bounds__(kMrTH) mr_kernel(MrArgs<T> a) {
 template <typename T, int NF>
 int occupancy_of() {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, mr_kernel<T, NF>, kMrTH, 0) != hipSuccess) return 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, mr_kernel<T, NF>, mr_threads(sizeof(T) == 8), 0) !=
+      hipSuccess)
+    return 1;
   return n < 1 ? 1 : n;
 }
 
@@ -323,8 +357,9 @@ int mr_occupancy(int nf) {
 template <typename T>
 hipError_t mr_launch(const MrArgs<T>& a, int nf, int grid, hipStream_t s) {
   if (a.tiles < 1 || grid < 1 || grid > a.tiles) return hipErrorInvalidValue;
-  if (nf == 2) hipLaunchKernelGGL((mr_kernel<T, 2>), dim3((unsigned)grid), dim3(kMrTH), 0, s, a);
-  else hipLaunchKernelGGL((mr_kernel<T, 1>), dim3((unsigned)grid), dim3(kMrTH), 0, s, a);
+  const unsigned th = mr_threads(sizeof(T) == 8);
+  if (nf == 2) hipLaunchKernelGGL((mr_kernel<T, 2>), dim3((unsigned)grid), dim3(th), 0, s, a);
+  else hipLaunchKernelGGL((mr_kernel<T, 1>), dim3((unsigned)grid), dim3(th), 0, s, a);
   return hipGetLastError();
 }
 

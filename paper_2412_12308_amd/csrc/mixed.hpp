@@ -23,7 +23,7 @@
 
 namespace fftpde {
 
-constexpr int kMrTH = 1024;         // threads per workgroup
+constexpr int mr_threads(bool fp64) { return fp64 ? 1024 : 1024; }  // per workgroup
 constexpr int kMrMaxSide = 4096;
 constexpr int kMrMaxColLines = 64;  // columns per column tile
 constexpr int kMrMaxStages = 12;
