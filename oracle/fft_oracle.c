@@ -93,15 +93,29 @@ static void fft_rec(const cplx *in, size_t stride, cplx *out, int n, int sign)
 static int is_pow2(int n) { return n >= 1 && (n & (n - 1)) == 0; }
 
 /* The DFT sum itself for any length n: out[k] = sum_j in[j stride]
- * exp(sign 2 pi i (j k mod n) / n). */
+ * exp(sign 2 pi i (j k mod n) / n).  The n roots of unity are taken from
+ * libm once per line (the same values as per term). */
 static void dft_direct(const cplx *in, size_t stride, cplx *out, int n, int sign)
 {
+    cplx *w = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    for (int m = 0; m < n && w; m++) {
+        double ang = sign * 2.0 * PI * (double)m / (double)n;
+        w[m].re = cos(ang);
+        w[m].im = sin(ang);
+    }
     for (int k = 0; k < n; k++) {
         double re = 0.0, im = 0.0;
         for (int j = 0; j < n; j++) {
             long long m = ((long long)j * k) % n;
-            double ang = sign * 2.0 * PI * (double)m / (double)n;
-            double wr = cos(ang), wi = sin(ang);
+            double wr, wi;
+            if (w) {
+                wr = w[m].re;
+                wi = w[m].im;
+            } else {
+                double ang = sign * 2.0 * PI * (double)m / (double)n;
+                wr = cos(ang);
+                wi = sin(ang);
+            }
             cplx x = in[(size_t)j * stride];
             re += wr * x.re - wi * x.im;
             im += wr * x.im + wi * x.re;
@@ -109,6 +123,7 @@ static void dft_direct(const cplx *in, size_t stride, cplx *out, int n, int sign
         out[k].re = re;
         out[k].im = im;
     }
+    free(w);
 }
 
 /* One line: the radix-2 recursion for powers of two, the plain sum else. */
