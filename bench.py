@@ -223,6 +223,48 @@ def leg_3d(fp, torch, steps: int, warmup: int, check: bool):
     return res
 
 
+def mixed_leg(fp, torch, steps: int, warmup: int, check: bool, n: int = 1536, batch: int = 8):
+    """The wave problem on a side that is not a power of two (1536 = 2^9 3,
+    the mixed-radix path), FP32 complex, batch 8: three passes, algorithmic
+    bytes 6 b P per solve; per-pass times from a second, profiled run."""
+    import numpy as np
+
+    dev = torch.device("cuda:0")
+    host = make_inputs(n, batch, seed=5)
+    u0 = torch.from_numpy(host).to(torch.complex64).to(dev)
+    out = torch.empty_like(u0)
+    for w in range(warmup):
+        fp.solve_wave(u0, None, C_SPEED, (w + 1) * DT, out=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(steps):
+        fp.solve_wave(u0, None, C_SPEED, (k + 1) * DT, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    alg = 6.0 * 8 * n * n * batch * steps
+    res = {"workload": f"wave2d_{n}x{n}_periodic_unit_square (mixed radix 8, 8, 8, 3), FP32 complex",
+           "batch": batch, "solves_per_s": round(batch * steps / (ms * 1e-3), 2),
+           "ms_per_step": round(ms / steps, 4), "alg_gbs": round(alg / (ms * 1e-3) / 1e9, 1),
+           "alg_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    fp.profile(0, True)
+    for k in range(min(steps, 5)):
+        fp.solve_wave(u0, None, C_SPEED, (k + 1) * DT, out=out)
+    torch.cuda.synchronize()
+    prof = fp.profile_read(0)
+    fp.profile(0, False)
+    res["kernels"] = [{"kernel": k["kernel"], "launches": k["launches"],
+                       "avg_us": round(k["total_ms"] / k["launches"] * 1e3, 2),
+                       "gbs": round(k["bytes"] / (k["total_ms"] * 1e-3) / 1e9, 1)} for k in prof]
+    if check:
+        t = min(steps, 5) * DT
+        res["err_vs_oracle"] = oracle_check(out[0], host[0], "c64", t)
+        res["err_tol"] = 2 * 2e-6 * math.log2(n)
+    del u0, out
+    return res
+
+
 def oracle_check(out_dev, host_field, dtype_name, t):
     """Relative L2 error of one GPU result against the FP64 oracle."""
     import numpy as np
@@ -411,6 +453,7 @@ def main(argv=None):
     ap.add_argument("--no-real", action="store_true", help="skip the real-field legs")
     ap.add_argument("--no-source", action="store_true", help="skip the constant-source leg")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D leg")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-radix (1536^2) leg")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-probe", action="store_true",
@@ -474,6 +517,10 @@ def main(argv=None):
     if not a.no_3d:
         print("# 3d leg", file=sys.stderr, flush=True)
         three = leg_3d(fp, torch, a.steps, a.warmup, not a.no_check)
+    mixed = None
+    if not a.no_mixed:
+        print("# mixed-radix leg", file=sys.stderr, flush=True)
+        mixed = mixed_leg(fp, torch, a.steps, a.warmup, not a.no_check)
     source = None
     if not a.no_source:
         print("# wave with a constant source leg", file=sys.stderr, flush=True)
@@ -536,6 +583,8 @@ def main(argv=None):
                                            "is real and even)", **real}
     if three:
         line["wave3d"] = three
+    if mixed:
+        line["wave_mixed_radix"] = mixed
     if source:
         line["wave_source"] = source
     if batch:
