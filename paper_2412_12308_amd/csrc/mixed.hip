@@ -248,7 +248,14 @@ __global__ void __launch_bounds__(mr_threads(sizeof(T) == 8)) mr_kernel(MrArgs<T
   const bool has2 = NF == 2 && a.in1 != nullptr;
   const bool out2 = NF == 2 && a.out1 != nullptr;
   constexpr int PT = (CAP + TH - 1) / TH;  // points per thread of a full tile
-  long long t = blockIdx.x;
+  // Round k of the walk covers tiles [k G, (k + 1) G).  Workgroups are
+  // dispatched to the 8 XCDs in turn (blockIdx mod 8), so a round hands each
+  // XCD G/8 consecutive tiles: adjacent column tiles, which share the cache
+  // lines of their row pieces, then meet in one L2.
+  const int G = gridDim.x;
+  const long long lane = (G % 8 == 0) ? (long long)(blockIdx.x % 8) * (G / 8) + blockIdx.x / 8 : blockIdx.x;
+  long long t = lane;
+  if (t >= a.tiles) return;
   while (true) {
     const Tile g = tile_at(t);
     // every load of the tile is issued before the first value lands in LDS
@@ -331,7 +338,7 @@ __global__ void __launch_bounds__(mr_threads(sizeof(T) == 8)) mr_kernel(MrArgs<T
         out[off] = conj_out ? cx<T>{v.re * sc, -v.im * sc} : v;
       }
     }
-    t += gridDim.x;
+    t += G;
     if (t >= a.tiles) break;
     __syncthreads();  // every thread is done with LDS before the next tile lands
   }
