@@ -139,6 +139,43 @@ def ifft2d(x, threads: int = 1) -> np.ndarray:
     return out
 
 
+def rfft2d(x, threads: int = 1) -> np.ndarray:
+    """Half spectrum of a real [ny][nx] field: columns a = 0 .. nx/2 of its
+    forward 2D transform (the others follow from X[-b][-a] = conj(X[b][a])
+    for real data, Sec. II.B)."""
+    x = np.asarray(x, dtype=np.float64)
+    ny, nx = x.shape
+    return fft2d(x.astype(np.complex128), threads=threads)[:, : nx // 2 + 1].copy()
+
+
+def hermitian_extension(X, nx: int) -> np.ndarray:
+    """The full [ny][nx] spectrum of which the half spectrum X ([ny][nx/2+1])
+    is the Hermitian part: columns 0 < a < nx/2 as given, a > nx/2 from
+    conj(X[-b][nx - a]), and columns a = 0 and a = nx/2 replaced by
+    (X[b][a] + conj(X[-b][a])) / 2."""
+    X = np.asarray(X, dtype=np.complex128)
+    ny, h = X.shape
+    assert h == nx // 2 + 1 and nx % 2 == 0
+    full = np.empty((ny, nx), dtype=np.complex128)
+    for b in range(ny):
+        bm = (-b) % ny
+        for a in range(nx):
+            if a == 0 or a == nx // 2:
+                full[b, a] = (X[b, a] + np.conj(X[bm, a])) / 2
+            elif a < nx // 2:
+                full[b, a] = X[b, a]
+            else:
+                full[b, a] = np.conj(X[bm, nx - a])
+    return full
+
+
+def irfft2d(X, nx: int, threads: int = 1) -> np.ndarray:
+    """The real field whose half spectrum is the Hermitian part of X: the
+    inverse 2D transform (1/(nx*ny)) of hermitian_extension(X, nx)."""
+    z = ifft2d(hermitian_extension(X, nx), threads=threads)
+    return z.real.copy()
+
+
 # ---------------------------------------------------------------------------
 # solves
 # ---------------------------------------------------------------------------
