@@ -201,6 +201,28 @@ int fft2d_forward(fftpde_ctx *ctx, const void *in, void *out, int nx, int ny, in
 int fft2d_inverse(fftpde_ctx *ctx, const void *in, void *out, int nx, int ny, int batch,
                   int dtype, fftpde_stream stream);
 
+/* ---- 2D transforms of real fields (half spectra) ----------------------------
+ * The transform of real data has X[-b][-a] = conj(X[b][a]) (Sec. II.B), so
+ * columns a = 0 .. nx/2 of the spectrum determine it: the half spectrum, a
+ * [ny][nx/2 + 1] complex field.
+ * fft2d_r2c: out = the half spectrum (unnormalised forward transform) of
+ *   each real field of `in`.  dtype FFTPDE_R32 (in: float, out: FP32
+ *   complex) or FFTPDE_R64 (double / FP64 complex); sides powers of two in
+ *   [2, 4096].
+ * fft2d_c2r: out = the real field whose half spectrum is the Hermitian part
+ *   of `in`, times 1/(nx ny): columns 0 < a < nx/2 as given, the rest of the
+ *   spectrum from the symmetry, and the self-conjugate columns a = 0 and
+ *   a = nx/2 replaced by (X[b][a] + conj(X[-b][a]))/2 (no change for half
+ *   spectra of real fields).  Same dtypes and sides.
+ * Both: in and out must not overlap (EINVAL).  Two real fields go through
+ *   one complex transform (row pass with real loads or stores), their
+ *   spectrum in the per-stream scratch; one more pass splits it into the
+ *   two half spectra (or joins them). */
+int fft2d_r2c(fftpde_ctx *ctx, const void *in, void *out, int nx, int ny, int batch, int dtype,
+              fftpde_stream stream);
+int fft2d_c2r(fftpde_ctx *ctx, const void *in, void *out, int nx, int ny, int batch, int dtype,
+              fftpde_stream stream);
+
 /* ---- spectral solves ----------------------------------------------------
  * Each is forward 2D FFT -> pointwise multiply by the equation's Fourier
  * symbol -> inverse 2D FFT.  The multiply and the 1/(nx ny) of the inverse

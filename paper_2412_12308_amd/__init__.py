@@ -116,6 +116,8 @@ def _declare(L):
     L.fftpde_version.restype = ctypes.c_char_p
     L.fftpde_last_error.restype = ctypes.c_char_p
     L.fft2d_forward.argtypes = [vp, vp, vp, i, i, i, i, vp]
+    L.fft2d_r2c.argtypes = [vp, vp, vp, i, i, i, i, vp]
+    L.fft2d_c2r.argtypes = [vp, vp, vp, i, i, i, i, vp]
     L.fft2d_inverse.argtypes = [vp, vp, vp, i, i, i, i, vp]
     L.solve_poisson.argtypes = [vp, vp, vp, i, i, i, d, d, i, vp]
     L.solve_diffusion.argtypes = [vp, vp, vp, i, i, i, d, d, d, d, i, vp]
@@ -167,7 +169,7 @@ def _declare(L):
               "fftpde_server_stats", "fftpde_server_destroy",
               "fftpde_batch_create", "fftpde_batch_run", "fftpde_batch_status", "fftpde_batch_info",
               "fftpde_batch_destroy", "fftpde_plan_small", "fftpde_plan_tiled", "fftpde_plan_chunk", "fftpde_evolve_create", "fftpde_evolve_step", "fftpde_evolve_destroy", "fftpde_autotune", "fftpde_plan_save", "fftpde_plan_load", "fftpde_plan_variants",
-              "fftpde_plan_select", "fftpde_profile", "fftpde_profile_read", "fftpde_create", "fftpde_destroy", "fft2d_forward", "fft2d_inverse", "solve_poisson",
+              "fftpde_plan_select", "fftpde_profile", "fftpde_profile_read", "fftpde_create", "fftpde_destroy", "fft2d_forward", "fft2d_inverse", "fft2d_r2c", "fft2d_c2r", "solve_poisson",
               "solve_diffusion", "solve_wave", "solve_diffusion_source", "solve_wave_source", "fftpde_wave_rk4",
               "fft3d_forward", "fft3d_inverse", "solve_poisson_3d", "solve_diffusion_3d", "solve_wave_3d"):
         getattr(L, f).restype = i
@@ -362,6 +364,45 @@ def fft2d_inverse(x, out=None):
     out = _like(x, out)
     _check(lib().fft2d_inverse(context(x.device.index), _ptr(x), _ptr(out), nx, ny, batch, dt,
                                _stream(x)), "fft2d_inverse")
+    return out
+
+
+def fft2d_r2c(x, out=None):
+    """Half spectrum [..., ny, nx/2 + 1] (complex) of real fields x [..., ny, nx]
+    (float32 -> complex64, float64 -> complex128): columns 0..nx/2 of the
+    unnormalised forward 2D FFT."""
+    torch = _torch()
+    nx, ny, batch, dt = _field(x, "x", True)
+    if dt not in (R32, R64):
+        raise ValueError("fft2d_r2c takes real fields (float32 / float64)")
+    shape = tuple(x.shape[:-1]) + (nx // 2 + 1,)
+    cdt = torch.complex64 if dt == R32 else torch.complex128
+    if out is None:
+        out = torch.empty(shape, dtype=cdt, device=x.device)
+    elif tuple(out.shape) != shape or out.dtype != cdt or not out.is_contiguous() or out.device != x.device:
+        raise ValueError(f"out must be a contiguous {cdt} tensor of shape {shape}")
+    _check(lib().fft2d_r2c(context(x.device.index), _ptr(x), _ptr(out), nx, ny, batch, dt, _stream(x)),
+           "fft2d_r2c")
+    return out
+
+
+def fft2d_c2r(X, nx: int, out=None):
+    """Real fields [..., ny, nx] whose half spectrum is the Hermitian part of
+    X [..., ny, nx/2 + 1] (complex64 -> float32, complex128 -> float64),
+    inverse 2D FFT times 1/(nx ny)."""
+    torch = _torch()
+    h, ny, batch, cdt = _field(X, "X")
+    if h != nx // 2 + 1:
+        raise ValueError(f"X has {h} columns; a half spectrum of width nx = {nx} has {nx // 2 + 1}")
+    dt = R32 if cdt == C64 else R64
+    shape = tuple(X.shape[:-1]) + (nx,)
+    rdt = torch.float32 if dt == R32 else torch.float64
+    if out is None:
+        out = torch.empty(shape, dtype=rdt, device=X.device)
+    elif tuple(out.shape) != shape or out.dtype != rdt or not out.is_contiguous() or out.device != X.device:
+        raise ValueError(f"out must be a contiguous {rdt} tensor of shape {shape}")
+    _check(lib().fft2d_c2r(context(X.device.index), _ptr(X), _ptr(out), nx, ny, batch, dt, _stream(X)),
+           "fft2d_c2r")
     return out
 
 

@@ -470,9 +470,23 @@ int check_common(fftpde_ctx* ctx, int nx, int ny, int batch, int dtype, bool rea
 
 bool is_mixed(int nx, int ny) { return !pow2_side(nx) || !pow2_side(ny); }
 
+
 int check_field(const void* p, int dtype) { return (p && aligned(p, dtype)) ? FFTPDE_OK : FFTPDE_EINVAL; }
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+// real fields (R32 / R64) <-> half spectra of the matching complex dtype
+int half_checks(fftpde_ctx* ctx, const void* real, const void* half, int nx, int ny, int batch, int dtype) {
+  if (dtype != FFTPDE_R32 && dtype != FFTPDE_R64) return FFTPDE_EINVAL;
+  int rc = check_common(ctx, nx, ny, batch, dtype, true);
+  if (rc == FFTPDE_OK) rc = check_field(real, dtype);
+  if (rc == FFTPDE_OK) rc = check_field(half, dtype == FFTPDE_R32 ? FFTPDE_C64 : FFTPDE_C128);
+  if (rc != FFTPDE_OK) return rc;
+  const size_t elem = dtype == FFTPDE_R32 ? 4 : 8;
+  const uintptr_t r0 = reinterpret_cast<uintptr_t>(real), h0 = reinterpret_cast<uintptr_t>(half);
+  const uintptr_t r1 = r0 + elem * (size_t)nx * ny * batch, h1 = h0 + 2 * elem * (size_t)(nx / 2 + 1) * ny * batch;
+  return (r0 < h1 && h0 < r1) ? FFTPDE_EINVAL : FFTPDE_OK;  // no overlap
+}
 
 }  // namespace
 
@@ -502,6 +516,24 @@ int fft2d_inverse(fftpde_ctx* ctx, const void* in, void* out, int nx, int ny, in
   if (is_mixed(nx, ny))
     return run_mixed_transform(c, dtype, true, in, out, nx, ny, batch, static_cast<hipStream_t>(stream));
   return run_transform(c, dtype, true, in, out, nx, ny, batch, static_cast<hipStream_t>(stream));
+}
+
+int fft2d_r2c(fftpde_ctx* ctx, const void* in, void* out, int nx, int ny, int batch, int dtype,
+              fftpde_stream stream) {
+  const int rc = half_checks(ctx, in, out, nx, ny, batch, dtype);
+  if (rc != FFTPDE_OK) return rc;
+  Context* c = reinterpret_cast<Context*>(ctx);
+  DeviceGuard g(c->device);
+  return run_half_transform(c, dtype, false, in, out, nx, ny, batch, static_cast<hipStream_t>(stream));
+}
+
+int fft2d_c2r(fftpde_ctx* ctx, const void* in, void* out, int nx, int ny, int batch, int dtype,
+              fftpde_stream stream) {
+  const int rc = half_checks(ctx, out, in, nx, ny, batch, dtype);
+  if (rc != FFTPDE_OK) return rc;
+  Context* c = reinterpret_cast<Context*>(ctx);
+  DeviceGuard g(c->device);
+  return run_half_transform(c, dtype, true, in, out, nx, ny, batch, static_cast<hipStream_t>(stream));
 }
 
 int solve_poisson(fftpde_ctx* ctx, const void* s_in, void* u, int nx, int ny, int batch, double lx, double ly,

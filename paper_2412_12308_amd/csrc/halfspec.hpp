@@ -1,0 +1,27 @@
+// halfspec.hpp -- conversions between the spectrum of a pair of real fields
+// (transformed as one complex field) and the two half spectra
+// [ny][nx/2 + 1] of the fields (fft2d_r2c / fft2d_c2r).  Sides are powers
+// of two.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fft_engine.hpp"
+
+namespace fftpde {
+
+template <typename T>
+struct HalfArgs {
+  cx<T>* spec;       // npairs complex [ny][nx] spectra (read by untangle, written by tangle)
+  cx<T>* half;       // nreal half spectra [ny][nx/2 + 1] (written by untangle, read by tangle)
+  int nx, ny;
+  long long npairs;  // pairs in this launch
+  long long nreal;   // real fields in this launch (2 npairs, or one less)
+};
+
+template <typename T>
+hipError_t launch_untangle(const HalfArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_tangle(const HalfArgs<T>& a, hipStream_t s);
+
+}  // namespace fftpde

@@ -4,6 +4,7 @@
 #include "solve.hpp"
 
 #include "diag.hpp"
+#include "halfspec.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -434,6 +435,66 @@ int run_transform(Context* c, int dtype, bool inverse, const void* in, void* out
   if (r != -100) return r;
   return dtype == FFTPDE_C64 ? transform<float>(c, in, out, nx, ny, batch, inverse, s)
                              : transform<double>(c, in, out, nx, ny, batch, inverse, s);
+}
+
+// fft2d_r2c / fft2d_c2r: real fields in pairs, each pair one complex field
+// (row pass with real loads or stores), its spectrum in the per-stream
+// scratch, and the half spectra split off (forward) or joined (inverse).
+template <typename T>
+int half_transform(Context* c, bool inverse, const void* in, void* out, int nx, int ny, int batch, hipStream_t s) {
+  const int dt = sizeof(T) == 4 ? FFTPDE_C64 : FFTPDE_C128;
+  const int lx = ilog2(nx), ly = ilog2(ny);
+  const long long pts = (long long)nx * ny, hpts = (long long)(nx / 2 + 1) * ny;
+  const size_t pair_bytes = sizeof(cx<T>) * (size_t)pts;
+  const long long npairs = (batch + 1) / 2;
+  const long long cb = c->chunk_bytes_for(dt, lx, ly);
+  long long chunk = cb > 0 ? std::max<long long>(1, cb / (long long)pair_bytes) : npairs;
+  chunk = std::min<long long>(chunk, npairs);
+  void* w = nullptr;
+  const int rcw = c->workspace(pair_bytes * (size_t)chunk, s, &w);
+  if (rcw != FFTPDE_OK) return rcw;
+  const SymParams sym = make_sym(kSymScale, nx, ny, 1.0, 1.0, 0.0, 0.0);
+  const char* name = inverse ? (sizeof(T) == 4 ? "tangle_float" : "tangle_double")
+                             : (sizeof(T) == 4 ? "untangle_float" : "untangle_double");
+  for (long long p0 = 0; p0 < npairs; p0 += chunk) {
+    const long long np = std::min<long long>(chunk, npairs - p0);
+    const long long nrows = (long long)ny * np;
+    const long long f0 = 2 * p0, nreal = std::min<long long>(2 * np, batch - f0);
+    const size_t real_off = sizeof(T) * (size_t)(f0 * pts), half_off = sizeof(cx<T>) * (size_t)(f0 * hpts);
+    HalfArgs<T> h{static_cast<cx<T>*>(w), nullptr, nx, ny, np, nreal};
+    const double hbytes = (double)sizeof(cx<T>) * (double)(np * pts + nreal * hpts);
+    int rc = FFTPDE_OK;
+    if (!inverse) {
+      h.half = static_cast<cx<T>*>(at<T>(out, half_off));
+      rc = row_pass<T>(c, at<T>(in, real_off), w, lx, ly, nrows, false, 1.0, s, -1, -1, 1, 0, nreal);
+      if (rc == FFTPDE_OK) rc = col_pass<T>(c, w, nullptr, w, nullptr, lx, ly, np, kColForward, sym, 1, s);
+      if (rc == FFTPDE_OK) {
+        const hipError_t e = timed_launch(c, name, hbytes, s, [&] { return launch_untangle<T>(h, s); });
+        if (e != hipSuccess) {
+          set_last_error(name, e);
+          rc = FFTPDE_EDEVICE;
+        }
+      }
+    } else {
+      h.half = static_cast<cx<T>*>(const_cast<void*>(at<T>(in, half_off)));
+      const hipError_t e = timed_launch(c, name, hbytes, s, [&] { return launch_tangle<T>(h, s); });
+      if (e != hipSuccess) {
+        set_last_error(name, e);
+        rc = FFTPDE_EDEVICE;
+      }
+      if (rc == FFTPDE_OK) rc = col_pass<T>(c, w, nullptr, w, nullptr, lx, ly, np, kColInverse, sym, 1, s);
+      if (rc == FFTPDE_OK)
+        rc = row_pass<T>(c, w, at<T>(out, real_off), lx, ly, nrows, true, 1.0, s, -1, -1, 0, 1, nreal);
+    }
+    if (rc != FFTPDE_OK) return rc;
+  }
+  return FFTPDE_OK;
+}
+
+int run_half_transform(Context* c, int dtype, bool inverse, const void* in, void* out, int nx, int ny, int batch,
+                       hipStream_t s) {
+  return dtype == FFTPDE_R32 ? half_transform<float>(c, inverse, in, out, nx, ny, batch, s)
+                             : half_transform<double>(c, inverse, in, out, nx, ny, batch, s);
 }
 
 int run_solve(Context* c, int dtype, int op, const void* in, const void* in2, void* out, void* out2, int nx, int ny,

@@ -45,6 +45,11 @@ int col_pass(Context* c, const void* in0, const void* in1, void* out0, void* out
 int run_transform(Context* c, int dtype, bool inverse, const void* in, void* out, int nx, int ny, int batch,
                   hipStream_t s);
 
+// fft2d_r2c (inverse = false: real fields -> half spectra [ny][nx/2 + 1]) and
+// fft2d_c2r (inverse = true, scaled by 1/(nx ny)); dtype FFTPDE_R32 / R64.
+int run_half_transform(Context* c, int dtype, bool inverse, const void* in, void* out, int nx, int ny, int batch,
+                       hipStream_t s);
+
 // A solve (op = FFTPDE_POISSON / DIFFUSION / WAVE; for the wave, in2 is the
 // initial velocity and out2 the velocity output, either may be null).
 int run_solve(Context* c, int dtype, int op, const void* in, const void* in2, void* out, void* out2, int nx, int ny,

@@ -322,3 +322,24 @@ def test_sides_that_are_not_powers_of_two_only_reach_the_mixed_radix_entry_point
     h = ctypes.c_void_p()
     assert L.fftpde_evolve_create(DUMMY, fp.WAVE, P, None, 12, 4, 1, 1.0, 1.0, 0.1, 0, None,
                                   ctypes.byref(h)) == fp.EINVAL
+
+
+def test_half_spectrum_transforms_reject_bad_arguments():
+    """fft2d_r2c / fft2d_c2r: real dtypes only, powers of two, aligned, and
+    input and output must not overlap -- all before touching the context."""
+    fp, L = _lib()
+    big = ctypes.create_string_buffer(1 << 16)
+    A = (ctypes.cast(big, ctypes.c_void_p).value + 255) // 256 * 256
+    B = A + 8192
+    for fn in (L.fft2d_r2c, L.fft2d_c2r):
+        for dtype in (0, 1, 4, -1):                          # complex or unknown dtypes
+            assert fn(DUMMY, A, B, 8, 8, 1, dtype, None) == fp.EINVAL
+        assert fn(DUMMY, A, B, 12, 8, 1, 2, None) == fp.EINVAL  # not a power of two
+        assert fn(DUMMY, A, B, 8, 1, 1, 2, None) == fp.EINVAL   # side below 2
+        assert fn(DUMMY, A, B, 8, 8, 0, 3, None) == fp.EINVAL   # empty batch
+        assert fn(None, A, B, 8, 8, 1, 2, None) == fp.EINVAL
+    # overlapping real field (8x8 floats = 256 B) and half spectrum (8x5 complex64)
+    assert L.fft2d_r2c(DUMMY, A, A + 128, 8, 8, 1, 2, None) == fp.EINVAL
+    assert L.fft2d_c2r(DUMMY, A + 64, A, 8, 8, 1, 2, None) == fp.EINVAL
+    # half spectra are complex: FP64 needs 16-byte alignment
+    assert L.fft2d_r2c(DUMMY, A, B + 8, 8, 8, 1, 3, None) == fp.EINVAL
