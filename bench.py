@@ -265,6 +265,42 @@ def mixed_leg(fp, torch, steps: int, warmup: int, check: bool, n: int = 1536, ba
     return res
 
 
+def half_spectrum_leg(fp, torch, host_fields, steps: int, warmup: int, check: bool):
+    """fft2d_r2c and fft2d_c2r of real FP32 fields (the real parts of the
+    pulse fields).  Algorithmic bytes of one transform: the real fields
+    (4 B per point) and the half spectra (8 B per point of [ny][nx/2+1])."""
+    import numpy as np
+
+    batch, ny, nx = host_fields.shape
+    x = torch.from_numpy(np.ascontiguousarray(host_fields.real)).to(torch.float32).to("cuda:0")
+    X = fp.fft2d_r2c(x)
+    y = torch.empty_like(x)
+    alg = (4.0 * nx * ny + 8.0 * (nx // 2 + 1) * ny) * batch
+    res = {"workload": f"half spectra of {batch} real {nx}x{ny} FP32 fields", "batch": batch}
+    for name, fn in (("r2c", lambda: fp.fft2d_r2c(x, out=X)), ("c2r", lambda: fp.fft2d_c2r(X, nx, out=y))):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        res[name] = {"ms": round(ms, 4), "fields_per_s": round(batch / (ms * 1e-3), 1),
+                     "alg_gbs": round(alg / (ms * 1e-3) / 1e9, 1),
+                     "alg_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    if check:
+        import oracle
+        x0 = x[0].cpu().numpy().astype(np.float64)
+        ref = oracle.rfft2d(x0, threads=oracle.default_threads())
+        res["r2c_err_vs_oracle"] = oracle.rel_l2(X[0].cpu().numpy().astype(np.complex128), ref)
+        res["round_trip_err"] = float(np.linalg.norm(y[0].cpu().numpy() - x0) / np.linalg.norm(x0))
+    del x, X, y
+    return res
+
+
 def oracle_check(out_dev, host_field, dtype_name, t):
     """Relative L2 error of one GPU result against the FP64 oracle."""
     import numpy as np
@@ -497,6 +533,7 @@ def main(argv=None):
         r64 = run_leg(fp, torch, f64, "c128", a.steps, a.warmup)
         err64 = None if a.no_check else oracle_check(r64["last_out"][0], f64[0], "c128", r64["last_t"])
     real = {}
+    half = None
     if not a.no_real:
         # the same real-valued initial data as real fields, two per complex
         # transform: 2B FP32 / B FP64 fields, the complex legs' bytes in flight
@@ -513,6 +550,8 @@ def main(argv=None):
                                        "avg_us": round(k["avg_us"], 2), "gbs": round(k["gbs"], 1)}
                                       for k in rr["kernels"]]}
             del rr
+        print("# half-spectrum leg", file=sys.stderr, flush=True)
+        half = half_spectrum_leg(fp, torch, fields, a.steps, a.warmup, not a.no_check)
     three = None
     if not a.no_3d:
         print("# 3d leg", file=sys.stderr, flush=True)
@@ -581,6 +620,8 @@ def main(argv=None):
         line["real_fields"] = {"workload": "the same wave problems with u0 stored as real fields, solved two "
                                            "per complex transform (S(u1 + i u2) = S(u1) + i S(u2): the symbol "
                                            "is real and even)", **real}
+    if half:
+        line["half_spectrum"] = half
     if three:
         line["wave3d"] = three
     if mixed:
