@@ -262,7 +262,9 @@ struct Symbol<T, kSymScale> {
 };
 
 // Wave propagator with an initial velocity: cw = cos(w t), sw = sin(w t),
-// sow = sin(w t)/w (t at w = 0), w = c |k|; all but the final rounding in FP64.
+// sow = sin(w t)/w (t at w = 0), w = c |k|.  FP64: all but the final
+// rounding in FP64.  FP32: the phase w t formed and reduced in FP64, then
+// FP32 sin/cos; w and sin(w t)/w, which only scale FP32 values, in FP32.
 template <typename T>
 struct WaveCoeffs {
   double hx2, hy, kx2, kys, c, t;
@@ -281,25 +283,32 @@ struct WaveCoeffs {
   __device__ __forceinline__ void operator()(int b, T& cw, T& sw, T& sow, T& w_out) const {
     const int bi = signed_index(b, logny);
     const double hyb = hy * bi, ky = kys * bi;
-    const double w = c * sqrt(fma(ky, ky, kx2));
-    // w t / pi; hx, hy carry t squared away, so restore its sign (sin is odd)
-    double h = sqrt(fma(hyb, hyb, hx2));
-    if (t < 0) h = -h;
     if constexpr (sizeof(T) == 4) {
+      // the phase w t / pi in FP64 (square root from an FP32 seed and one
+      // FP64 correction), reduced exactly; w itself only scales FP32 values,
+      // so it and sin(w t)/w are formed in FP32
+      double h = sqrt_fp64_from_fp32(fma(hyb, hyb, hx2));
+      if (t < 0) h = -h;  // hx, hy carry t squared away; sin is odd
       h = fma(-2.0, rint(0.5 * h), h);
       float s, cc;
       sincospif(float(h), &s, &cc);
+      const float w = float(c) * __builtin_amdgcn_sqrtf(float(fma(ky, ky, kx2)));
       cw = cc;
       sw = s;
-      sow = w == 0.0 ? T(t) : T(double(s) / w);
+      sow = w == 0.0f ? T(t) : s * __builtin_amdgcn_rcpf(w);
+      w_out = w;
     } else {
+      const double w = c * sqrt(fma(ky, ky, kx2));
+      // w t / pi; hx, hy carry t squared away, so restore its sign (sin is odd)
+      double h = sqrt(fma(hyb, hyb, hx2));
+      if (t < 0) h = -h;
       double s, cc;
       sincospi(h, &s, &cc);
       cw = cc;
       sw = s;
       sow = w == 0.0 ? t : s / w;
+      w_out = w;
     }
-    w_out = T(w);
   }
 };
 

@@ -180,28 +180,46 @@ int solve_real_symbol(Context* c, const void* in, void* out, int nx, int ny, int
   return FFTPDE_OK;
 }
 
+// The wave with an initial velocity and/or the velocity output: both
+// spectra go through one two-field column pass.  Like the one-field solves,
+// the spectra live in per-stream scratch in column blocks (the tiled
+// intermediate), two fields per 256 MiB chunk of fields.
 template <typename T>
 int solve_wave_two(Context* c, const void* u0, const void* v0, void* u, void* v, int nx, int ny, int batch,
                    const SymParams& sym, hipStream_t s) {
+  const int dt = sizeof(T) == 4 ? FFTPDE_C64 : FFTPDE_C128;
   const int lx = ilog2(nx), ly = ilog2(ny);
   const size_t field = sizeof(cx<T>) * (size_t)nx * ny;
-  const long long cb = c->chunk_bytes_for(sizeof(T) == 4 ? FFTPDE_C64 : FFTPDE_C128, lx, ly);
+  const long long cb = c->chunk_bytes_for(dt, lx, ly);
   const long long chunk = std::min<long long>(cb > 0 ? std::max<long long>(1, cb / (long long)field) : batch, batch);
-  void* vbuf = nullptr;  // the velocity's spectrum when no velocity output is asked for
-  if (v0 && !v) {
-    int rc = c->workspace(field * (size_t)chunk, s, &vbuf);
+  const ColVariant* cv = c->col_variant(dt, ly, 2);
+  if (!cv) return FFTPDE_EINVAL;
+  const int tiled_bytes = c->tiled_bytes_for(dt, lx, ly);
+  int lt = -1;
+  if (tiled_bytes > 0) {
+    int bt = 0;  // log2 of the block width in columns
+    while ((int)sizeof(cx<T>) << (bt + 1) <= tiled_bytes) bt++;
+    lt = bt > cv->logt ? bt : cv->logt;
+    if (lt >= lx) lt = -1;
+  }
+  // spectra: F (then U) and G (then V); in the outputs when row-major
+  void* w = nullptr;
+  if (lt >= 0 || (v0 && !v)) {
+    const int rc = c->workspace(field * (size_t)chunk * (lt >= 0 ? 2 : 1), s, &w);
     if (rc != FFTPDE_OK) return rc;
   }
   return for_chunks<T>(c, nx, ny, batch, [&](long long, long long nb, size_t off) {
     const long long nrows = (long long)ny * nb;
     void* ub = at<T>(u, off);
     void* vb = at<T>(v, off);
-    void* gb = v0 ? (v ? vb : vbuf) : nullptr;
-    int rc = row_pass<T>(c, at<T>(u0, off), ub, lx, ly, nrows, false, 1.0, s);
-    if (rc == FFTPDE_OK && v0) rc = row_pass<T>(c, at<T>(v0, off), gb, lx, ly, nrows, false, 1.0, s);
-    if (rc == FFTPDE_OK) rc = col_pass<T>(c, ub, gb, ub, vb, lx, ly, nb, kColFwdMulInv, sym, 2, s);
-    if (rc == FFTPDE_OK) rc = row_pass<T>(c, ub, ub, lx, ly, nrows, true, 1.0, s);
-    if (rc == FFTPDE_OK && vb) rc = row_pass<T>(c, vb, vb, lx, ly, nrows, true, 1.0, s);
+    void* fs = lt >= 0 ? w : ub;
+    void* gs = lt >= 0 ? static_cast<char*>(w) + field * (size_t)chunk : (v ? vb : w);
+    int rc = row_pass<T>(c, at<T>(u0, off), fs, lx, ly, nrows, false, 1.0, s, -1, lt);
+    if (rc == FFTPDE_OK && v0) rc = row_pass<T>(c, at<T>(v0, off), gs, lx, ly, nrows, false, 1.0, s, -1, lt);
+    if (rc == FFTPDE_OK)
+      rc = col_pass<T>(c, fs, v0 ? gs : nullptr, fs, v ? gs : nullptr, lx, ly, nb, kColFwdMulInv, sym, 2, s, lt);
+    if (rc == FFTPDE_OK) rc = row_pass<T>(c, fs, ub, lx, ly, nrows, true, 1.0, s, lt, -1);
+    if (rc == FFTPDE_OK && vb) rc = row_pass<T>(c, gs, vb, lx, ly, nrows, true, 1.0, s, lt, -1);
     return rc;
   });
 }
@@ -248,7 +266,7 @@ int solve_real_pairs(Context* c, const void* in, const void* in2, void* out, voi
   if (!cv) return FFTPDE_EINVAL;
   int lt = -1;
   const int tiled_bytes = c->tiled_bytes_for(dt, lx, ly);
-  if (nf == 1 && tiled_bytes > 0) {
+  if (tiled_bytes > 0) {
     int bt = 0;
     while ((int)sizeof(cx<T>) << (bt + 1) <= tiled_bytes) bt++;
     lt = bt > cv->logt ? bt : cv->logt;
@@ -266,14 +284,14 @@ int solve_real_pairs(Context* c, const void* in, const void* in2, void* out, voi
     const size_t off = sizeof(T) * (size_t)(f0 * pts);
     int rc = row_pass<T>(c, at<T>(in, off), mid, lx, ly, nrows, false, 1.0, s, -1, lt, 1, 0, nreal);
     if (rc == FFTPDE_OK && nf == 2) {
-      if (in2) rc = row_pass<T>(c, at<T>(in2, off), mid2, lx, ly, nrows, false, 1.0, s, -1, -1, 1, 0, nreal);
+      if (in2) rc = row_pass<T>(c, at<T>(in2, off), mid2, lx, ly, nrows, false, 1.0, s, -1, lt, 1, 0, nreal);
     }
     if (rc == FFTPDE_OK)
       rc = col_pass<T>(c, mid, nf == 2 && in2 ? mid2 : nullptr, mid, nf == 2 && out2 ? mid2 : nullptr, lx, ly, np,
                        kColFwdMulInv, sym, nf, s, lt);
     if (rc == FFTPDE_OK) rc = row_pass<T>(c, mid, at<T>(out, off), lx, ly, nrows, true, 1.0, s, lt, -1, 0, 1, nreal);
     if (rc == FFTPDE_OK && out2)
-      rc = row_pass<T>(c, mid2, at<T>(out2, off), lx, ly, nrows, true, 1.0, s, -1, -1, 0, 1, nreal);
+      rc = row_pass<T>(c, mid2, at<T>(out2, off), lx, ly, nrows, true, 1.0, s, lt, -1, 0, 1, nreal);
     if (rc != FFTPDE_OK) return rc;
   }
   return FFTPDE_OK;
