@@ -295,7 +295,8 @@ struct WaveCoeffs {
       const float w = float(c) * __builtin_amdgcn_sqrtf(float(fma(ky, ky, kx2)));
       cw = cc;
       sw = s;
-      sow = w == 0.0f ? T(t) : s * __builtin_amdgcn_rcpf(w);
+      // below 1e-18, sin(w t)/w = t to far better than FP32 (and 1/w would overflow)
+      sow = w > 1e-18f ? s * __builtin_amdgcn_rcpf(w) : T(t);
       w_out = w;
     } else {
       const double w = c * sqrt(fma(ky, ky, kx2));
@@ -319,7 +320,8 @@ struct WaveCoeffs {
 //   wave       U = cos(w t) F + sin(w t)/w G + p S,  V = -w sin(w t) F + cos(w t) G + sin(w t)/w S,
 //              p = (1 - cos(w t))/w^2 = 2 sin^2(w t/2)/w^2 (t^2/2 at w = 0)
 // The half-angle form and expm1 keep p and m accurate where w t or q t is
-// small; all arguments are formed in FP64.
+// small.  Arguments (q t and the phase w t) are formed in FP64; with FP32
+// fields, w and the ratios that only scale FP32 values are FP32.
 template <typename T>
 struct SourceCoeffs {
   int op, logny;
@@ -349,29 +351,44 @@ struct SourceCoeffs {
       ug = vf = vg = vs = T(0);
       return;
     }
-    const double w = c * sqrt(k2);
     const double hyb = hy * bi;
-    double h = sqrt(fma(hyb, hyb, hx2));  // |w t| / pi
-    if (t < 0) h = -h;
-    double cw, sw, hs;
     if constexpr (sizeof(T) == 4) {
-      h = fma(-2.0, rint(0.5 * h), h);  // reduction to [-1, 1], exact
+      // the phase in FP64 (square root from an FP32 seed and one FP64
+      // correction) reduced exactly to [-1, 1]; w, which only scales FP32
+      // values, in FP32
+      double h = sqrt_fp64_from_fp32(fma(hyb, hyb, hx2));  // |w t| / pi
+      if (t < 0) h = -h;
+      h = fma(-2.0, rint(0.5 * h), h);
       float s1, c1;
       sincospif(float(h), &s1, &c1);
-      cw = c1;
-      sw = s1;
-      hs = sinpif(float(0.5 * h));  // sin(w t/2) up to sign
+      const float hs = sinpif(float(0.5 * h));  // sin(w t/2) up to sign
+      const float w = float(c) * __builtin_amdgcn_sqrtf(float(k2));
+      // below 1e-18 the w -> 0 limits hold to far better than FP32
+      const bool live = w > 1e-18f;
+      const float rw = live ? __builtin_amdgcn_rcpf(w) : 0.0f;
+      const float sow = live ? s1 * rw : float(t);
+      const float hw = hs * rw;
+      uf = c1;
+      ug = sow;
+      us = live ? 2.0f * hw * hw : float(0.5 * t * t);
+      vf = -w * s1;
+      vg = c1;
+      vs = sow;
     } else {
+      const double w = c * sqrt(k2);
+      double h = sqrt(fma(hyb, hyb, hx2));  // |w t| / pi
+      if (t < 0) h = -h;
+      double cw, sw;
       sincospi(h, &sw, &cw);
-      hs = sinpi(0.5 * h);
+      const double hs = sinpi(0.5 * h);
+      const double sow = w == 0.0 ? t : sw / w;
+      uf = cw;
+      ug = sow;
+      us = w == 0.0 ? 0.5 * t * t : 2.0 * hs * hs / (w * w);
+      vf = -w * sw;
+      vg = cw;
+      vs = sow;
     }
-    const double sow = w == 0.0 ? t : sw / w;
-    uf = T(cw);
-    ug = T(sow);
-    us = w == 0.0 ? T(0.5 * t * t) : T(2.0 * hs * hs / (w * w));
-    vf = T(-w * sw);
-    vg = T(cw);
-    vs = T(sow);
   }
 };
 
