@@ -124,13 +124,15 @@ __device__ __forceinline__ int signed_index(int a, int logn) {
 
 // sqrt of a non-negative FP64 value to about 1e-14 relative: an FP32 square
 // root refined by one Newton step in FP64 (the error squares), cheaper than
-// the correctly rounded FP64 root and ample for an FP32 result.
+// the correctly rounded FP64 root and ample for an FP32 result.  Values that
+// the FP32 seed cannot represent (positive below 1e-30, e.g. a wave speed
+// near zero, or above 1e36) take the FP64 root; 0 and negatives give 0.
 __device__ __forceinline__ double sqrt_fp64_from_fp32(double v) {
+  if (!(v >= 1e-30 && v <= 1e36)) return v > 0.0 ? sqrt(v) : 0.0;
   const float s0 = __builtin_amdgcn_sqrtf(float(v));
   const double d = double(s0);
   const double r = fma(-d, d, v);
-  const double h = fma(r, double(0.5f * __builtin_amdgcn_rcpf(s0)), d);
-  return v > 0.0 ? h : 0.0;
+  return fma(r, double(0.5f * __builtin_amdgcn_rcpf(s0)), d);
 }
 
 // cos(pi r) for |r| <= 1/2 in FP32: the Taylor series of cos about 0 in
