@@ -368,13 +368,12 @@ int fftpde_evolve_destroy(fftpde_evolve *ev);
 /* ---- batches of uneven solves ---------------------------------------------
  * Many independent solves of different power-of-two shapes, operators, boxes
  * and times (the per-field work of Sec. III, for many small and medium
- * fields at once) in three launches of persistent kernels: every job is a
- * row pass, a fused column pass (forward y FFT, symbol, inverse y FFT) and
- * an inverse row pass, cut into tiles of 8192 (FP32) / 4096 (FP64) points;
- * each launch runs one of the three passes for every job, its workgroups
- * taking tiles from that pass's queue (largest jobs first).  Each job is
- * computed exactly as the single-field solves above define it (same
- * symbols, same FP64 phases and exponents).
+ * fields at once) as ONE persistent kernel: every job is a row pass, a fused
+ * column pass (forward y FFT, symbol, inverse y FFT) and an inverse row pass,
+ * cut into tiles of 8192 (FP32) / 4096 (FP64) points; workgroups take tiles
+ * from one queue and a job's column tiles start as soon as its own row tiles
+ * are done.  Each job is computed exactly as the single-field solves above
+ * define it (same symbols, same FP64 phases and exponents).
  *
  * fftpde_job: op = FFTPDE_POISSON (coef, t unused), FFTPDE_DIFFUSION
  *   (coef = kappa >= 0, t >= 0) or FFTPDE_WAVE (coef = c >= 0, t finite,
@@ -388,14 +387,13 @@ int fftpde_evolve_destroy(fftpde_evolve *ev);
  *   buffers between runs.  Errors: EINVAL (any bad job or overlap; nothing is
  *   allocated), ENOMEM, EDEVICE.
  * fftpde_batch_run: enqueues one run on `stream`: replays the captured graph
- *   (use_graph != 0) or launches the same four kernels (a reset and the three
- *   passes) directly (use_graph = 0, e.g. inside a caller's own capture).
- *   Runs of one batch share its queue counters: runs on different streams
- *   must not overlap in time.
- * fftpde_batch_status: waits for `stream`, then returns FFTPDE_OK
- *   (FFTPDE_ETIMEOUT is reserved: no pass waits inside a launch).
- * fftpde_batch_info: number of tiles in the queues, the largest number of
- *   workgroups of one of the three launches and
+ *   (use_graph != 0) or launches the same two kernels directly (use_graph = 0,
+ *   e.g. inside a caller's own capture).  Runs of one batch share its queue
+ *   and counters: runs on different streams must not overlap in time.
+ * fftpde_batch_status: waits for `stream`, then returns FFTPDE_OK, or
+ *   FFTPDE_ETIMEOUT if a tile's wait for its job's previous step gave up
+ *   (about a second; results of that run are then invalid).
+ * fftpde_batch_info: number of tiles in the queue, workgroups launched and
  *   algorithmic HBM bytes of one run (6 field passes per job); NULL outputs
  *   are skipped.
  * fftpde_batch_destroy: frees the batch (waits for nothing: the caller

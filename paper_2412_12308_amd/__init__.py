@@ -606,9 +606,8 @@ class Evolution:
 
 
 class Batch:
-    """Many independent solves of uneven power-of-two shapes run by three
-    persistent kernels (fftpde_batch_*, one per pass), replayed from a
-    captured HIP graph.
+    """Many independent solves of uneven power-of-two shapes run by one
+    persistent kernel (fftpde_batch_*), replayed from a captured HIP graph.
 
     jobs: sequence of dicts with keys op (POISSON / DIFFUSION / WAVE), inp (a
     [ny, nx] complex device tensor), and optionally out (default: a new

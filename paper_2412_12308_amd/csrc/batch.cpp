@@ -1,6 +1,5 @@
 // batch.cpp -- planning and launching a batch of uneven solves: job checks,
-// the per-step item queues, device tables and the captured graph (reset +
-// the three step kernels).
+// the item queue, device tables and the captured graph (reset + kernel).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,7 +22,7 @@ struct fftpde_batch {
   int dtype = 0;
   int njobs = 0;
   long long nitems = 0;
-  int grid[3] = {};
+  int grid = 0;
   double bytes = 0.0;  // algorithmic HBM bytes of one run
   void* dmem = nullptr;
   BatchArgs args{};
@@ -92,7 +91,7 @@ void destroy_batch(fftpde_batch* b) {
 }
 
 hipError_t enqueue(fftpde_batch* b, hipStream_t s) {
-  hipError_t e = batch_reset(b->args.ctl, s);
+  hipError_t e = batch_reset(b->args.ctl, b->args.done, b->njobs, s);
   if (e == hipSuccess) e = batch_launch(b->dtype == FFTPDE_C128, b->args, b->grid, s);
   return e;
 }
@@ -137,14 +136,11 @@ int fftpde_batch_create(fftpde_ctx* ctx, const fftpde_job* jobs, int njobs, int 
     return (long long)jobs[a].nx * jobs[a].ny > (long long)jobs[b].nx * jobs[b].ny;
   });
   std::vector<BatchItem> items;
-  long long begin[4] = {0, 0, 0, 0};
-  for (int s = 0; s < 3; s++) {
-    begin[s] = (long long)items.size();
+  for (int s = 0; s < 3; s++)
     for (int i : order)
-      for (int t = 0; t < ntile[s][i]; t++) items.push_back({i, t});
-  }
-  begin[3] = (long long)items.size();
-  if (items.size() > (size_t)0x7fffffff) return FFTPDE_EINVAL;  // item indices fit 31 bits
+      for (int t = 0; t < ntile[s][i]; t++) items.push_back({i, s, t, s > 0 ? ntile[s - 1][i] : 0});
+
+  if (items.size() > (size_t)0x7fffffff) return FFTPDE_EINVAL;  // 32-bit tile counters
 
   auto* b = new fftpde_batch();
   b->ctx = c;
@@ -152,15 +148,13 @@ int fftpde_batch_create(fftpde_ctx* ctx, const fftpde_job* jobs, int njobs, int 
   b->njobs = njobs;
   b->nitems = (long long)items.size();
   b->bytes = bytes;
-  for (int s = 0; s < 3; s++) {
-    const long long claims = (begin[s + 1] - begin[s] + kBatchClaim - 1) / kBatchClaim;
-    long long g = (long long)std::max(1, batch_occupancy(fp64, s)) * std::max(1, c->num_cus);
-    b->grid[s] = (int)std::max<long long>(1, std::min(g, claims));
-  }
+  const int occ = batch_occupancy(fp64);
+  b->grid = std::max(1, occ) * std::max(1, c->num_cus);
+  if (b->grid > b->nitems) b->grid = (int)b->nitems;
 
-  // one device allocation: control word, jobs, items
-  const size_t o_ctl = 0;
-  const size_t o_jobs = align_up(sizeof(BatchCtl));
+  // one device allocation: control word, counters, jobs, items
+  const size_t o_ctl = 0, o_done = align_up(sizeof(BatchCtl));
+  const size_t o_jobs = o_done + align_up(sizeof(unsigned) * 2 * (size_t)njobs);
   const size_t o_items = o_jobs + align_up(sizeof(BatchJobDesc) * (size_t)njobs);
   const size_t total = o_items + align_up(sizeof(BatchItem) * items.size());
   hipError_t e = hipSetDevice(c->device);
@@ -172,10 +166,16 @@ int fftpde_batch_create(fftpde_ctx* ctx, const fftpde_job* jobs, int njobs, int 
   }
   char* base = static_cast<char*>(b->dmem);
   b->args.ctl = reinterpret_cast<BatchCtl*>(base + o_ctl);
+  b->args.done = reinterpret_cast<unsigned*>(base + o_done);
   b->args.jobs = reinterpret_cast<const BatchJobDesc*>(base + o_jobs);
   b->args.items = reinterpret_cast<const BatchItem*>(base + o_items);
+  b->args.nitems = b->nitems;
   b->args.njobs = njobs;
-  for (int s = 0; s < 4; s++) b->args.begin[s] = begin[s];
+  for (int s = 0; s < 2; s++) {
+    long long n = 0;
+    for (int i = 0; i < njobs; i++) n += ntile[s][i];
+    b->args.step_items[s] = (unsigned)n;
+  }
   b->args.tw = fp64 ? static_cast<const void*>(c->tw64) : static_cast<const void*>(c->tw32);
   for (int l = 0; l <= kBatchMaxLog; l++)
     for (int r = 0; r < 2; r++) b->args.stw[l][r] = l >= 1 ? c->stage_tw_at[l][3][r] : 0;
@@ -231,7 +231,7 @@ int fftpde_batch_status(fftpde_batch* b, fftpde_stream stream) {
 int fftpde_batch_info(const fftpde_batch* b, long long* items, int* grid, double* bytes) {
   if (!b) return FFTPDE_EINVAL;
   if (items) *items = b->nitems;
-  if (grid) *grid = std::max(b->grid[0], std::max(b->grid[1], b->grid[2]));
+  if (grid) *grid = b->grid;
   if (bytes) *bytes = b->bytes;
   return FFTPDE_OK;
 }

@@ -1,6 +1,5 @@
-// batch.hip -- the batch's three step kernels (row forward, column, row
-// inverse): queue claims and the row / column tiles for every side 16..4096
-// (workgroups of 512).
+// batch.hip -- the persistent batch kernel: queue, per-job dependencies and
+// the row / column tiles for every side 16..4096 (one workgroup of 512).
 #include "batch.hpp"
 
 namespace fftpde {
@@ -97,91 +96,147 @@ __device__ __forceinline__ void dispatch_col(int logn, cx<T>* data, int lognx, i
   }
 }
 
-// One step of the batch: every tile of that step of every job, persistent
-// workgroups claiming runs of kBatchClaim items.  The steps are three launches in
-// stream order, so a step reads what the previous one wrote with no waits or
-// fences of its own.
-template <typename T, int STEP>
-__global__ void __launch_bounds__(kBatchTH) batch_step_kernel(BatchArgs a) {
+// about a second of polling
+constexpr long kSpinLimit = 1l << 22;
+// completions a workgroup may hold before it publishes them
+constexpr int kMaxPending = 64;
+// consecutive queue items taken by one atomic: the queue head is one counter
+// that every workgroup updates, and its atomics serialize (one item per
+// atomic spent about 0.65 ms of queue traffic per run of the 1024-job batch)
+constexpr int kClaim = 4;
+
+// Publication.  A finished row-forward or column tile is not announced at
+// once: the workgroup notes it (job counter index) in LDS and publishes its
+// notes together -- every wave drains its stores, one agent-scope release
+// (an L2 write-back) covers the workgroup, then relaxed counter increments --
+// before it takes an item of a later step (the only items that may wait),
+// when the notes are full, and when the queue is empty.  A workgroup holding
+// unpublished notes is thus always working on an item that does not wait, so
+// every note is eventually published and no wait can be circular.
+//
+// Acquisition.  A waiting item spins on its job's counter, then one wave
+// performs an agent-scope acquire (invalidating this CU's and XCD's cached
+// lines) before any wave reads.  Once a workgroup has done that after the
+// whole batch's previous step was published (the step counters), its later
+// items of that step need neither the wait nor the invalidation.
+template <typename T>
+__global__ void __launch_bounds__(kBatchTH) batch_kernel(BatchArgs a) {
   __shared__ cx<T> lds[BatchCfg<T>::kLdsElems];
   __shared__ long long s_item;
+  __shared__ int s_note[kMaxPending];
+  __shared__ int s_flag;
   int tid = threadIdx.x;
   const cx<T>* tw = static_cast<const cx<T>*>(a.tw);
-  const long long lo = a.begin[STEP], hi = a.begin[STEP + 1];
-  auto claim = [&]() {
-    return lo + (long long)__hip_atomic_fetch_add(&a.ctl->head[STEP], (unsigned long long)kBatchClaim, __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
+  int nnote = 0, note_step = 0;  // uniform across the workgroup
+  int acquired = 0;              // bit s: step s items need no wait
+
+  auto publish = [&]() {
+    if (nnote == 0) return;
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have reached its L2
+    __syncthreads();
+    if (tid == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      for (int k = 0; k < nnote; k++)
+        __hip_atomic_fetch_add(&a.done[s_note[k]], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&a.ctl->step_done[note_step], (unsigned)nnote, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    }
+    nnote = 0;
   };
-  if (tid == 0) s_item = claim();
+
+  auto claim = [&]() {
+    return __hip_atomic_fetch_add(&a.ctl->head, (unsigned long long)kClaim, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+  };
+  if (tid == 0) s_item = (long long)claim();
   __syncthreads();
   long long base = s_item;
-  while (base < hi) {
+  while (base < a.nitems) {
     // the next claim travels while this one is worked on
-    long long next = 0;
+    unsigned long long next = 0;
     if (tid == 0) next = claim();
-    const long long end = min(base + kBatchClaim, hi);
+    const long long end = min(base + kClaim, a.nitems);
     for (long long it = base; it < end; it++) {
       // keeps per-stage addresses from being hoisted out of the item loop
       // (they would all stay live in registers across items)
       tid = opaque(tid);
       const BatchItem item = a.items[it];
+      if (nnote > 0 && (item.step != note_step || nnote == kMaxPending)) publish();
+      if (item.step > 0 && !((acquired >> item.step) & 1)) {
+        if (tid == 0) {
+          const unsigned* cnt = &a.done[2 * item.job + item.step - 1];
+          long spins = 0;
+          while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (unsigned)item.need) {
+            __builtin_amdgcn_s_sleep(8);
+            if (++spins > kSpinLimit) {
+              __hip_atomic_store(&a.ctl->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              break;
+            }
+          }
+          const unsigned all = __hip_atomic_load(&a.ctl->step_done[item.step - 1], __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          s_flag = all >= a.step_items[item.step - 1];
+        }
+        __syncthreads();
+        if (s_flag) acquired |= 1 << item.step;
+      }
       const BatchJobDesc& job = a.jobs[item.job];
       const int lognx = job.sym.lognx, logny = job.sym.logny;
       cx<T>* out = static_cast<cx<T>*>(job.out);
-      if constexpr (STEP == 1) {
+      if (item.step == 1) {
         dispatch_col<T>(logny, out, lognx, item.tile, job.sym, tw, a, lds, tid);
       } else {
-        const cx<T>* src = STEP == 0 ? static_cast<const cx<T>*>(job.in) : out;
-        dispatch_row<T>(lognx, src, out, 1 << logny, item.tile, STEP == 2, tw, a, lds, tid);
+        const cx<T>* src = item.step == 0 ? static_cast<const cx<T>*>(job.in) : out;
+        dispatch_row<T>(lognx, src, out, 1 << logny, item.tile, item.step == 2, tw, a, lds, tid);
+      }
+      if (item.step < 2) {
+        if (tid == 0) s_note[nnote] = 2 * item.job + item.step;
+        note_step = item.step;
+        nnote++;
       }
     }
     __syncthreads();  // every thread has read s_item
-    if (tid == 0) s_item = next;
+    if (tid == 0) s_item = (long long)next;
     __syncthreads();
     base = s_item;
   }
+  publish();
 }
 
-__global__ void batch_reset_kernel(BatchCtl* ctl) {
-  if (threadIdx.x == 0) {
-    ctl->head[0] = 0;
-    ctl->head[1] = 0;
-    ctl->head[2] = 0;
+__global__ void batch_reset_kernel(BatchCtl* ctl, unsigned* done, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    ctl->head = 0;
+    ctl->step_done[0] = 0;
+    ctl->step_done[1] = 0;
     ctl->error = 0;
   }
-}
-
-template <typename T, int STEP>
-int occ() {
-  int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_step_kernel<T, STEP>, kBatchTH, 0) != hipSuccess)
-    return 0;
-  return n;
+  if (i < n) done[i] = 0;
 }
 
 template <typename T>
-void launch_steps(const BatchArgs& a, const int grid[3], hipStream_t s) {
-  hipLaunchKernelGGL((batch_step_kernel<T, 0>), dim3(grid[0]), dim3(kBatchTH), 0, s, a);
-  hipLaunchKernelGGL((batch_step_kernel<T, 1>), dim3(grid[1]), dim3(kBatchTH), 0, s, a);
-  hipLaunchKernelGGL((batch_step_kernel<T, 2>), dim3(grid[2]), dim3(kBatchTH), 0, s, a);
+int occ() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel<T>, kBatchTH, 0) != hipSuccess) return 0;
+  return n;
 }
 
 }  // namespace
 
-hipError_t batch_launch(int fp64, const BatchArgs& a, const int grid[3], hipStream_t s) {
-  if (fp64) launch_steps<double>(a, grid, s);
-  else launch_steps<float>(a, grid, s);
+hipError_t batch_launch(int fp64, const BatchArgs& a, int grid, hipStream_t s) {
+  if (fp64) hipLaunchKernelGGL(batch_kernel<double>, dim3(grid), dim3(kBatchTH), 0, s, a);
+  else hipLaunchKernelGGL(batch_kernel<float>, dim3(grid), dim3(kBatchTH), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t batch_reset(BatchCtl* ctl, hipStream_t s) {
-  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, ctl);
+hipError_t batch_reset(BatchCtl* ctl, unsigned* done, int njobs, hipStream_t s) {
+  const int n = 2 * njobs;
+  const int blocks = n / 256 + 1;
+  hipLaunchKernelGGL(batch_reset_kernel, dim3(blocks), dim3(256), 0, s, ctl, done, n);
   return hipGetLastError();
 }
 
-int batch_occupancy(int fp64, int step) {
-  if (fp64) return step == 0 ? occ<double, 0>() : step == 1 ? occ<double, 1>() : occ<double, 2>();
-  return step == 0 ? occ<float, 0>() : step == 1 ? occ<float, 1>() : occ<float, 2>();
-}
+int batch_occupancy(int fp64) { return fp64 ? occ<double>() : occ<float>(); }
 
 }  // namespace fftpde

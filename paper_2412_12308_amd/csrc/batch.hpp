@@ -5,12 +5,16 @@
 // Every job is three steps of tiles: row tiles of x forward transforms
 // (in -> out), column tiles that run the y forward transform, multiply by the
 // job's symbol and run the y inverse (out -> out), and row tiles of x inverse
-// transforms (out -> out).  Each step is one launch of a persistent kernel
-// over that step's tiles of every job (largest jobs first); the three
-// launches run in stream order, so a step sees everything the previous one
-// wrote without any waits.  Workgroups claim a few consecutive tiles at a
-// time from the step's queue counter (the next claim travels while the
-// current one is worked on).
+// transforms (out -> out).  All tiles of all jobs sit in one queue, first
+// every row-forward tile, then every column tile, then every row-inverse
+// tile, largest jobs first.  Workgroups claim a few consecutive items at a
+// time with one atomic counter (the next claim travels while the current one
+// is worked on) and work through them in queue order; an item of step s
+// waits until its job's step s-1 tiles are all published (a per-job
+// counter).  An item only ever waits on items earlier in the queue, so the
+// queue drains whatever the number of resident workgroups (see the
+// publication rule in batch.hip).  Each wait is still bounded and reports a
+// timeout through an error flag instead of spinning forever.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -22,11 +26,6 @@ namespace fftpde {
 constexpr int kBatchTH = 512;
 constexpr int kBatchMinLog = 4;   // sides 16 ..
 constexpr int kBatchMaxLog = 12;  // .. 4096
-// consecutive queue items taken by one atomic: a step's queue head is one
-// counter that all its workgroups update, and those atomics serialize (one
-// item per atomic spent about 0.65 ms of queue traffic per run of a
-// 1024-job batch)
-constexpr int kBatchClaim = 4;
 
 template <typename T>
 struct BatchCfg {
@@ -47,32 +46,36 @@ struct BatchJobDesc {
 
 struct BatchItem {
   int job;
+  int step;   // 0: row forward, 1: column, 2: row inverse
   int tile;
+  int need;   // tiles of the job's previous step (0 for step 0)
 };
 
 struct BatchCtl {
-  unsigned long long head[3];  // next item of each step (relative to its range)
-  int error;                   // always 0 (no step waits); read by fftpde_batch_status
+  unsigned long long head;  // next item
+  unsigned step_done[2];    // published tiles of steps 0 and 1, whole batch
+  int error;                // 1: a dependency wait timed out
   int pad;
 };
 
 struct BatchArgs {
   const BatchJobDesc* jobs;
   const BatchItem* items;
-  long long begin[4];  // items of step s: [begin[s], begin[s + 1])
+  long long nitems;
   BatchCtl* ctl;
+  unsigned* done;  // per job: [row-forward tiles done, column tiles done]
   int njobs;
+  unsigned step_items[2];  // tiles of steps 0 and 1, whole batch
   const void* tw;
   // entry offsets from tw of the stage tables (Engine::stw_off) of the
   // radix-8 plans: stw[log2 length][0 forward, 1 reversed]
   int stw[kBatchMaxLog + 1][2];
 };
 
-// the three step launches, grid[s] persistent workgroups each
-hipError_t batch_launch(int fp64, const BatchArgs& a, const int grid[3], hipStream_t s);
-// Clears the queue heads and the error word (a kernel, so the reset may be
-// captured in a graph).
-hipError_t batch_reset(BatchCtl* ctl, hipStream_t s);
-int batch_occupancy(int fp64, int step);
+hipError_t batch_launch(int fp64, const BatchArgs& a, int grid, hipStream_t s);
+// Clears the queue head, the error flag and the per-job counters (a kernel,
+// so the reset may be captured in a graph).
+hipError_t batch_reset(BatchCtl* ctl, unsigned* done, int njobs, hipStream_t s);
+int batch_occupancy(int fp64);
 
 }  // namespace fftpde
