@@ -12,9 +12,10 @@
 // Persistent workgroups walk the tiles (whole lines, up to mr_cap points per
 // field).  A tile is loaded into LDS, every stage runs there -- each thread
 // takes its butterflies' inputs into registers, the workgroup synchronises,
-// the outputs go back to the same buffer -- and the tile is written out.  Twiddles are the n-th roots of unity of the line
-// length, generated in FP64 on the host and rounded once (one table per
-// length, cached in the context), copied into LDS by each workgroup.
+// the outputs go back to the same buffer -- and the tile is written out.
+// Twiddles are the n-th roots of unity of the line length, generated in FP64
+// on the host and rounded once (one table per length, cached in the
+// context), copied into LDS by each workgroup.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -23,7 +24,9 @@
 
 namespace fftpde {
 
-constexpr int mr_threads(bool fp64) { return fp64 ? 1024 : 1024; }  // per workgroup
+// Threads per workgroup, both dtypes (512-thread FP32 workgroups on smaller
+// tiles ran rows faster and columns slower).
+constexpr int mr_threads(bool /*fp64*/) { return 1024; }
 constexpr int kMrMaxSide = 4096;
 constexpr int kMrMaxColLines = 64;  // columns per column tile
 constexpr int kMrMaxStages = 12;
@@ -47,8 +50,6 @@ __host__ __device__ constexpr bool mr_side_ok(int n) {
   return n == 1;
 }
 
-// Radix sequence of a length: 8s first, then a 4 or a 2 for the rest of the
-// power of two, then 7s, 5s and 3s.
 // Exact x / d for 0 <= x < 2^16 and 1 <= d < 2^16 by one multiply:
 // floor(x M / 2^32) with M = floor(2^32 / d) + 1 (the error x (M - 2^32/d)
 // / 2^32 < 2^-16 < 1/d never crosses an integer).
@@ -61,6 +62,8 @@ struct MrDiv {
   }
 };
 
+// Radix sequence of a length: 8s first, then a 4 or a 2 for the rest of the
+// power of two, then 7s, 5s and 3s.
 struct MrPlan {
   int n = 0;
   int nst = 0;
