@@ -151,3 +151,23 @@ def test_rejects_sizes_outside_the_mixed_path(fp):
     r = torch.zeros((30, 12), dtype=torch.float32, device="cuda:0")
     with pytest.raises(Exception):
         fp.solve_poisson(r)
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_wave_with_velocity_in_place_and_batched(fp, dt):
+    """u and v written over u0 and v0, three fields of a 7-smooth shape."""
+    nx, ny, b, lx, ly, c, t = 45, 28, 3, 1.0, 0.7, 0.9, 0.33
+    say(f"mixed wave velocity in place {nx}x{ny}x{b} {dt}")
+    u0 = W.random_field((b, ny, nx), seed=41)
+    v0 = W.random_field((b, ny, nx), seed=42)
+    du, dv = to_dev(u0, dt), to_dev(v0, dt)
+    u, v = fp.solve_wave(du, dv, c, t, lx, ly, out=du, v_out=dv, want_v=True)
+    assert u.data_ptr() == du.data_ptr() and v.data_ptr() == dv.data_ptr()
+    hu, hv = to_host(u), to_host(v)
+    for k in range(b):
+        ru, rv = oracle.solve_wave(as_oracle_input(u0[k], dt), as_oracle_input(v0[k], dt), lx, ly, c, t,
+                                   want_v=True, threads=THREADS)
+        norm = np.linalg.norm(u0[k]) + np.linalg.norm(v0[k])
+        wmax = c * math.pi * max(nx / lx, ny / ly)
+        assert rel_err_vs_input(hu[k], ru, norm) <= tol(dt, nx, ny, 2)
+        assert rel_err_vs_input(hv[k], rv, norm * wmax) <= tol(dt, nx, ny, 2)

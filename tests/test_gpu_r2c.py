@@ -83,3 +83,15 @@ def test_odd_batch_last_field_alone(fp):
     assert np.abs(X[4] - X4[0]).max() <= 1e-12 * np.abs(X4).max()
     y = fp.fft2d_c2r(fp.fft2d_r2c(_dev(x, "f64")), nx).cpu().numpy()
     assert np.abs(y - x).max() <= 1e-13 * np.abs(x).max()
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_smallest_fields(fp, dt):
+    """2 x 2 fields: the half spectrum is the whole spectrum (columns 0 and 1)."""
+    say(f"r2c 2x2 {dt}")
+    x = _real((1, 2, 2), 9, dt)
+    X = fp.fft2d_r2c(_dev(x, dt)).cpu().numpy().astype(np.complex128)
+    ref = oracle.rfft2d(x[0])
+    assert np.abs(X[0] - ref).max() <= (1e-15 if dt == "f64" else 1e-6) * np.abs(ref).max()
+    y = fp.fft2d_c2r(fp.fft2d_r2c(_dev(x, dt)), 2).cpu().numpy()
+    assert np.abs(y - x).max() <= (1e-15 if dt == "f64" else 1e-6) * np.abs(x).max()
