@@ -16,10 +16,11 @@
  *  Sizes.  nx and ny are powers of two in [2, 4096] (the FFT's 2^m
  *    restriction, Sec. II.C); batch >= 1.  fft2d_forward, fft2d_inverse,
  *    solve_poisson, solve_diffusion and solve_wave also take sides that are
- *    not powers of two, for complex dtypes: any side in [2, 4096] whose prime
- *    factors are 2, 3, 5 and 7 (the mixed-radix path: Stockham stages of
- *    radix 2, 3, 4, 5, 7 and 8, an extension of Sec. II.D; EINVAL for other
- *    sides and for real dtypes).  The first call for a new side allocates
+ *    not powers of two: any side in [2, 4096] whose prime factors are 2, 3,
+ *    5 and 7 (the mixed-radix path: Stockham stages of radix 2, 3, 4, 5, 7
+ *    and 8, an extension of Sec. II.D; EINVAL for other sides).  The three
+ *    solves take real dtypes there too (real fields in pairs, as on powers
+ *    of two; the workspace holds the pair spectra).  The first call for a new side allocates
  *    and uploads that length's twiddle table (kept until the context is
  *    destroyed).  Every other entry point takes powers of two only.
  *  Pointers.  Every field pointer is a DEVICE pointer on the context's GPU,

@@ -457,14 +457,14 @@ int fftpde_destroy(fftpde_ctx* ctx) {
 // ---------------------------------------------------------------------------
 namespace {
 
-// mixed_ok: sides may also be 7-smooth (the mixed-radix path; complex
-// dtypes only).
+// mixed_ok: sides may also be 7-smooth (the mixed-radix path, with real
+// dtypes where real_ok).
 int check_common(fftpde_ctx* ctx, int nx, int ny, int batch, int dtype, bool real_ok = false, bool mixed_ok = false) {
   if (!ctx || batch < 1) return FFTPDE_EINVAL;
   const bool real = dtype == FFTPDE_R32 || dtype == FFTPDE_R64;
   if (dtype != FFTPDE_C64 && dtype != FFTPDE_C128 && !(real_ok && real)) return FFTPDE_EINVAL;
   if (pow2_side(nx) && pow2_side(ny)) return FFTPDE_OK;
-  if (mixed_ok && !real && mixed_side(nx) && mixed_side(ny)) return FFTPDE_OK;
+  if (mixed_ok && mixed_side(nx) && mixed_side(ny)) return FFTPDE_OK;
   return FFTPDE_EINVAL;
 }
 

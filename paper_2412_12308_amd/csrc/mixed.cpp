@@ -70,9 +70,12 @@ const cx<T>* mr_table(Context* c, int n) {
   else return it->second.f64;
 }
 
+// Real fields in pairs: rin (forward rows) or rout (inverse rows) with nreal
+// real fields; `fields` then counts pair fields.
 template <typename T>
 int mr_pass(Context* c, int mode, int nf, const void* in0, const void* in1, void* out0, void* out1, int nx, int ny,
-            long long fields, double scale, const MrSym& sym, hipStream_t s) {
+            long long fields, double scale, const MrSym& sym, hipStream_t s, const void* rin = nullptr,
+            void* rout = nullptr, long long nreal = 0) {
   const bool col = mode >= kMrColFwd;
   const int n = col ? ny : nx;
   MrArgs<T> a{};
@@ -90,6 +93,10 @@ int mr_pass(Context* c, int mode, int nf, const void* in0, const void* in1, void
   a.mode = mode;
   a.scale = T(scale);
   a.sym = sym;
+  a.rin = static_cast<const T*>(rin);
+  a.rout = static_cast<T*>(rout);
+  a.nreal = nreal;
+  a.by_ny = MrDiv(ny);
   const int cap = mr_cap(sizeof(T) == 8, nf);
   if (col) {
     // adjacent columns, each padded by one in LDS
@@ -105,7 +112,9 @@ int mr_pass(Context* c, int mode, int nf, const void* in0, const void* in1, void
   a.by_lines = MrDiv(a.lines);
   const long long grid = std::min<long long>(a.tiles, (long long)std::max(1, c->num_cus) * mr_occupancy<T>(nf));
   const int nin = 1 + (in1 ? 1 : 0), nout = 1 + (out1 ? 1 : 0);
-  const double bytes = (double)sizeof(cx<T>) * (double)nx * ny * (double)fields * (nin + nout);
+  double bytes = (double)sizeof(cx<T>) * (double)nx * ny * (double)fields * (nin + nout);
+  if (rin || rout)  // one real side, one pair-field side
+    bytes = (double)nx * ny * ((double)sizeof(T) * (double)nreal + (double)sizeof(cx<T>) * (double)fields);
   const char* name = col ? (sizeof(T) == 4 ? "mixed_col_float" : "mixed_col_double")
                          : (sizeof(T) == 4 ? "mixed_row_float" : "mixed_row_double");
   const hipError_t e = timed_launch(c, name, bytes, s, [&] { return mr_launch<T>(a, nf, (int)grid, s); });
@@ -169,6 +178,37 @@ int solve(Context* c, int op, const void* in, const void* in2, void* out, void* 
   return rc;
 }
 
+// Real fields (R32 / R64): pairs x1 + i x2 through the complex passes.  The
+// symbols are real and even in k, so the solve of the pair is the pair of the
+// solves; rows read and write the real fields directly, the pair spectra
+// live in the workspace.
+template <typename T>
+int solve_real(Context* c, int op, const void* in, const void* in2, void* out, void* out2, int nx, int ny, int batch,
+               double lx, double ly, double coef, double t, hipStream_t s) {
+  const MrSym sym = mr_sym(op, nx, ny, lx, ly, coef, t);
+  const MrSym none;
+  const bool two = op == FFTPDE_WAVE && (in2 || out2);
+  const long long npairs = (batch + 1) / 2;
+  const size_t pair_bytes = sizeof(cx<T>) * (size_t)nx * ny * (size_t)npairs;
+  void* w = nullptr;
+  const int rcw = c->workspace(pair_bytes * (two ? 2 : 1), s, &w);
+  if (rcw != FFTPDE_OK) return rcw;
+  void* mid = w;
+  void* mid2 = two ? static_cast<char*>(w) + pair_bytes : nullptr;
+  int rc = mr_pass<T>(c, kMrRowFwd, 1, nullptr, nullptr, mid, nullptr, nx, ny, npairs, 1.0, none, s, in, nullptr, batch);
+  if (rc == FFTPDE_OK && two && in2)
+    rc = mr_pass<T>(c, kMrRowFwd, 1, nullptr, nullptr, mid2, nullptr, nx, ny, npairs, 1.0, none, s, in2, nullptr, batch);
+  if (rc == FFTPDE_OK)
+    rc = mr_pass<T>(c, kMrColSolve, two ? 2 : 1, mid, two && in2 ? mid2 : nullptr, mid, two && out2 ? mid2 : nullptr,
+                    nx, ny, npairs, 1.0, sym, s);
+  if (rc == FFTPDE_OK)
+    rc = mr_pass<T>(c, kMrRowInv, 1, mid, nullptr, nullptr, nullptr, nx, ny, npairs, 1.0, none, s, nullptr, out, batch);
+  if (rc == FFTPDE_OK && two && out2)
+    rc = mr_pass<T>(c, kMrRowInv, 1, mid2, nullptr, nullptr, nullptr, nx, ny, npairs, 1.0, none, s, nullptr, out2,
+                    batch);
+  return rc;
+}
+
 }  // namespace
 
 bool mixed_side(int n) { return mr_side_ok(n); }
@@ -181,8 +221,13 @@ int run_mixed_transform(Context* c, int dtype, bool inverse, const void* in, voi
 
 int run_mixed_solve(Context* c, int dtype, int op, const void* in, const void* in2, void* out, void* out2, int nx,
                     int ny, int batch, double lx, double ly, double coef, double t, hipStream_t s) {
-  return dtype == FFTPDE_C64 ? solve<float>(c, op, in, in2, out, out2, nx, ny, batch, lx, ly, coef, t, s)
-                             : solve<double>(c, op, in, in2, out, out2, nx, ny, batch, lx, ly, coef, t, s);
+  switch (dtype) {
+    case FFTPDE_C64: return solve<float>(c, op, in, in2, out, out2, nx, ny, batch, lx, ly, coef, t, s);
+    case FFTPDE_C128: return solve<double>(c, op, in, in2, out, out2, nx, ny, batch, lx, ly, coef, t, s);
+    case FFTPDE_R32: return solve_real<float>(c, op, in, in2, out, out2, nx, ny, batch, lx, ly, coef, t, s);
+    case FFTPDE_R64: return solve_real<double>(c, op, in, in2, out, out2, nx, ny, batch, lx, ly, coef, t, s);
+    default: return FFTPDE_EINVAL;
+  }
 }
 
 }  // namespace fftpde

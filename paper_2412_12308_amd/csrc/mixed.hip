@@ -212,7 +212,7 @@ __global__ void __launch_bounds__(mr_threads(sizeof(T) == 8)) mr_kernel(MrArgs<T
   // segments) over the full tile width; positions past the last column of a
   // ragged tile are skipped.
   struct Tile {
-    long long base;
+    long long base, row0;
     int nl, c0, span;
   };
   auto tile_at = [&](long long t) {
@@ -222,6 +222,7 @@ __global__ void __launch_bounds__(mr_threads(sizeof(T) == 8)) mr_kernel(MrArgs<T
       const long long row0 = t * a.lines;
       g.nl = (int)min((long long)a.lines, nrows - row0);
       g.base = row0 * n;
+      g.row0 = row0;
       g.c0 = 0;
       g.span = g.nl * n;
     } else {
@@ -230,6 +231,7 @@ __global__ void __launch_bounds__(mr_threads(sizeof(T) == 8)) mr_kernel(MrArgs<T
       g.c0 = (int)(t - f * tpf) * a.lines;
       g.nl = min(a.lines, a.nx - g.c0);
       g.base = f * (long long)a.nx * a.ny + g.c0;
+      g.row0 = 0;
       g.span = a.lines * n;
     }
     return g;
@@ -243,6 +245,17 @@ __global__ void __launch_bounds__(mr_threads(sizeof(T) == 8)) mr_kernel(MrArgs<T
     j = a.by_lines(idx);
     line = idx - j * a.lines;
     return g.base + (long long)j * a.nx + line;
+  };
+  // Real fields in pairs: row `line` of tile g is row r of pair field p,
+  // i.e. row r of real fields 2p and 2p + 1; returns the offset r nx + j in
+  // a real field and sets p.  (row0 mod ny) + line stays below 2^16.
+  const long long pts = (long long)a.nx * a.ny;
+  auto real_at = [&](const Tile& g, int line, int j, long long& p) -> long long {
+    const long long p0 = g.row0 / a.ny;
+    const int rr = (int)(g.row0 - p0 * a.ny) + line;
+    const int dp = a.by_ny(rr);
+    p = p0 + dp;
+    return (long long)(rr - dp * a.ny) * a.nx + j;
   };
   const bool conj_in = a.mode == kMrRowInv || a.mode == kMrColInv;
   const bool has2 = NF == 2 && a.in1 != nullptr;
@@ -264,7 +277,18 @@ __global__ void __launch_bounds__(mr_threads(sizeof(T) == 8)) mr_kernel(MrArgs<T
       const cx<T>* in = fi == 0 ? a.in0 : a.in1;
       if (fi == 1 && !has2) continue;
       cx<T>* buf = lds + fi * LDSF;
-      if constexpr (sizeof(T) == 4) {
+      if (NF == 1 && a.rin != nullptr) {  // forward rows of real fields in pairs
+        for (int idx = tid; idx < g.span; idx += TH) {
+          int line, j;
+          (void)where(g, idx, line, j);
+          if (line >= g.nl) continue;
+          long long p;
+          const long long e = real_at(g, line, j, p);
+          const T re = a.rin[2 * p * pts + e];
+          const T im = 2 * p + 1 < a.nreal ? a.rin[(2 * p + 1) * pts + e] : T(0);
+          buf[mr_pad(line * a.ls + j)] = {re, im};
+        }
+      } else if constexpr (sizeof(T) == 4) {
         cx<T> v[PT];
 #pragma unroll
         for (int i = 0; i < PT; i++) {
@@ -330,6 +354,19 @@ __global__ void __launch_bounds__(mr_threads(sizeof(T) == 8)) mr_kernel(MrArgs<T
       cx<T>* out = fi == 0 ? a.out0 : a.out1;
       if (fi == 1 && !out2) continue;
       const cx<T>* buf = lds + fi * LDSF;
+      if (NF == 1 && a.rout != nullptr) {  // inverse rows back to real fields in pairs
+        for (int idx = tid; idx < g.span; idx += TH) {
+          int line, j;
+          (void)where(g, idx, line, j);
+          if (line >= nl) continue;
+          long long p;
+          const long long e = real_at(g, line, j, p);
+          const cx<T> v = buf[mr_pad(line * a.ls + j)];
+          a.rout[2 * p * pts + e] = v.re * sc;
+          if (2 * p + 1 < a.nreal) a.rout[(2 * p + 1) * pts + e] = -v.im * sc;
+        }
+        continue;
+      }
       for (int idx = tid; idx < g.span; idx += TH) {
         int line, j;
         const long long off = where(g, idx, line, j);

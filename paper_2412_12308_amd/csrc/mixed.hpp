@@ -136,6 +136,15 @@ struct MrArgs {
   int mode;
   T scale;    // kMrRowInv
   MrSym sym;  // kMrColSolve
+  // Real fields in pairs (rows only): with rin the forward row pass reads
+  // pair field p as real fields 2p + i (2p + 1) of rin (the odd last one
+  // paired with zero); with rout the inverse row pass writes the real and
+  // imaginary parts to them.  nreal real fields; by_ny splits a pair-field
+  // row index into (pair, row).
+  const T* rin;
+  T* rout;
+  long long nreal;
+  MrDiv by_ny;
 };
 
 // grid: persistent workgroups (at most a.tiles)

@@ -63,12 +63,11 @@ BUF = ctypes.create_string_buffer(256)
 P = (ctypes.cast(BUF, ctypes.c_void_p).value + 15) // 16 * 16  # 16-byte aligned "field"
 
 
-# sides must be 7-smooth (powers of two, or the mixed-radix path) in [2, 4096];
-# the mixed-radix path takes complex dtypes only
+# sides must be 7-smooth (powers of two, or the mixed-radix path) in [2, 4096]
 @pytest.mark.parametrize("nx,ny,batch,dtype", [
     (11, 4, 1, 0), (4, 13, 1, 0), (22, 77, 1, 1), (4097, 4, 1, 0), (1, 4, 1, 0), (4, 1, 1, 1), (8192, 4, 1, 0),
     (4, 8192, 1, 1), (0, 4, 1, 0), (-4, 4, 1, 0), (4, 4, 0, 0), (4, 4, -1, 1), (4, 4, 1, 4), (4, 4, 1, -1),
-    (4, 6, 1, 2), (12, 4, 1, 3),
+    (4, 11, 1, 2), (13, 4, 1, 3),
 ])
 def test_transforms_reject_bad_shape_or_dtype(nx, ny, batch, dtype):
     fp, L = _lib()
@@ -311,6 +310,13 @@ def test_3d_solves_reject_bad_coefficients_and_real_dtypes():
     assert L.solve_wave_3d(DUMMY, P, P, 4, 4, 4, 1, 1.0, 1.0, 1.0, -1.0, 0.5, 0, None) == fp.EINVAL
     assert L.fft3d_forward(DUMMY, P, P, 4, 4, 4, 1, 2, None) == fp.EINVAL
     assert L.fft3d_forward(None, P, P, 4, 4, 4, 1, 0, None) == fp.EINVAL
+
+
+@pytest.mark.parametrize("nx,ny,dtype", [(4, 6, 2), (12, 4, 3)])
+def test_complex_transforms_reject_real_dtypes_on_7_smooth_sides(nx, ny, dtype):
+    fp, L = _lib()
+    assert L.fft2d_forward(DUMMY, P, P, nx, ny, 1, dtype, None) == fp.EINVAL
+    assert L.fft2d_inverse(DUMMY, P, P, nx, ny, 1, dtype, None) == fp.EINVAL
 
 
 def test_sides_that_are_not_powers_of_two_only_reach_the_mixed_radix_entry_points():

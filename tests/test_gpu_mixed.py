@@ -6,7 +6,8 @@ Shapes cover every radix (2, 3, 4, 5, 7, 8), odd and even sides, rows and
 columns of one point short of a tile, ragged last column tiles, one power-
 of-two side with one other side, the largest 7-smooth sides below 4096, and
 batches; the three solves include the wave with an initial velocity and the
-velocity output."""
+velocity output, on complex fields and on real fields (solved in pairs, as on
+powers of two)."""
 import math
 
 import numpy as np
@@ -147,10 +148,10 @@ def test_rejects_sizes_outside_the_mixed_path(fp):
             fp.fft2d_forward(x)
         with pytest.raises(Exception):
             fp.solve_poisson(x)
-    # real fields and the 3D path stay on powers of two
+    # the complex transforms take no real fields, on any side
     r = torch.zeros((30, 12), dtype=torch.float32, device="cuda:0")
     with pytest.raises(Exception):
-        fp.solve_poisson(r)
+        fp.fft2d_forward(r)
 
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
@@ -171,3 +172,101 @@ def test_wave_with_velocity_in_place_and_batched(fp, dt):
         wmax = c * math.pi * max(nx / lx, ny / ly)
         assert rel_err_vs_input(hu[k], ru, norm) <= tol(dt, nx, ny, 2)
         assert rel_err_vs_input(hv[k], rv, norm * wmax) <= tol(dt, nx, ny, 2)
+
+
+def _rdev(a, dt):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to({"r32": torch.float32, "r64": torch.float64}[dt]).cuda()
+
+
+def _rseen(a, dt):
+    a = np.asarray(a, dtype=np.float64)
+    return a.astype(np.float32).astype(np.float64) if dt == "r32" else a
+
+
+def _check_real_pairs(got, refs, dt, nx, ny, scale=1.0):
+    """Field k against the oracle's solve of field k alone, relative to the
+    joint norm of its pair (the pair is one complex transform), times scale."""
+    bound = TOL_FP64 if dt == "r64" else tol("c64", nx, ny, 2)
+    for k, ref in enumerate(refs):
+        assert np.linalg.norm(ref.imag) <= 1e-12 * max(np.linalg.norm(ref.real), 1e-300)
+        p = k - (k % 2)
+        denom = max(np.sqrt(sum(np.linalg.norm(r.real) ** 2 for r in refs[p:p + 2])), 1e-300) * scale
+        err = np.linalg.norm(got[k] - ref.real) / denom
+        assert err <= bound, (k, err, bound)
+
+
+@pytest.mark.parametrize("dt", ["r32", "r64"])
+@pytest.mark.parametrize("op,nx,ny,batch", [
+    ("poisson", 96, 30, 1), ("diffusion", 45, 64, 3), ("wave", 210, 125, 2), ("poisson", 3, 5, 5),
+    ("wave", 1000, 24, 4), ("diffusion", 7, 343, 3), ("poisson", 1536, 20, 2)])
+def test_real_solves_on_7_smooth_grids(fp, dt, op, nx, ny, batch):
+    say(f"mixed real {op} {nx}x{ny}x{batch} {dt}")
+    f = W.random_field((batch, ny, nx), seed=5 * nx + ny + batch).real
+    x = _rdev(f, dt)
+    lx, ly, coef, t = 1.0, 1.7, 0.3, 0.41
+    if op == "poisson":
+        u = fp.solve_poisson(x, lx, ly)
+    elif op == "diffusion":
+        u = fp.solve_diffusion(x, coef, t, lx, ly)
+    else:
+        u = fp.solve_wave(x, None, coef, t, lx, ly)[0]
+    assert u.dtype == x.dtype and u.shape == x.shape
+    got = u.cpu().numpy().astype(np.float64)
+    refs = []
+    for k in range(batch):
+        g = _rseen(f[k], dt).astype(np.complex128)
+        if op == "poisson":
+            refs.append(oracle.solve_poisson(g, lx, ly, threads=THREADS))
+        elif op == "diffusion":
+            refs.append(oracle.solve_diffusion(g, lx, ly, coef, t, threads=THREADS))
+        else:
+            refs.append(oracle.solve_wave(g, None, lx, ly, coef, t, threads=THREADS)[0])
+    _check_real_pairs(got, refs, dt, nx, ny)
+
+
+@pytest.mark.parametrize("dt", ["r32", "r64"])
+def test_real_wave_with_velocity_on_a_7_smooth_grid(fp, dt):
+    """u0 and v0 real, u and u_t out (also in place), v0 without u_t, u_t
+    without v0; three fields, so the last pair holds one field."""
+    import torch
+    nx, ny, b, lx, ly, c, t = 75, 36, 3, 1.5, 1.0, 1.2, 0.37
+    say(f"mixed real wave velocity {nx}x{ny}x{b} {dt}")
+    u0 = W.random_field((b, ny, nx), seed=51).real
+    v0 = W.random_field((b, ny, nx), seed=52).real
+    wmax = c * math.pi * max(nx / lx, ny / ly)
+    refs = [oracle.solve_wave(_rseen(u0[k], dt).astype(np.complex128), _rseen(v0[k], dt).astype(np.complex128),
+                              lx, ly, c, t, want_v=True, threads=THREADS) for k in range(b)]
+    du, dv = _rdev(u0, dt), _rdev(v0, dt)
+    u, v = fp.solve_wave(du, dv, c, t, lx, ly, want_v=True)
+    _check_real_pairs(u.cpu().numpy(), [r[0] for r in refs], dt, nx, ny, scale=2.0)
+    _check_real_pairs(v.cpu().numpy(), [r[1] for r in refs], dt, nx, ny, scale=2.0 * wmax)
+    u2, none = fp.solve_wave(du, dv, c, t, lx, ly)
+    assert none is None and torch.equal(u2, u)
+    fp.solve_wave(du, dv, c, t, lx, ly, out=du, v_out=dv, want_v=True)
+    assert torch.equal(du, u) and torch.equal(dv, v)
+    refs0 = [oracle.solve_wave(_rseen(u0[k], dt).astype(np.complex128), None, lx, ly, c, t, want_v=True,
+                               threads=THREADS) for k in range(b)]
+    u3, v3 = fp.solve_wave(_rdev(u0, dt), None, c, t, lx, ly, want_v=True)
+    _check_real_pairs(u3.cpu().numpy(), [r[0] for r in refs0], dt, nx, ny)
+    _check_real_pairs(v3.cpu().numpy(), [r[1] for r in refs0], dt, nx, ny, scale=wmax)
+
+
+@pytest.mark.parametrize("dt", ["r32", "r64"])
+def test_real_solve_matches_the_complex_path_on_a_7_smooth_grid(fp, dt):
+    """The same fields as complex fields with imaginary part 0: one field at a
+    time through the complex mixed path; the real path in place too."""
+    import torch
+    nx, ny, b = 120, 63, 5
+    say(f"mixed real vs complex {nx}x{ny}x{b} {dt}")
+    f = W.random_field((b, ny, nx), seed=61).real
+    x = _rdev(f, dt)
+    whole = fp.solve_diffusion(x, 0.05, 0.3, 1.0, 1.0)
+    y = x.clone()
+    fp.solve_diffusion(y, 0.05, 0.3, 1.0, 1.0, out=y)
+    assert torch.equal(y, whole)
+    cdt = torch.complex64 if dt == "r32" else torch.complex128
+    zc = fp.solve_diffusion(x.to(cdt), 0.05, 0.3, 1.0, 1.0).real.cpu().numpy()
+    bound = TOL_FP64 if dt == "r64" else tol("c64", nx, ny, 2)
+    err = np.linalg.norm(whole.cpu().numpy() - zc) / np.linalg.norm(zc)
+    assert err <= bound
