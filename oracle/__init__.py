@@ -149,20 +149,22 @@ def rfft2d(x, threads: int = 1) -> np.ndarray:
 
 
 def hermitian_extension(X, nx: int) -> np.ndarray:
-    """The full [ny][nx] spectrum of which the half spectrum X ([ny][nx/2+1])
+    """The full [ny][nx] spectrum of which the half spectrum X ([ny][nx//2+1])
     is the Hermitian part: columns 0 < a < nx/2 as given, a > nx/2 from
-    conj(X[-b][nx - a]), and columns a = 0 and a = nx/2 replaced by
-    (X[b][a] + conj(X[-b][a])) / 2."""
+    conj(X[-b][nx - a]), and the columns that the symmetry maps to
+    themselves (a = 0, and a = nx/2 when nx is even) replaced by
+    (X[b][a] + conj(X[-b][a])) / 2.  For odd nx the half spectrum holds
+    columns 0 .. (nx-1)/2, all but a = 0 as given."""
     X = np.asarray(X, dtype=np.complex128)
     ny, h = X.shape
-    assert h == nx // 2 + 1 and nx % 2 == 0
+    assert h == nx // 2 + 1 and nx >= 1
     full = np.empty((ny, nx), dtype=np.complex128)
     for b in range(ny):
         bm = (-b) % ny
         for a in range(nx):
-            if a == 0 or a == nx // 2:
+            if a == 0 or 2 * a == nx:
                 full[b, a] = (X[b, a] + np.conj(X[bm, a])) / 2
-            elif a < nx // 2:
+            elif 2 * a < nx:
                 full[b, a] = X[b, a]
             else:
                 full[b, a] = np.conj(X[bm, nx - a])

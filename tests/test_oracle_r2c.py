@@ -6,7 +6,8 @@ transform of real data, Sec. II.B).
 Fixed independently of the oracle: numpy.fft.rfft2 and irfft2 (a separate
 implementation; numpy's inverse also reads only the Hermitian part of the
 a = 0 and a = nx/2 columns), a cosine mode's two-spike half spectrum, the
-round trip, and the projection being idempotent."""
+round trip, and the projection being idempotent; odd sides, whose half
+spectrum has no self-conjugate column besides a = 0, included."""
 import math
 
 import numpy as np
@@ -15,7 +16,8 @@ import pytest
 import oracle
 
 
-@pytest.mark.parametrize("ny,nx", [(4, 2), (2, 8), (16, 16), (32, 8), (8, 64)])
+@pytest.mark.parametrize("ny,nx", [(4, 2), (2, 8), (16, 16), (32, 8), (8, 64), (5, 3), (6, 15), (7, 7),
+                                   (12, 9), (3, 10)])
 def test_rfft2d_matches_numpy_and_round_trips(ny, nx):
     x = np.random.default_rng(nx * 31 + ny).standard_normal((ny, nx))
     X = oracle.rfft2d(x)
@@ -35,7 +37,7 @@ def test_half_spectrum_of_a_cosine_mode():
     assert np.abs(X - ref).max() <= 1e-12 * nx * ny
 
 
-@pytest.mark.parametrize("ny,nx", [(8, 8), (6, 4), (16, 2)])
+@pytest.mark.parametrize("ny,nx", [(8, 8), (6, 4), (16, 2), (5, 5), (6, 9), (9, 6), (4, 1), (1, 7)])
 def test_inverse_of_a_non_hermitian_half_spectrum_matches_numpy(ny, nx):
     rng = np.random.default_rng(7 + nx + ny)
     X = rng.standard_normal((ny, nx // 2 + 1)) + 1j * rng.standard_normal((ny, nx // 2 + 1))
@@ -45,3 +47,16 @@ def test_inverse_of_a_non_hermitian_half_spectrum_matches_numpy(ny, nx):
     full = oracle.hermitian_extension(X, nx)
     again = oracle.hermitian_extension(full[:, : nx // 2 + 1], nx)
     assert np.abs(full - again).max() <= 1e-15 * np.abs(full).max()
+
+
+def test_odd_side_extension_by_hand():
+    """nx = 3, ny = 1: the half spectrum [X0, X1] extends to
+    [Re X0, X1, conj(X1)] (only a = 0 maps to itself)."""
+    X = np.array([[2.0 + 3.0j, 1.0 - 4.0j]])
+    full = oracle.hermitian_extension(X, 3)
+    assert np.array_equal(full, np.array([[2.0 + 0.0j, 1.0 - 4.0j, 1.0 + 4.0j]]))
+    # and the inverse is the real field of that spectrum, by the DFT sum
+    x = oracle.irfft2d(X, 3)
+    j = np.arange(3)
+    ref = (2.0 + 2 * ((1.0 - 4.0j) * np.exp(2j * math.pi * j / 3)).real) / 3
+    assert np.abs(x[0] - ref).max() <= 1e-15
