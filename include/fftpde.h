@@ -15,14 +15,15 @@
  *    endpoint excluded); the origin x0 never enters a solve.
  *  Sizes.  nx and ny are powers of two in [2, 4096] (the FFT's 2^m
  *    restriction, Sec. II.C); batch >= 1.  fft2d_forward, fft2d_inverse,
- *    solve_poisson, solve_diffusion and solve_wave also take sides that are
- *    not powers of two: any side in [2, 4096] whose prime factors are 2, 3,
- *    5 and 7 (the mixed-radix path: Stockham stages of radix 2, 3, 4, 5, 7
- *    and 8, an extension of Sec. II.D; EINVAL for other sides).  The three
- *    solves take real dtypes there too (real fields in pairs, as on powers
- *    of two; the workspace holds the pair spectra).  The first call for a new side allocates
- *    and uploads that length's twiddle table (kept until the context is
- *    destroyed).  Every other entry point takes powers of two only.
+ *    fft2d_r2c, fft2d_c2r, solve_poisson, solve_diffusion and solve_wave
+ *    also take sides that are not powers of two: any side in [2, 4096]
+ *    whose prime factors are 2, 3, 5 and 7 (the mixed-radix path: Stockham
+ *    stages of radix 2, 3, 4, 5, 7 and 8, an extension of Sec. II.D; EINVAL
+ *    for other sides), with the same dtypes as on powers of two (real
+ *    fields in pairs; the workspace holds the pair spectra).  The first
+ *    call for a new side allocates and uploads that length's twiddle table
+ *    (kept until the context is destroyed).  Every other entry point takes
+ *    powers of two only.
  *  Pointers.  Every field pointer is a DEVICE pointer on the context's GPU,
  *    aligned to the element size.  The caller owns every field buffer.
  *    in == out (in place) is allowed wherever an input and an output have the
@@ -205,16 +206,17 @@ int fft2d_inverse(fftpde_ctx *ctx, const void *in, void *out, int nx, int ny, in
 /* ---- 2D transforms of real fields (half spectra) ----------------------------
  * The transform of real data has X[-b][-a] = conj(X[b][a]) (Sec. II.B), so
  * columns a = 0 .. nx/2 of the spectrum determine it: the half spectrum, a
- * [ny][nx/2 + 1] complex field.
+ * [ny][nx/2 + 1] complex field (nx/2 rounded down: columns 0 .. (nx-1)/2
+ * on odd sides).
  * fft2d_r2c: out = the half spectrum (unnormalised forward transform) of
  *   each real field of `in`.  dtype FFTPDE_R32 (in: float, out: FP32
- *   complex) or FFTPDE_R64 (double / FP64 complex); sides powers of two in
- *   [2, 4096].
+ *   complex) or FFTPDE_R64 (double / FP64 complex); sides in [2, 4096],
+ *   powers of two or 7-smooth.
  * fft2d_c2r: out = the real field whose half spectrum is the Hermitian part
  *   of `in`, times 1/(nx ny): columns 0 < a < nx/2 as given, the rest of the
- *   spectrum from the symmetry, and the self-conjugate columns a = 0 and
- *   a = nx/2 replaced by (X[b][a] + conj(X[-b][a]))/2 (no change for half
- *   spectra of real fields).  Same dtypes and sides.
+ *   spectrum from the symmetry, and the self-conjugate columns (a = 0, and
+ *   a = nx/2 on even nx) replaced by (X[b][a] + conj(X[-b][a]))/2 (no change
+ *   for half spectra of real fields).  Same dtypes and sides.
  * Both: in and out must not overlap (EINVAL).  Two real fields go through
  *   one complex transform (row pass with real loads or stores), their
  *   spectrum in the per-stream scratch; one more pass splits it into the

@@ -478,7 +478,7 @@ bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 // real fields (R32 / R64) <-> half spectra of the matching complex dtype
 int half_checks(fftpde_ctx* ctx, const void* real, const void* half, int nx, int ny, int batch, int dtype) {
   if (dtype != FFTPDE_R32 && dtype != FFTPDE_R64) return FFTPDE_EINVAL;
-  int rc = check_common(ctx, nx, ny, batch, dtype, true);
+  int rc = check_common(ctx, nx, ny, batch, dtype, true, true);
   if (rc == FFTPDE_OK) rc = check_field(real, dtype);
   if (rc == FFTPDE_OK) rc = check_field(half, dtype == FFTPDE_R32 ? FFTPDE_C64 : FFTPDE_C128);
   if (rc != FFTPDE_OK) return rc;
@@ -524,6 +524,8 @@ int fft2d_r2c(fftpde_ctx* ctx, const void* in, void* out, int nx, int ny, int ba
   if (rc != FFTPDE_OK) return rc;
   Context* c = reinterpret_cast<Context*>(ctx);
   DeviceGuard g(c->device);
+  if (is_mixed(nx, ny))
+    return run_mixed_half(c, dtype, false, in, out, nx, ny, batch, static_cast<hipStream_t>(stream));
   return run_half_transform(c, dtype, false, in, out, nx, ny, batch, static_cast<hipStream_t>(stream));
 }
 
@@ -533,6 +535,8 @@ int fft2d_c2r(fftpde_ctx* ctx, const void* in, void* out, int nx, int ny, int ba
   if (rc != FFTPDE_OK) return rc;
   Context* c = reinterpret_cast<Context*>(ctx);
   DeviceGuard g(c->device);
+  if (is_mixed(nx, ny))
+    return run_mixed_half(c, dtype, true, in, out, nx, ny, batch, static_cast<hipStream_t>(stream));
   return run_half_transform(c, dtype, true, in, out, nx, ny, batch, static_cast<hipStream_t>(stream));
 }
 

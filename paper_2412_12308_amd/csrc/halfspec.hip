@@ -7,7 +7,8 @@
 //   X1 = (Z + conj(Zm)) / 2,   X2 = (Z - conj(Zm)) / (2i).
 // Backwards, the Hermitian extension of each half spectrum gives the full
 // X1, X2 and Z = X1 + i X2 is transformed back as one complex field whose
-// real and imaginary parts are x1 and x2.
+// real and imaginary parts are x1 and x2.  Sides may be odd: index -b is
+// ny - b for b > 0, and on odd nx no column but a = 0 maps to itself.
 #include "halfspec.hpp"
 
 namespace fftpde {
@@ -21,14 +22,14 @@ __global__ void __launch_bounds__(kHalfTH) untangle_kernel(HalfArgs<T> a) {
   const long long row = blockIdx.x;  // p * ny + b
   const long long p = row / a.ny;
   const int b = (int)(row - p * a.ny);
-  const int bm = (a.ny - b) & (a.ny - 1);
+  const int bm = b == 0 ? 0 : a.ny - b;
   const int h = a.nx / 2 + 1;
   const cx<T>* S = a.spec + p * (long long)a.nx * a.ny;
   const bool second = 2 * p + 1 < a.nreal;
   cx<T>* o1 = a.half + (2 * p * (long long)a.ny + b) * h;
   cx<T>* o2 = o1 + (long long)a.ny * h;
   for (int c = threadIdx.x; c < h; c += kHalfTH) {
-    const int cm = (a.nx - c) & (a.nx - 1);
+    const int cm = c == 0 ? 0 : a.nx - c;
     const cx<T> z = S[(long long)b * a.nx + c];
     const cx<T> zm = S[(long long)bm * a.nx + cm];
     o1[c] = {T(0.5) * (z.re + zm.re), T(0.5) * (z.im - zm.im)};
@@ -38,15 +39,14 @@ __global__ void __launch_bounds__(kHalfTH) untangle_kernel(HalfArgs<T> a) {
 
 // The Hermitian extension of half spectrum X at (b, a): columns 0 < a < nx/2
 // as given, a > nx/2 from conj(X[-b][nx - a]), and the self-conjugate columns
-// a = 0 and a = nx/2 projected to (X[b][a] + conj(X[-b][a])) / 2.
+// (a = 0, and a = nx/2 on even nx) projected to (X[b][a] + conj(X[-b][a])) / 2.
 template <typename T>
 __device__ __forceinline__ cx<T> hermitian_at(const cx<T>* X, int h, int nx, int b, int bm, int c) {
-  const int half = nx / 2;
-  if (c == 0 || c == half) {
+  if (c == 0 || 2 * c == nx) {
     const cx<T> v = X[(long long)b * h + c], w = X[(long long)bm * h + c];
     return {T(0.5) * (v.re + w.re), T(0.5) * (v.im - w.im)};
   }
-  if (c < half) return X[(long long)b * h + c];
+  if (2 * c < nx) return X[(long long)b * h + c];
   const cx<T> v = X[(long long)bm * h + (nx - c)];
   return {v.re, -v.im};
 }
@@ -56,7 +56,7 @@ __global__ void __launch_bounds__(kHalfTH) tangle_kernel(HalfArgs<T> a) {
   const long long row = blockIdx.x;
   const long long p = row / a.ny;
   const int b = (int)(row - p * a.ny);
-  const int bm = (a.ny - b) & (a.ny - 1);
+  const int bm = b == 0 ? 0 : a.ny - b;
   const int h = a.nx / 2 + 1;
   cx<T>* S = a.spec + p * (long long)a.nx * a.ny + (long long)b * a.nx;
   const cx<T>* X1 = a.half + 2 * p * (long long)a.ny * h;

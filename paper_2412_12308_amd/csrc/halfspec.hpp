@@ -1,7 +1,7 @@
 // halfspec.hpp -- conversions between the spectrum of a pair of real fields
 // (transformed as one complex field) and the two half spectra
-// [ny][nx/2 + 1] of the fields (fft2d_r2c / fft2d_c2r).  Sides are powers
-// of two.
+// [ny][nx/2 + 1] of the fields (fft2d_r2c / fft2d_c2r).  Any sides: the
+// spectra come from the power-of-two or the mixed-radix passes.
 #pragma once
 
 #include <hip/hip_runtime.h>

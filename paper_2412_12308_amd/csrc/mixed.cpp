@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/fftpde.h"
+#include "halfspec.hpp"
 #include "mixed.hpp"
 #include "solve.hpp"
 
@@ -209,6 +210,45 @@ int solve_real(Context* c, int op, const void* in, const void* in2, void* out, v
   return rc;
 }
 
+// Half spectra of real fields: the pairs' complex spectra in the workspace,
+// split into (forward) or joined from (inverse) the half spectra.
+template <typename T>
+int half(Context* c, bool inverse, const void* in, void* out, int nx, int ny, int batch, hipStream_t s) {
+  const MrSym none;
+  const long long npairs = (batch + 1) / 2;
+  const long long pts = (long long)nx * ny, hpts = (long long)(nx / 2 + 1) * ny;
+  void* w = nullptr;
+  const int rcw = c->workspace(sizeof(cx<T>) * (size_t)pts * (size_t)npairs, s, &w);
+  if (rcw != FFTPDE_OK) return rcw;
+  HalfArgs<T> h{static_cast<cx<T>*>(w), nullptr, nx, ny, npairs, batch};
+  const char* name = inverse ? (sizeof(T) == 4 ? "tangle_float" : "tangle_double")
+                             : (sizeof(T) == 4 ? "untangle_float" : "untangle_double");
+  const double hbytes = (double)sizeof(cx<T>) * (double)(npairs * pts + batch * hpts);
+  auto split_or_join = [&]() -> int {
+    const hipError_t e =
+        timed_launch(c, name, hbytes, s, [&] { return inverse ? launch_tangle<T>(h, s) : launch_untangle<T>(h, s); });
+    if (e != hipSuccess) {
+      set_last_error(name, e);
+      return FFTPDE_EDEVICE;
+    }
+    return FFTPDE_OK;
+  };
+  if (!inverse) {
+    h.half = static_cast<cx<T>*>(out);
+    int rc = mr_pass<T>(c, kMrRowFwd, 1, nullptr, nullptr, w, nullptr, nx, ny, npairs, 1.0, none, s, in, nullptr, batch);
+    if (rc == FFTPDE_OK) rc = mr_pass<T>(c, kMrColFwd, 1, w, nullptr, w, nullptr, nx, ny, npairs, 1.0, none, s);
+    if (rc == FFTPDE_OK) rc = split_or_join();
+    return rc;
+  }
+  h.half = static_cast<cx<T>*>(const_cast<void*>(in));
+  int rc = split_or_join();
+  if (rc == FFTPDE_OK) rc = mr_pass<T>(c, kMrColInv, 1, w, nullptr, w, nullptr, nx, ny, npairs, 1.0, none, s);
+  if (rc == FFTPDE_OK)
+    rc = mr_pass<T>(c, kMrRowInv, 1, w, nullptr, nullptr, nullptr, nx, ny, npairs, 1.0 / ((double)nx * ny), none, s,
+                    nullptr, out, batch);
+  return rc;
+}
+
 }  // namespace
 
 bool mixed_side(int n) { return mr_side_ok(n); }
@@ -228,6 +268,12 @@ int run_mixed_solve(Context* c, int dtype, int op, const void* in, const void* i
     case FFTPDE_R64: return solve_real<double>(c, op, in, in2, out, out2, nx, ny, batch, lx, ly, coef, t, s);
     default: return FFTPDE_EINVAL;
   }
+}
+
+int run_mixed_half(Context* c, int dtype, bool inverse, const void* in, void* out, int nx, int ny, int batch,
+                   hipStream_t s) {
+  return dtype == FFTPDE_R32 ? half<float>(c, inverse, in, out, nx, ny, batch, s)
+                             : half<double>(c, inverse, in, out, nx, ny, batch, s);
 }
 
 }  // namespace fftpde

@@ -86,5 +86,8 @@ int run_mixed_transform(Context* c, int dtype, bool inverse, const void* in, voi
                         hipStream_t s);
 int run_mixed_solve(Context* c, int dtype, int op, const void* in, const void* in2, void* out, void* out2, int nx,
                     int ny, int batch, double lx, double ly, double coef, double t, hipStream_t s);
+// half spectra of real fields (R32 / R64) on 7-smooth sides
+int run_mixed_half(Context* c, int dtype, bool inverse, const void* in, void* out, int nx, int ny, int batch,
+                   hipStream_t s);
 
 }  // namespace fftpde

@@ -331,7 +331,7 @@ def test_sides_that_are_not_powers_of_two_only_reach_the_mixed_radix_entry_point
 
 
 def test_half_spectrum_transforms_reject_bad_arguments():
-    """fft2d_r2c / fft2d_c2r: real dtypes only, powers of two, aligned, and
+    """fft2d_r2c / fft2d_c2r: real dtypes only, 7-smooth sides, aligned, and
     input and output must not overlap -- all before touching the context."""
     fp, L = _lib()
     big = ctypes.create_string_buffer(1 << 16)
@@ -340,7 +340,8 @@ def test_half_spectrum_transforms_reject_bad_arguments():
     for fn in (L.fft2d_r2c, L.fft2d_c2r):
         for dtype in (0, 1, 4, -1):                          # complex or unknown dtypes
             assert fn(DUMMY, A, B, 8, 8, 1, dtype, None) == fp.EINVAL
-        assert fn(DUMMY, A, B, 12, 8, 1, 2, None) == fp.EINVAL  # not a power of two
+        assert fn(DUMMY, A, B, 11, 8, 1, 2, None) == fp.EINVAL  # prime factor 11
+        assert fn(DUMMY, A, B, 8, 4097, 1, 3, None) == fp.EINVAL  # side above 4096
         assert fn(DUMMY, A, B, 8, 1, 1, 2, None) == fp.EINVAL   # side below 2
         assert fn(DUMMY, A, B, 8, 8, 0, 3, None) == fp.EINVAL   # empty batch
         assert fn(None, A, B, 8, 8, 1, 2, None) == fp.EINVAL

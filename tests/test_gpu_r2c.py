@@ -1,6 +1,7 @@
 """GPU half-spectrum transforms of real fields (fft2d_r2c / fft2d_c2r)
 against the FP64 oracle's rfft2d / irfft2d (columns 0..nx/2 of the 2D
-transform, and the inverse of the Hermitian part)."""
+transform, and the inverse of the Hermitian part), on powers of two and on
+7-smooth sides (odd nx: no Nyquist column)."""
 import numpy as np
 import pytest
 
@@ -11,6 +12,8 @@ pytestmark = pytest.mark.gpu
 THREADS = oracle.default_threads()
 
 SHAPES = [(2, 4), (8, 2), (64, 32), (256, 1024), (4096, 16), (16, 4096), (2048, 2048)]
+# 7-smooth sides (the mixed-radix passes), odd and even nx
+SHAPES += [(3, 2), (5, 7), (12, 20), (45, 64), (64, 45), (96, 30), (105, 7), (1536, 10), (9, 2048), (4050, 3)]
 
 
 @pytest.fixture(scope="module")
