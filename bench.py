@@ -291,6 +291,16 @@ def half_spectrum_leg(fp, torch, host_fields, steps: int, warmup: int, check: bo
         res[name] = {"ms": round(ms, 4), "fields_per_s": round(batch / (ms * 1e-3), 1),
                      "alg_gbs": round(alg / (ms * 1e-3) / 1e9, 1),
                      "alg_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        # per-kernel split (HIP events around each launch, outside the timed loop)
+        fp.profile(0, True)
+        for _ in range(min(steps, 5)):
+            fn()
+        torch.cuda.synchronize()
+        prof = fp.profile_read(0)
+        fp.profile(0, False)
+        res[name]["kernels"] = [{"kernel": k["kernel"], "launches": k["launches"],
+                                 "avg_us": round(k["total_ms"] / k["launches"] * 1e3, 2),
+                                 "gbs": round(k["bytes"] / (k["total_ms"] * 1e-3) / 1e9, 1)} for k in prof]
     if check:
         import oracle
         x0 = x[0].cpu().numpy().astype(np.float64)

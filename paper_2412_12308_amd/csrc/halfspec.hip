@@ -16,6 +16,13 @@ namespace {
 
 constexpr int kHalfTH = 256;
 
+// offset of spectrum element (row b, column c) within one pair's field
+template <typename T>
+__device__ __forceinline__ long long spec_at(const HalfArgs<T>& a, int b, int c) {
+  if (a.t < 0) return (long long)b * a.nx + c;
+  return ((long long)(c >> a.t) << (a.logny + a.t)) + ((long long)b << a.t) + (c & ((1 << a.t) - 1));
+}
+
 // One block per spectrum row (pair p, row b); threads over the columns.
 template <typename T>
 __global__ void __launch_bounds__(kHalfTH) untangle_kernel(HalfArgs<T> a) {
@@ -30,8 +37,8 @@ __global__ void __launch_bounds__(kHalfTH) untangle_kernel(HalfArgs<T> a) {
   cx<T>* o2 = o1 + (long long)a.ny * h;
   for (int c = threadIdx.x; c < h; c += kHalfTH) {
     const int cm = c == 0 ? 0 : a.nx - c;
-    const cx<T> z = S[(long long)b * a.nx + c];
-    const cx<T> zm = S[(long long)bm * a.nx + cm];
+    const cx<T> z = S[spec_at(a, b, c)];
+    const cx<T> zm = S[spec_at(a, bm, cm)];
     o1[c] = {T(0.5) * (z.re + zm.re), T(0.5) * (z.im - zm.im)};
     if (second) o2[c] = {T(0.5) * (z.im + zm.im), T(0.5) * (zm.re - z.re)};
   }
@@ -58,14 +65,14 @@ __global__ void __launch_bounds__(kHalfTH) tangle_kernel(HalfArgs<T> a) {
   const int b = (int)(row - p * a.ny);
   const int bm = b == 0 ? 0 : a.ny - b;
   const int h = a.nx / 2 + 1;
-  cx<T>* S = a.spec + p * (long long)a.nx * a.ny + (long long)b * a.nx;
+  cx<T>* S = a.spec + p * (long long)a.nx * a.ny;
   const cx<T>* X1 = a.half + 2 * p * (long long)a.ny * h;
   const cx<T>* X2 = X1 + (long long)a.ny * h;
   const bool second = 2 * p + 1 < a.nreal;
   for (int c = threadIdx.x; c < a.nx; c += kHalfTH) {
     const cx<T> u = hermitian_at(X1, h, a.nx, b, bm, c);
     const cx<T> v = second ? hermitian_at(X2, h, a.nx, b, bm, c) : cx<T>{T(0), T(0)};
-    S[c] = {u.re - v.im, u.im + v.re};  // X1 + i X2
+    S[spec_at(a, b, c)] = {u.re - v.im, u.im + v.re};  // X1 + i X2
   }
 }
 

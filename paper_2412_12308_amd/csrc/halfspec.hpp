@@ -17,6 +17,11 @@ struct HalfArgs {
   int nx, ny;
   long long npairs;  // pairs in this launch
   long long nreal;   // real fields in this launch (2 npairs, or one less)
+  // Layout of spec: t < 0 row-major; else blocks of 2^t columns x ny rows,
+  // element (y, x) at block (x >> t), offset y 2^t + (x mod 2^t) within it
+  // (the column passes' tiled layout), ny = 2^logny.
+  int t = -1;
+  int logny = 0;
 };
 
 template <typename T>

@@ -468,6 +468,17 @@ int half_transform(Context* c, bool inverse, const void* in, void* out, int nx, 
   const long long cb = c->chunk_bytes_for(dt, lx, ly);
   long long chunk = cb > 0 ? std::max<long long>(1, cb / (long long)pair_bytes) : npairs;
   chunk = std::min<long long>(chunk, npairs);
+  // the pair spectra in the column passes' tiled layout, as in the solves
+  const ColVariant* cv = c->col_variant(dt, ly, 1);
+  if (!cv) return FFTPDE_EINVAL;
+  int lt = -1;
+  const int tiled_bytes = c->tiled_bytes_for(dt, lx, ly);
+  if (tiled_bytes > 0) {
+    int bt = 0;
+    while ((int)sizeof(cx<T>) << (bt + 1) <= tiled_bytes) bt++;
+    lt = bt > cv->logt ? bt : cv->logt;
+    if (lt >= lx) lt = -1;
+  }
   void* w = nullptr;
   const int rcw = c->workspace(pair_bytes * (size_t)chunk, s, &w);
   if (rcw != FFTPDE_OK) return rcw;
@@ -479,13 +490,13 @@ int half_transform(Context* c, bool inverse, const void* in, void* out, int nx, 
     const long long nrows = (long long)ny * np;
     const long long f0 = 2 * p0, nreal = std::min<long long>(2 * np, batch - f0);
     const size_t real_off = sizeof(T) * (size_t)(f0 * pts), half_off = sizeof(cx<T>) * (size_t)(f0 * hpts);
-    HalfArgs<T> h{static_cast<cx<T>*>(w), nullptr, nx, ny, np, nreal};
+    HalfArgs<T> h{static_cast<cx<T>*>(w), nullptr, nx, ny, np, nreal, lt, ly};
     const double hbytes = (double)sizeof(cx<T>) * (double)(np * pts + nreal * hpts);
     int rc = FFTPDE_OK;
     if (!inverse) {
       h.half = static_cast<cx<T>*>(at<T>(out, half_off));
-      rc = row_pass<T>(c, at<T>(in, real_off), w, lx, ly, nrows, false, 1.0, s, -1, -1, 1, 0, nreal);
-      if (rc == FFTPDE_OK) rc = col_pass<T>(c, w, nullptr, w, nullptr, lx, ly, np, kColForward, sym, 1, s);
+      rc = row_pass<T>(c, at<T>(in, real_off), w, lx, ly, nrows, false, 1.0, s, -1, lt, 1, 0, nreal);
+      if (rc == FFTPDE_OK) rc = col_pass<T>(c, w, nullptr, w, nullptr, lx, ly, np, kColForward, sym, 1, s, lt);
       if (rc == FFTPDE_OK) {
         const hipError_t e = timed_launch(c, name, hbytes, s, [&] { return launch_untangle<T>(h, s); });
         if (e != hipSuccess) {
@@ -500,9 +511,9 @@ int half_transform(Context* c, bool inverse, const void* in, void* out, int nx, 
         set_last_error(name, e);
         rc = FFTPDE_EDEVICE;
       }
-      if (rc == FFTPDE_OK) rc = col_pass<T>(c, w, nullptr, w, nullptr, lx, ly, np, kColInverse, sym, 1, s);
+      if (rc == FFTPDE_OK) rc = col_pass<T>(c, w, nullptr, w, nullptr, lx, ly, np, kColInverse, sym, 1, s, lt);
       if (rc == FFTPDE_OK)
-        rc = row_pass<T>(c, w, at<T>(out, real_off), lx, ly, nrows, true, 1.0, s, -1, -1, 0, 1, nreal);
+        rc = row_pass<T>(c, w, at<T>(out, real_off), lx, ly, nrows, true, 1.0, s, lt, -1, 0, 1, nreal);
     }
     if (rc != FFTPDE_OK) return rc;
   }
