@@ -69,7 +69,8 @@ extern "C" {
 /* ---- dtypes and operators ---------------------------------------------- */
 #define FFTPDE_C64 0  /* FP32 complex; FP64 twiddles rounded once, FP64 phases */
 #define FFTPDE_C128 1 /* FP64 complex throughout */
-/* Real fields (solves only): FP32 / FP64 points, batch*nx*ny values per
+/* Real fields (the 2D solves, the sourced solves and the half-spectrum
+ * transforms): FP32 / FP64 points, batch*nx*ny values per
  * buffer, same row-major layout.  The solves' symbols are real and even in k,
  * so a solve maps real fields to real fields and S(u1 + i u2) = S(u1) +
  * i S(u2): fields 2p and 2p+1 of the batch are solved together as the real
@@ -77,8 +78,8 @@ extern "C" {
  * with zero), in the precision of FFTPDE_C64 / FFTPDE_C128.  Each real field
  * moves half the bytes of a complex one.  The rounding error of a field is
  * bounded relative to the norm of its pair (sqrt(|u1|^2 + |u2|^2)), not its
- * own norm alone.  fft2d_forward / fft2d_inverse, evolution, batches and the
- * server take complex fields only. */
+ * own norm alone.  fft2d_forward / fft2d_inverse, 3D, RK4, evolution,
+ * batches and the server take complex fields only. */
 #define FFTPDE_R32 2
 #define FFTPDE_R64 3
 
