@@ -98,7 +98,8 @@ int mr_pass(Context* c, int mode, int nf, const void* in0, const void* in1, void
   a.rout = static_cast<T*>(rout);
   a.nreal = nreal;
   a.by_ny = MrDiv(ny);
-  const int cap = mr_cap(sizeof(T) == 8, nf);
+  const bool small = mr_row_small(sizeof(T) == 8, nf, col);
+  const int cap = small ? kMrRowCap : mr_cap(sizeof(T) == 8, nf);
   if (col) {
     // adjacent columns, each padded by one in LDS
     a.lines = std::max(1, std::min(kMrMaxColLines, cap / (n + 1)));
@@ -111,14 +112,14 @@ int mr_pass(Context* c, int mode, int nf, const void* in0, const void* in1, void
     a.tiles = ((long long)ny * fields + a.lines - 1) / a.lines;
   }
   a.by_lines = MrDiv(a.lines);
-  const long long grid = std::min<long long>(a.tiles, (long long)std::max(1, c->num_cus) * mr_occupancy<T>(nf));
+  const long long grid = std::min<long long>(a.tiles, (long long)std::max(1, c->num_cus) * mr_occupancy<T>(nf, small));
   const int nin = 1 + (in1 ? 1 : 0), nout = 1 + (out1 ? 1 : 0);
   double bytes = (double)sizeof(cx<T>) * (double)nx * ny * (double)fields * (nin + nout);
   if (rin || rout)  // one real side, one pair-field side
     bytes = (double)nx * ny * ((double)sizeof(T) * (double)nreal + (double)sizeof(cx<T>) * (double)fields);
   const char* name = col ? (sizeof(T) == 4 ? "mixed_col_float" : "mixed_col_double")
                          : (sizeof(T) == 4 ? "mixed_row_float" : "mixed_row_double");
-  const hipError_t e = timed_launch(c, name, bytes, s, [&] { return mr_launch<T>(a, nf, (int)grid, s); });
+  const hipError_t e = timed_launch(c, name, bytes, s, [&] { return mr_launch<T>(a, nf, small, (int)grid, s); });
   if (e != hipSuccess) {
     set_last_error(name, e);
     return FFTPDE_EDEVICE;

@@ -189,10 +189,10 @@ struct MrWave {
   }
 };
 
-template <typename T, int NF>
-__global__ void __launch_bounds__(mr_threads(sizeof(T) == 8)) mr_kernel(MrArgs<T> a) {
-  constexpr int TH = mr_threads(sizeof(T) == 8);
-  constexpr int CAP = mr_cap(sizeof(T) == 8, NF);
+template <typename T, int NF, bool SMALL>
+__global__ void __launch_bounds__(SMALL ? kMrRowTH : mr_threads(sizeof(T) == 8)) mr_kernel(MrArgs<T> a) {
+  constexpr int TH = SMALL ? kMrRowTH : mr_threads(sizeof(T) == 8);
+  constexpr int CAP = SMALL ? kMrRowCap : mr_cap(sizeof(T) == 8, NF);
   // per field: column tiles pad each line by one, then the bank pad
   constexpr int LDSF = mr_padded(CAP + kMrMaxColLines);
   constexpr bool TWL = mr_tw_in_lds(sizeof(T) == 8, NF);
@@ -381,35 +381,43 @@ __global__ void __launch_bounds__(mr_threads(sizeof(T) == 8)) mr_kernel(MrArgs<T
   }
 }
 
-template <typename T, int NF>
+template <typename T, int NF, bool SMALL>
 int occupancy_of() {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, mr_kernel<T, NF>, mr_threads(sizeof(T) == 8), 0) !=
-      hipSuccess)
-    return 1;
+  const int th = SMALL ? kMrRowTH : mr_threads(sizeof(T) == 8);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, mr_kernel<T, NF, SMALL>, th, 0) != hipSuccess) return 1;
   return n < 1 ? 1 : n;
 }
 
 }  // namespace
 
 template <typename T>
-int mr_occupancy(int nf) {
-  static const int o1 = occupancy_of<T, 1>(), o2 = occupancy_of<T, 2>();
+int mr_occupancy(int nf, bool small) {
+  static const int o1 = occupancy_of<T, 1, false>(), o2 = occupancy_of<T, 2, false>();
+  static const int os = sizeof(T) == 4 ? occupancy_of<T, 1, true>() : 1;
+  if (small) return os;
   return nf == 2 ? o2 : o1;
 }
 
 template <typename T>
-hipError_t mr_launch(const MrArgs<T>& a, int nf, int grid, hipStream_t s) {
+hipError_t mr_launch(const MrArgs<T>& a, int nf, bool small, int grid, hipStream_t s) {
   if (a.tiles < 1 || grid < 1 || grid > a.tiles) return hipErrorInvalidValue;
+  if (small && !mr_row_small(sizeof(T) == 8, nf, a.mode >= kMrColFwd)) return hipErrorInvalidValue;
   const unsigned th = mr_threads(sizeof(T) == 8);
-  if (nf == 2) hipLaunchKernelGGL((mr_kernel<T, 2>), dim3((unsigned)grid), dim3(th), 0, s, a);
-  else hipLaunchKernelGGL((mr_kernel<T, 1>), dim3((unsigned)grid), dim3(th), 0, s, a);
+  if (small) {
+    if constexpr (sizeof(T) == 4)
+      hipLaunchKernelGGL((mr_kernel<T, 1, true>), dim3((unsigned)grid), dim3(kMrRowTH), 0, s, a);
+  } else if (nf == 2) {
+    hipLaunchKernelGGL((mr_kernel<T, 2, false>), dim3((unsigned)grid), dim3(th), 0, s, a);
+  } else {
+    hipLaunchKernelGGL((mr_kernel<T, 1, false>), dim3((unsigned)grid), dim3(th), 0, s, a);
+  }
   return hipGetLastError();
 }
 
-template int mr_occupancy<float>(int);
-template int mr_occupancy<double>(int);
-template hipError_t mr_launch<float>(const MrArgs<float>&, int, int, hipStream_t);
-template hipError_t mr_launch<double>(const MrArgs<double>&, int, int, hipStream_t);
+template int mr_occupancy<float>(int, bool);
+template int mr_occupancy<double>(int, bool);
+template hipError_t mr_launch<float>(const MrArgs<float>&, int, bool, int, hipStream_t);
+template hipError_t mr_launch<double>(const MrArgs<double>&, int, bool, int, hipStream_t);
 
 }  // namespace fftpde

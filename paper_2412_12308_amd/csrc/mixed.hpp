@@ -24,8 +24,9 @@
 
 namespace fftpde {
 
-// Threads per workgroup, both dtypes (512-thread FP32 workgroups on smaller
-// tiles ran rows faster and columns slower).
+// Threads per workgroup, both dtypes; FP32 one-field row passes use the
+// smaller variant below (on column passes it ran 30 % slower: a column tile
+// of half the points holds half the adjacent columns).
 constexpr int mr_threads(bool /*fp64*/) { return 1024; }
 constexpr int kMrMaxSide = 4096;
 constexpr int kMrMaxColLines = 64;  // columns per column tile
@@ -38,6 +39,12 @@ constexpr int kMrMaxStages = 12;
 // of 8192 points beat 4096 (with the next tile staged in registers) and
 // 12288 (register spills); the table in LDS beats reading it from L1/L2.
 constexpr int mr_cap(bool fp64, int nf) { return fp64 ? 4096 : 8192 / nf; }
+// FP32 one-field row passes: 512-thread workgroups on 4096-point tiles, two
+// per CU, so that one workgroup's loads overlap the other's stages (1536^2
+// rows, 8 fields: 118 us against 127 with the 1024-thread variant).
+constexpr int kMrRowTH = 512;
+constexpr int kMrRowCap = 4096;
+constexpr bool mr_row_small(bool fp64, int nf, bool col) { return !fp64 && nf == 1 && !col; }
 constexpr bool mr_tw_in_lds(bool fp64, int nf) { return !(fp64 && nf == 2); }
 
 // Sides the mixed-radix path takes: 2..4096, 7-smooth.
@@ -147,11 +154,12 @@ struct MrArgs {
   MrDiv by_ny;
 };
 
-// grid: persistent workgroups (at most a.tiles)
+// grid: persistent workgroups (at most a.tiles); small: the row variant of
+// mr_row_small
 template <typename T>
-hipError_t mr_launch(const MrArgs<T>& a, int nf, int grid, hipStream_t s);
-// resident workgroups per CU of the kernel for (T, nf)
+hipError_t mr_launch(const MrArgs<T>& a, int nf, bool small, int grid, hipStream_t s);
+// resident workgroups per CU of the kernel for (T, nf, small)
 template <typename T>
-int mr_occupancy(int nf);
+int mr_occupancy(int nf, bool small);
 
 }  // namespace fftpde
