@@ -400,7 +400,7 @@ def batch_leg(fp, torch, reps: int, warmup: int, check: bool):
 
 
 def serving_leg(fp, torch, duration: float = 11.0, warm: float = 1.0, budget_gib: int = 64,
-                slots: int = 64, streams: int = 4):
+                slots: int = 64, streams: int = 4, check: bool = True):
     """Open-loop serving: requests are submitted at their arrival times from
     a client thread; the main thread waits for each, records its latency and
     releases it.  Latency = completion (device timestamp) - submission."""
@@ -450,6 +450,12 @@ def serving_leg(fp, torch, duration: float = 11.0, warm: float = 1.0, budget_gib
     th = threading.Thread(target=client, daemon=True)
     th.start()
     started.wait()
+    # a sample of served results is kept for a check against the FP64 oracle
+    # after the run: the largest request of each kind and every 2000th
+    largest = {k: max((i for i, t in enumerate(trace) if t.kind == k), key=lambda i: trace[i].nx * trace[i].ny)
+               for k in (0, 1, 2) if any(t.kind == k for t in trace)}
+    keep_ids = set(largest.values()) | set(range(0, len(trace), 2000))
+    kept = {}
     lat, kinds, arr = [], [], []
     failed = 0
     for i, t in enumerate(trace):
@@ -462,6 +468,8 @@ def serving_leg(fp, torch, duration: float = 11.0, warm: float = 1.0, budget_gib
             lat.append((res["t_done"] - res["t_submit"]) * 1e3 + lag[i] * 1e3)
             kinds.append(t.kind)
             arr.append(t.arrival)
+            if check and i in keep_ids:
+                kept[i] = srv.copy_out(ids[i], torch.empty((t.ny, t.nx), dtype=torch.complex64, device=dev))
         srv.release(ids[i])
     th.join()
     st = srv.stats()
@@ -472,6 +480,27 @@ def serving_leg(fp, torch, duration: float = 11.0, warm: float = 1.0, budget_gib
 
     def q(v, p):
         return float(np.percentile(v, p, method="inverted_cdf")) if len(v) else None
+    checked = []
+    if kept:
+        import oracle
+        th_n = oracle.default_threads()
+        for i in sorted(kept):
+            t = trace[i]
+            f, lx, ly = W.serving_input(t.kind, t.nx, t.ny)
+            x = f.astype(np.complex64).astype(np.complex128)
+            T = t.steps * t.dt
+            if t.kind == 0:
+                ref = oracle.solve_poisson(x, lx, ly, threads=th_n)
+            elif t.kind == 1:
+                ref = oracle.solve_diffusion(x, lx, ly, t.coef, T, threads=th_n)
+            else:
+                ref = oracle.solve_wave(x, None, lx, ly, t.coef, T, threads=th_n)[0]
+            got = kept[i].cpu().numpy().astype(np.complex128)
+            den = max(float(np.linalg.norm(ref)), float(np.linalg.norm(x)) if t.kind else 0.0)
+            err = float(np.linalg.norm(got - ref) / den)
+            checked.append({"kind": ("poisson", "diffusion", "wave")[t.kind], "nx": t.nx, "ny": t.ny,
+                            "steps": t.steps, "err_vs_oracle": err,
+                            "tol": 2 * 2e-6 * np.log2(max(t.nx, t.ny))})
     per_kind = {name: {"p50_ms": q(lat[m & (kinds == k)], 50), "p99_ms": q(lat[m & (kinds == k)], 99),
                        "count": int((m & (kinds == k)).sum())}
                 for k, name in ((0, "poisson"), (1, "diffusion"), (2, "wave"))}
@@ -484,6 +513,7 @@ def serving_leg(fp, torch, duration: float = 11.0, warm: float = 1.0, budget_gib
             "submit_lag_p99_ms": round(float(np.percentile(np.array(lag), 99)) * 1e3, 3),
             "hbm_budget_gib": budget_gib, "hbm_high_water_gib": round(st["hbm_high_water"] / 2 ** 30, 3),
             "max_slots": slots, "streams": streams, "iterations": st["iterations"],
+            "checked_vs_oracle": checked,
             "latency": "device completion - submission + client submit lag",
             "steps": "diagnostics (mean, energy) at every step from the resident spectra, "
                      "u materialised at the final step"}
@@ -581,7 +611,7 @@ def main(argv=None):
     serve = None
     if not a.no_serve:
         print("# serving leg", file=sys.stderr, flush=True)
-        serve = serving_leg(fp, torch, duration=a.serve_seconds)
+        serve = serving_leg(fp, torch, duration=a.serve_seconds, check=not a.no_check)
     cpu = None
     if not a.no_cpu:
         print("# cpu baseline", file=sys.stderr, flush=True)

@@ -450,8 +450,9 @@ int fftpde_batch_destroy(fftpde_batch *batch);
  *   and diag valid until the request has ended.
  * Budget.  A request is charged its footprint while it runs: the bytes of its
  *   fields (in, v0, out) plus what the server allocates for it (the resident
- *   spectra, a reduction scratch, a server-owned output) from a pool of
- *   `hbm_budget` bytes reserved at creation.  A request whose footprint
+ *   spectra of an evolution, a reduction scratch, a Poisson solve's spectrum
+ *   between its passes, a server-owned output) from a pool of `hbm_budget`
+ *   bytes reserved at creation; no request allocates outside the pool.  A request whose footprint
  *   exceeds the whole budget is rejected at submission (FFTPDE_EBUDGET); one
  *   that does not fit now waits, and so do all requests behind it.
  * fftpde_server_create: ctx names the device (the server keeps its own

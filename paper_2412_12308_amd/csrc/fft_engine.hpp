@@ -279,7 +279,44 @@ constexpr int plan_pad(int logn, int maxlr, bool rev) {
 // The engine.  x[q R + t] holds element (line(g), j(g) + t N/R) of the
 // current stage's input, g = tid + TH q.
 // ---------------------------------------------------------------------------
-template <typename T, int LOGN, int E, int TH, int MAXLR, bool REV, class Map, bool SPLIT = false>
+// Moves value v from lane src of its group of G consecutive lanes (G = 2 or
+// 4) to every lane of the group: a DPP quad permutation, one move per 32-bit
+// word.  src must fold to a constant.
+template <int G>
+__device__ __forceinline__ int group_bcast_word(int v, int src) {
+  static_assert(G == 2 || G == 4, "groups of 2 or 4 lanes");
+  if constexpr (G == 4) {
+    switch (src) {
+      case 0: return __builtin_amdgcn_update_dpp(0, v, 0x00, 0xf, 0xf, false);
+      case 1: return __builtin_amdgcn_update_dpp(0, v, 0x55, 0xf, 0xf, false);
+      case 2: return __builtin_amdgcn_update_dpp(0, v, 0xaa, 0xf, 0xf, false);
+      default: return __builtin_amdgcn_update_dpp(0, v, 0xff, 0xf, 0xf, false);
+    }
+  } else {
+    // quad_perm [s, s, 2 + s, 2 + s]
+    return src == 0 ? __builtin_amdgcn_update_dpp(0, v, 0xa0, 0xf, 0xf, false)
+                    : __builtin_amdgcn_update_dpp(0, v, 0xf5, 0xf, 0xf, false);
+  }
+}
+template <int G, typename T>
+__device__ __forceinline__ cx<T> group_bcast(cx<T> v, int src) {
+  if constexpr (sizeof(T) == 4) {
+    return {__int_as_float(group_bcast_word<G>(__float_as_int(v.re), src)),
+            __int_as_float(group_bcast_word<G>(__float_as_int(v.im), src))};
+  } else {
+    auto d = [&](double x) {
+      const long long b = __double_as_longlong(x);
+      const int lo = group_bcast_word<G>(int(b & 0xffffffffll), src);
+      const int hi = group_bcast_word<G>(int(b >> 32), src);
+      return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+    };
+    return {d(v.re), d(v.im)};
+  }
+}
+
+// TWG: lanes l with equal l / TWG hold butterflies of the same index (the
+// columns of a column tile) and share their twiddles (TwSrc::stage only).
+template <typename T, int LOGN, int E, int TH, int MAXLR, bool REV, class Map, bool SPLIT = false, int TWG = 1>
 struct Engine {
   static constexpr int N = 1 << LOGN;
   static constexpr int NST = plan_nstages(LOGN, MAXLR);
@@ -435,7 +472,10 @@ struct Engine {
   //                  once);
   //   TwSrc::lds     a workgroup copy of w_N^e, e < N, in LDS;
   //   TwSrc::stage   per-stage tables in global memory (see stage_tw_off),
-  //                  requested one stage ahead like the global table.
+  //                  requested one stage ahead like the global table; with
+  //                  TWG > 1, each of the TWG lanes that share a butterfly
+  //                  index loads every TWG-th twiddle and the values reach
+  //                  the other lanes by cross-lane moves (DPP).
   enum class TwSrc { global, regs, lds, stage };
 
   // Stage tables: one table per engine plan holding, for every stage S >= 1,
@@ -463,8 +503,19 @@ struct Engine {
         int line, j;
         Map::split(tid + TH * q, LOGN - LR, line, j);
         const cx<T>* b = tws + stw_off<S>() + (j & (NS - 1));
+        if constexpr (TWG > 1) {
+          // lane c of a group loads t = TWG u + c + 1 (the group's last lane
+          // repeats t = R - 1 where R - 1 is not a multiple of TWG)
+          const int c = tid & (TWG - 1);
 #pragma unroll
-        for (int t = 1; t < R; t++) w[off + q * (R - 1) + t - 1] = b[(t - 1) * NS];
+          for (int u = 0; u < (R - 1 + TWG - 1) / TWG; u++) {
+            const int t = min(TWG * u + c + 1, R - 1);
+            w[off + q * (R - 1) + u] = b[(t - 1) * NS];
+          }
+        } else {
+#pragma unroll
+          for (int t = 1; t < R; t++) w[off + q * (R - 1) + t - 1] = b[(t - 1) * NS];
+        }
       }
     }
   }
@@ -522,6 +573,10 @@ struct Engine {
           const int k = j & (NS - 1);
 #pragma unroll
           for (int t = 1; t < R; t++) v[t] = cmul(v[t], twl[(t * k) << (LOGN - LNS - LR)]);
+        } else if constexpr (SRC == TwSrc::stage && TWG > 1) {
+#pragma unroll
+          for (int t = 1; t < R; t++)
+            v[t] = cmul(v[t], group_bcast<TWG>(w[off + q * (R - 1) + (t - 1) / TWG], (t - 1) % TWG));
         } else {
 #pragma unroll
           for (int t = 1; t < R; t++) v[t] = cmul(v[t], w[off + q * (R - 1) + t - 1]);

@@ -37,8 +37,10 @@ enum SymOp : int {
   kSymWaveSource = 5, // wave with a source constant in time (three-field pass)
 };
 
-// Where the passes read their twiddles (see Engine::TwSrc).
-enum TwMode : int { kTwGlobal = 0, kTwRegs = 1, kTwLds = 2, kTwStage = 3 };
+// Where the passes read their twiddles (see Engine::TwSrc).  kTwStageGrp:
+// stage tables, each value loaded by one lane of the tile's columns and
+// moved to the others across lanes (column tiles of 2 or 4 columns).
+enum TwMode : int { kTwGlobal = 0, kTwRegs = 1, kTwLds = 2, kTwStage = 3, kTwStageGrp = 4 };
 
 struct SymParams {
   int op;
@@ -54,6 +56,11 @@ struct SymParams {
   // scale x and kys, hy scale z.  lx3 = 0: 2D.
   int lx3;
   double ky3s, hy3;
+  // wave, FP32 fields: every nonzero (w t / pi)^2 of the grid lies in
+  // [1e-30, 1e36], so the phase may take the FP32-seeded square root without
+  // a range check per coefficient (set by the host from the extreme
+  // wavenumbers; 0 = check each coefficient)
+  int phase_fast;
 };
 
 // A load of streamed data read once: the non-temporal hint keeps it from
@@ -189,6 +196,17 @@ struct Symbol<T, kSymPoisson> {
     else m = nscale / k2;
     return (a0 && bi == 0) ? T(0) : m;
   }
+  // at b' = j + dd (see Symbol<T, kSymWave>::split)
+  __device__ __forceinline__ bool split_ok() const { return true; }
+  __device__ __forceinline__ T split(int j, int dd) const { return (*this)(0, j + dd); }
+  __device__ __forceinline__ T operator()(int, int bi) const {
+    const T ky = kys * T(bi);
+    const T k2 = kx2 + ky * ky;
+    T m;
+    if constexpr (sizeof(T) == 4) m = nscale * __builtin_amdgcn_rcpf(k2);
+    else m = nscale / k2;
+    return (a0 && bi == 0) ? T(0) : m;
+  }
 };
 
 // exp(-kappa |k|^2 t) (Eq. (solCalorFourier)); exponent formed in FP64
@@ -217,7 +235,36 @@ struct Symbol<T, kSymDiffusion> {
     if constexpr (sizeof(T) == 4) return scale * expf(-float(arg));
     else return scale * exp(-arg);
   }
+  // at b' = j + dd (see Symbol<T, kSymWave>::split)
+  __device__ __forceinline__ bool split_ok() const { return true; }
+  __device__ __forceinline__ T split(int j, int dd) const {
+    const double ky = fma(kys, double(dd), kys * double(j));
+    const double arg = fma(kt * ky, ky, ex);
+    if constexpr (sizeof(T) == 4) return scale * expf(-float(arg));
+    else return scale * exp(-arg);
+  }
 };
+
+// sqrt of v in [1e-30, 1e36] (or 0) to about 1e-14 relative: an FP32
+// reciprocal square root y of v, then one Newton step in FP64 on s = v y,
+// s + (y/2)(v - s^2) (the error squares).  The FP32 operand is kept at
+// 1e-30 or above, so v = 0 gives y finite and s = 0 exactly.
+__device__ __forceinline__ double sqrt_fp64_ranged(double v) {
+  const float y = __builtin_amdgcn_rsqf(fmaxf(float(v), 1e-30f));
+  const double yd = double(y);
+  const double s = v * yd;
+  return fma(0.5 * yd, fma(-s, s, v), s);
+}
+
+// cos(pi h) for FP64 h >= 0 in FP32: h is reduced exactly to r in [-1, 1]
+// (h minus an even integer), then to f = r - m in [-1/2, 1/2] with m in
+// {-1, 0, 1}; cos(pi r) = (-1)^m cos(pi f).
+__device__ __forceinline__ float cospi_reduced(double h) {
+  const double r = fma(-2.0, rint(0.5 * h), h);
+  const double m = rint(r);
+  const float c = cospi_half(float(r - m));
+  return m != 0.0 ? -c : c;
+}
 
 // cos(c |k| t), the wave propagator with zero initial velocity
 // (Eq. (OmegaNonZero), (OmegaZero)); phase in FP64 half-turns, reduced in FP64
@@ -226,7 +273,9 @@ struct Symbol<T, kSymWave> {
   double hx2, hy;
   T scale;
   int logny;
+  bool fast;
   __device__ __forceinline__ Symbol(const SymParams& p, int a) {
+    fast = p.phase_fast != 0;
     if (p.lx3 > 0) {
       const double hx = p.hx * signed_index(a & ((1 << p.lx3) - 1), p.lx3);
       const double hyy = p.hy3 * signed_index(a >> p.lx3, p.lognx - p.lx3);
@@ -254,6 +303,16 @@ struct Symbol<T, kSymWave> {
       return scale * cospi(sqrt(h2));
     }
   }
+  // The same at the signed index b' = j + dd (j >= 0; dd a compile-time
+  // offset of the caller's unrolled loop, so hy j is formed once per j); for
+  // FP32 only where `fast` holds (split_ok).
+  __device__ __forceinline__ bool split_ok() const { return sizeof(T) == 8 || fast; }
+  __device__ __forceinline__ T split(int j, int dd) const {
+    const double hyb = fma(hy, double(dd), hy * double(j));
+    const double h2 = fma(hyb, hyb, hx2);
+    if constexpr (sizeof(T) == 4) return scale * cospi_reduced(sqrt_fp64_ranged(h2));
+    else return scale * cospi(sqrt(h2));
+  }
 };
 
 template <typename T>
@@ -261,6 +320,8 @@ struct Symbol<T, kSymScale> {
   T scale;
   __device__ __forceinline__ Symbol(const SymParams& p, int) : scale(T(p.scale)) {}
   __device__ __forceinline__ T operator()(int) const { return scale; }
+  __device__ __forceinline__ bool split_ok() const { return true; }
+  __device__ __forceinline__ T split(int, int) const { return scale; }
 };
 
 // Wave propagator with an initial velocity: cw = cos(w t), sw = sin(w t),
@@ -575,14 +636,17 @@ __global__ void __launch_bounds__(TH) col_kernel(ColArgs<T> a) {
   constexpr int N = 1 << LOGN;
   constexpr int TT = 1 << LOGT;
   static_assert(N * TT == E * TH, "tile must hold whole columns");
-  static_assert(TWM == kTwGlobal || TWM == kTwLds || TWM == kTwStage,
+  static_assert(TWM == kTwGlobal || TWM == kTwLds || TWM == kTwStage || TWM == kTwStageGrp,
                 "column pass twiddles: global table, LDS or stage tables");
   // When TH is a multiple of T every thread stays on one column of the tile.
   constexpr bool kOneCol = (TH % TT) == 0;
+  // kTwStageGrp: the T consecutive lanes of a butterfly index share twiddles
+  static_assert(TWM != kTwStageGrp || (kOneCol && (TT == 2 || TT == 4)), "shared twiddles: tiles of 2 or 4 columns");
+  constexpr int kTwg = TWM == kTwStageGrp ? TT : 1;
   using FMap = ColMap<LOGN, LOGT, plan_pad(LOGN, MAXLR, false)>;
   using IMap = ColMap<LOGN, LOGT, plan_pad(LOGN, MAXLR, true)>;
-  using Fwd = Engine<T, LOGN, E, TH, MAXLR, false, FMap, SPLIT>;
-  using Inv = Engine<T, LOGN, E, TH, MAXLR, true, IMap, SPLIT>;
+  using Fwd = Engine<T, LOGN, E, TH, MAXLR, false, FMap, SPLIT, kTwg>;
+  using Inv = Engine<T, LOGN, E, TH, MAXLR, true, IMap, SPLIT, kTwg>;
   constexpr int kLdsWords = Fwd::kLdsWords > Inv::kLdsWords ? Fwd::kLdsWords : Inv::kLdsWords;
   __shared__ typename Fwd::Word lds[kLdsWords];
   __shared__ cx<T> twl[TWM == kTwLds ? N : 1];
@@ -687,12 +751,12 @@ __global__ void __launch_bounds__(TH) col_kernel(ColArgs<T> a) {
   }
   auto fwd = [&](cx<T>(&v)[E], int t) {
     if constexpr (TWM == kTwLds) Fwd::run_lds(v, lds, twl, t);
-    else if constexpr (TWM == kTwStage) Fwd::run_stage(v, lds, a.twf, t);
+    else if constexpr (TWM == kTwStage || TWM == kTwStageGrp) Fwd::run_stage(v, lds, a.twf, t);
     else Fwd::run(v, lds, a.tw, t);
   };
   auto inv = [&](cx<T>(&v)[E], int t) {
     if constexpr (TWM == kTwLds) Inv::run_lds(v, lds, twl, t);
-    else if constexpr (TWM == kTwStage) Inv::run_stage(v, lds, a.twi, t);
+    else if constexpr (TWM == kTwStage || TWM == kTwStageGrp) Inv::run_stage(v, lds, a.twi, t);
     else Inv::run(v, lds, a.tw, t);
   };
   // Multiply by a real symbol and conjugate (for the inverse by conjugation).
@@ -700,10 +764,22 @@ __global__ void __launch_bounds__(TH) col_kernel(ColArgs<T> a) {
     constexpr int OP = decltype(sym_tag)::value;
     if constexpr (kOneCol) {
       const Symbol<T, OP> sym(a.sym, int((col0 + (tid & (TT - 1))) & fmask));
-      Inv::for_each_input(tid, [&](int i, int, int n) {
-        const T m = sym(n);
-        v[i] = {v[i].re * m, -v[i].im * m};
-      });
+      // (the kernels for all modes keep the general form: the split one's
+      // registers would cost them a resident workgroup)
+      if (FUSED && sym.split_ok()) {
+        // position n = j + d of the inverse's first stage, d = t N/R a
+        // compile-time multiple of N/R: its signed index is j + d, or
+        // j + d - N once d reaches N/2 (N/2 is a multiple of N/R and j < N/R)
+        Inv::for_each_input_split(tid, [&](int i, int, int j, int d) {
+          const T m = sym.split(j, d >= (N >> 1) ? d - N : d);
+          v[i] = {v[i].re * m, -v[i].im * m};
+        });
+      } else {
+        Inv::for_each_input(tid, [&](int i, int, int n) {
+          const T m = sym(n);
+          v[i] = {v[i].re * m, -v[i].im * m};
+        });
+      }
     } else {
       Inv::for_each_input(tid, [&](int i, int line, int n) {
         const Symbol<T, OP> sym(a.sym, int((col0 + line) & fmask));

@@ -164,9 +164,15 @@ class HipBackend : public Backend {
     const fftpde_request& r = q.r;
     hipStream_t s = streams_[q.stream];
     if (q.dep_ev && hipStreamWaitEvent(s, q.dep_ev, 0) != hipSuccess) return FFTPDE_EDEVICE;
-    if (r.op == FFTPDE_POISSON)
+    if (r.op == FFTPDE_POISSON) {
+      // the spectrum between the passes goes to the request's pool block, so
+      // the solve neither allocates nor escapes the budget
+      SolveScratch sc;
+      sc.p = q.F;
+      sc.bytes = q.work_bytes;
       return run_solve(c_, r.dtype, FFTPDE_POISSON, r.in, nullptr, q.out, nullptr, r.nx, r.ny, 1, r.lx, r.ly, 0.0,
-                       0.0, s);
+                       0.0, s, sc);
+    }
     int rc = run_transform(c_, r.dtype, false, r.in, q.F, r.nx, r.ny, 1, s);
     if (rc == FFTPDE_OK && q.G) rc = run_transform(c_, r.dtype, false, r.v0, q.G, r.nx, r.ny, 1, s);
     return rc;
@@ -378,7 +384,9 @@ int check_request(const fftpde_request& r) {
 void sizes(const fftpde_request& r, size_t* work, size_t* out, long long* footprint) {
   const size_t fb = (size_t)r.nx * r.ny * (r.dtype == FFTPDE_C64 ? 8 : 16);
   size_t w = 0;
-  if (r.op != FFTPDE_POISSON) {
+  if (r.op == FFTPDE_POISSON) {
+    w += up256(fb);                  // the spectrum between the solve's passes
+  } else {
     w += up256(fb);                  // F
     if (r.v0) w += up256(fb);        // G
     if (r.diag) w += up256(diag_scratch_doubles(ilog2s(r.nx), ilog2s(r.ny), 1) * sizeof(double));

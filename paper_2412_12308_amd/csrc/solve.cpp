@@ -88,19 +88,38 @@ SymParams make_sym(int op, int nx, int ny, double lx, double ly, double coef, do
     p.t = t;
     p.hx = 2.0 * coef * t / lx;
     p.hy = 2.0 * coef * t / ly;
+    set_phase_range(p, nx, ny, 1);
   }
   return p;
+}
+
+// SymParams::phase_fast from the extreme nonzero (w t / pi)^2 of the grid:
+// the smallest is one step along an axis, the largest the corner of signed
+// indices n/2 (3D: the y term along hy3 with ny3 points).
+void set_phase_range(SymParams& p, int nx, int ny, int ny3) {
+  double lo = 1e300, hi = 0.0;
+  auto axis = [&](double h, int n) {
+    if (h == 0.0 || n < 2) return;
+    lo = std::min(lo, h * h);
+    const double e = h * (n / 2);
+    hi += e * e;
+  };
+  axis(p.hx, p.lx3 > 0 ? (1 << p.lx3) : nx);
+  axis(p.hy, ny);
+  if (p.lx3 > 0) axis(p.hy3, ny3);
+  p.phase_fast = (hi == 0.0 || (lo >= 1e-30 && hi <= 1e36)) ? 1 : 0;
 }
 
 // Runs f(b0, nb, byte offset) over chunks of the batch of about
 // Context::chunk_bytes of field data: every pass of one chunk before the next,
 // so that what a pass writes is still in the Infinity Cache for the next.
 template <typename T, class F>
-int for_chunks(Context* c, int nx, int ny, int batch, F&& f) {
+int for_chunks(Context* c, int nx, int ny, int batch, F&& f, long long max_chunk = 0) {
   const size_t field = sizeof(cx<T>) * (size_t)nx * ny;
   const long long cb = c->chunk_bytes_for(sizeof(T) == 4 ? FFTPDE_C64 : FFTPDE_C128, ilog2(nx), ilog2(ny));
   long long chunk = cb > 0 ? std::max<long long>(1, cb / (long long)field) : batch;
   chunk = std::min<long long>(chunk, batch);
+  if (max_chunk > 0) chunk = std::min<long long>(chunk, max_chunk);
   for (long long b0 = 0; b0 < batch; b0 += chunk) {
     const long long nb = std::min<long long>(chunk, batch - b0);
     const int rc = f(b0, nb, field * (size_t)b0);
@@ -142,7 +161,7 @@ int transform(Context* c, const void* in, void* out, int nx, int ny, int batch, 
 // the next chunk
 template <typename T>
 int solve_real_symbol(Context* c, const void* in, void* out, int nx, int ny, int batch, const SymParams& sym,
-                      hipStream_t s) {
+                      hipStream_t s, const SolveScratch& sc) {
   const int dt = sizeof(T) == 4 ? FFTPDE_C64 : FFTPDE_C128;
   const int lx = ilog2(nx), ly = ilog2(ny);
   const size_t field = sizeof(cx<T>) * (size_t)nx * ny;
@@ -161,7 +180,13 @@ int solve_real_symbol(Context* c, const void* in, void* out, int nx, int ny, int
     while ((int)sizeof(cx<T>) << (bt + 1) <= tiled_bytes) bt++;
     lt = bt > cv->logt ? bt : cv->logt;
     if (lt >= lx) lt = -1;
-    if (lt >= 0) {
+    if (lt >= 0 && sc.p) {
+      // caller-provided scratch: as many fields per chunk as it holds
+      const long long fit = (long long)(sc.bytes / field);
+      if (fit < 1) return FFTPDE_EINVAL;
+      chunk = std::min<long long>(chunk, fit);
+      w = sc.p;
+    } else if (lt >= 0) {
       const int rcw = c->workspace(field * (size_t)chunk, s, &w);
       if (rcw != FFTPDE_OK) return rcw;
     }
@@ -186,12 +211,12 @@ int solve_real_symbol(Context* c, const void* in, void* out, int nx, int ny, int
 // intermediate), two fields per 256 MiB chunk of fields.
 template <typename T>
 int solve_wave_two(Context* c, const void* u0, const void* v0, void* u, void* v, int nx, int ny, int batch,
-                   const SymParams& sym, hipStream_t s) {
+                   const SymParams& sym, hipStream_t s, const SolveScratch& sc) {
   const int dt = sizeof(T) == 4 ? FFTPDE_C64 : FFTPDE_C128;
   const int lx = ilog2(nx), ly = ilog2(ny);
   const size_t field = sizeof(cx<T>) * (size_t)nx * ny;
   const long long cb = c->chunk_bytes_for(dt, lx, ly);
-  const long long chunk = std::min<long long>(cb > 0 ? std::max<long long>(1, cb / (long long)field) : batch, batch);
+  long long chunk = std::min<long long>(cb > 0 ? std::max<long long>(1, cb / (long long)field) : batch, batch);
   const ColVariant* cv = c->col_variant(dt, ly, 2);
   if (!cv) return FFTPDE_EINVAL;
   const int tiled_bytes = c->tiled_bytes_for(dt, lx, ly);
@@ -205,8 +230,16 @@ int solve_wave_two(Context* c, const void* u0, const void* v0, void* u, void* v,
   // spectra: F (then U) and G (then V); in the outputs when row-major
   void* w = nullptr;
   if (lt >= 0 || (v0 && !v)) {
-    const int rc = c->workspace(field * (size_t)chunk * (lt >= 0 ? 2 : 1), s, &w);
-    if (rc != FFTPDE_OK) return rc;
+    const size_t per = field * (lt >= 0 ? 2 : 1);  // scratch bytes per field of a chunk
+    if (sc.p) {
+      const long long fit = (long long)(sc.bytes / per);
+      if (fit < 1) return FFTPDE_EINVAL;
+      chunk = std::min<long long>(chunk, fit);
+      w = sc.p;
+    } else {
+      const int rc = c->workspace(per * (size_t)chunk, s, &w);
+      if (rc != FFTPDE_OK) return rc;
+    }
   }
   return for_chunks<T>(c, nx, ny, batch, [&](long long, long long nb, size_t off) {
     const long long nrows = (long long)ny * nb;
@@ -221,7 +254,7 @@ int solve_wave_two(Context* c, const void* u0, const void* v0, void* u, void* v,
     if (rc == FFTPDE_OK) rc = row_pass<T>(c, fs, ub, lx, ly, nrows, true, 1.0, s, lt, -1);
     if (rc == FFTPDE_OK && vb) rc = row_pass<T>(c, gs, vb, lx, ly, nrows, true, 1.0, s, lt, -1);
     return rc;
-  });
+  }, chunk);
 }
 
 
@@ -312,6 +345,7 @@ SymParams make_sym3d(int op, int nx, int ny, int nz, double lx, double ly, doubl
     p.hx = 2.0 * coef * t / lx;
     p.hy3 = 2.0 * coef * t / ly;
     p.hy = 2.0 * coef * t / lz;
+    set_phase_range(p, nx, nz, ny);
   }
   p.scale = 1.0 / ((double)nx * (double)ny * (double)nz);
   return p;
@@ -527,7 +561,7 @@ int run_half_transform(Context* c, int dtype, bool inverse, const void* in, void
 }
 
 int run_solve(Context* c, int dtype, int op, const void* in, const void* in2, void* out, void* out2, int nx, int ny,
-              int batch, double lx, double ly, double coef, double t, hipStream_t s) {
+              int batch, double lx, double ly, double coef, double t, hipStream_t s, const SolveScratch& sc) {
   const int sop = op == FFTPDE_POISSON ? kSymPoisson : op == FFTPDE_DIFFUSION ? kSymDiffusion : kSymWave;
   const SymParams sym = make_sym(sop, nx, ny, lx, ly, coef, t);
   if (dtype == FFTPDE_R32) return solve_real_pairs<float>(c, in, in2, out, out2, nx, ny, batch, sym, s);
@@ -536,11 +570,11 @@ int run_solve(Context* c, int dtype, int op, const void* in, const void* in2, vo
     const int r = dtype == FFTPDE_C64 ? small_pass<float>(c, in, out, nx, ny, batch, kColFwdMulInv, sym, s)
                                       : small_pass<double>(c, in, out, nx, ny, batch, kColFwdMulInv, sym, s);
     if (r != -100) return r;
-    return dtype == FFTPDE_C64 ? solve_real_symbol<float>(c, in, out, nx, ny, batch, sym, s)
-                               : solve_real_symbol<double>(c, in, out, nx, ny, batch, sym, s);
+    return dtype == FFTPDE_C64 ? solve_real_symbol<float>(c, in, out, nx, ny, batch, sym, s, sc)
+                               : solve_real_symbol<double>(c, in, out, nx, ny, batch, sym, s, sc);
   }
-  return dtype == FFTPDE_C64 ? solve_wave_two<float>(c, in, in2, out, out2, nx, ny, batch, sym, s)
-                             : solve_wave_two<double>(c, in, in2, out, out2, nx, ny, batch, sym, s);
+  return dtype == FFTPDE_C64 ? solve_wave_two<float>(c, in, in2, out, out2, nx, ny, batch, sym, s, sc)
+                             : solve_wave_two<double>(c, in, in2, out, out2, nx, ny, batch, sym, s, sc);
 }
 
 template <typename T>

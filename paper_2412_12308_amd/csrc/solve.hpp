@@ -23,6 +23,9 @@ hipError_t timed_launch(Context* c, const char* name, double bytes, hipStream_t 
 }
 
 SymParams make_sym(int op, int nx, int ny, double lx, double ly, double coef, double t);
+// SymParams::phase_fast for a wave symbol on an nx x ny grid (3D, p.lx3 > 0:
+// x of 2^lx3 points, y of ny3 points along hy3, z of ny points along hy).
+void set_phase_range(SymParams& p, int nx, int ny, int ny3);
 
 // One row pass over nrows = batch * 2^logny rows of length 2^lognx (forward,
 // or inverse by conjugation with `scale`).  in_t / out_t: log2 of the column
@@ -50,10 +53,20 @@ int run_transform(Context* c, int dtype, bool inverse, const void* in, void* out
 int run_half_transform(Context* c, int dtype, bool inverse, const void* in, void* out, int nx, int ny, int batch,
                        hipStream_t s);
 
+// Device memory a caller lends to a solve for the spectrum between its
+// passes; p = null: the context's per-stream workspace (grown on demand).
+struct SolveScratch {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
 // A solve (op = FFTPDE_POISSON / DIFFUSION / WAVE; for the wave, in2 is the
-// initial velocity and out2 the velocity output, either may be null).
+// initial velocity and out2 the velocity output, either may be null).  With
+// sc.p set, complex power-of-two solves keep their spectra in sc (batches
+// run in chunks of as many fields as it holds; EINVAL if not one) and never
+// allocate; other paths ignore it.
 int run_solve(Context* c, int dtype, int op, const void* in, const void* in2, void* out, void* out2, int nx, int ny,
-              int batch, double lx, double ly, double coef, double t, hipStream_t s);
+              int batch, double lx, double ly, double coef, double t, hipStream_t s, const SolveScratch& sc = SolveScratch());
 
 // 3D fields [nz][ny][nx]: transforms and the three solves (no velocity).
 int run_transform3d(Context* c, int dtype, bool inverse, const void* in, void* out, int nx, int ny, int nz, int batch,

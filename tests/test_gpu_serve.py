@@ -19,12 +19,12 @@ def fp():
     return fp
 
 
-def _expect(op, x, lx, ly, coef, t):
+def _expect(op, x, lx, ly, coef, t, threads=1):
     if op == POISSON:
-        return oracle.solve_poisson(x, lx, ly)
+        return oracle.solve_poisson(x, lx, ly, threads=threads)
     if op == DIFFUSION:
-        return oracle.solve_diffusion(x, lx, ly, coef, t)
-    return oracle.solve_wave(x, None, lx, ly, coef, t)[0]
+        return oracle.solve_diffusion(x, lx, ly, coef, t, threads=threads)
+    return oracle.solve_wave(x, None, lx, ly, coef, t, threads=threads)[0]
 
 
 @pytest.mark.parametrize("dt", ["c64", "c128"])
@@ -106,6 +106,69 @@ def test_results_alone_equal_results_in_the_mix(fp):
             got = to_host(out_m)
             err = oracle.rel_l2(got, ref) if t.kind == POISSON else rel_err_vs_input(got, ref, float(np.linalg.norm(x)))
             assert err <= tol("c64", t.nx, t.ny, 2)
+
+
+def test_results_alone_equal_results_in_the_mix_at_every_side(fp):
+    """The serving mix over its whole side range (2^6..2^12 on each axis),
+    with the largest requests added: 4096^2 wave, diffusion and Poisson
+    solves and 4096 x 64 / 64 x 4096 / 4096 x 128 rectangles (multi-tile,
+    chunked and tiled-intermediate paths; a Poisson solve's spectrum lives in
+    the server's pool).  Every request alone equals itself in the mix, bit
+    for bit, and a sample that includes the largest sides of each kind
+    matches the FP64 oracle."""
+    import torch
+    trace = list(W.serving_trace(seed=5, rate=2000.0, duration=0.1, log2_sides=(6, 12)))
+    big = [W.Request(0.0, WAVE, 4096, 4096, 37, 1e-4, 1.0), W.Request(0.0, DIFFUSION, 4096, 4096, 25, 1e-3, 0.01),
+           W.Request(0.0, POISSON, 4096, 4096, 1, 0.0, 0.0), W.Request(0.0, POISSON, 4096, 64, 1, 0.0, 0.0),
+           W.Request(0.0, WAVE, 64, 4096, 50, 1e-4, 1.0), W.Request(0.0, DIFFUSION, 4096, 128, 12, 1e-3, 0.01)]
+    for k, r in enumerate(big):   # spread through the mix
+        trace.insert(min(len(trace), 5 + 30 * k), r)
+    assert len(trace) >= 200 and max(t.nx for t in trace) == 4096 and min(t.nx for t in trace) == 64
+    say(f"server alone vs mix, sides 2^6..2^12: {len(trace)} requests")
+    inputs = {}
+
+    def inp_for(t):
+        key = (t.kind, t.nx, t.ny)
+        if key not in inputs:
+            g = torch.Generator(device="cuda:0").manual_seed(t.nx * 7919 + t.ny * 31 + t.kind)
+            inputs[key] = torch.randn((t.ny, t.nx), dtype=torch.complex64, device="cuda:0", generator=g)
+        return inputs[key]
+
+    def submit(srv, t):
+        out = torch.empty((t.ny, t.nx), dtype=torch.complex64, device="cuda:0")
+        diag = torch.zeros(3 * t.steps, dtype=torch.float64, device="cuda:0") if t.kind != POISSON else None
+        rid = srv.submit(t.kind, inp_for(t), out=out, diag=diag, steps=t.steps, dt=t.dt, coef=t.coef)
+        return rid, out, diag
+
+    with fp.Server(8 << 30, 16, 4) as srv:
+        mix = [submit(srv, t) for t in trace]
+        for rid, _, _ in mix:
+            assert srv.wait(rid, 120)["status"] == 0
+        st = srv.stats()
+        assert st["hbm_high_water"] <= 8 << 30
+        say(f"  mix: p50 {st['p50_ms']:.2f} ms, p99 {st['p99_ms']:.2f} ms, high water {st['hbm_high_water'] >> 20} MiB")
+        for t, (rid_m, out_m, diag_m) in zip(trace, mix):
+            rid, out, diag = submit(srv, t)
+            assert srv.wait(rid, 60)["status"] == 0
+            assert torch.equal(out, out_m), (t.kind, t.nx, t.ny)
+            if diag is not None:
+                assert torch.equal(diag, diag_m), (t.kind, t.nx, t.ny)
+            srv.release(rid)
+            srv.release(rid_m)
+        # against the oracle: the largest request of each kind, the added
+        # rectangles and a few of the trace
+        by_size = sorted(range(len(trace)), key=lambda i: trace[i].nx * trace[i].ny)
+        sample = {max((i for i in by_size if trace[i].kind == k), key=lambda i: trace[i].nx * trace[i].ny)
+                  for k in (POISSON, DIFFUSION, WAVE)}
+        sample |= {i for i, t in enumerate(trace) if t in big} | set(range(0, len(trace), 37))
+        for i in sorted(sample):
+            t, (_, out_m, _) = trace[i], mix[i]
+            say(f"  oracle {t.kind} {t.nx}x{t.ny} steps {t.steps}")
+            x = to_host(inp_for(t))
+            ref = _expect(t.kind, x, 1.0, 1.0, t.coef, t.steps * t.dt, threads=oracle.default_threads())
+            got = to_host(out_m)
+            err = oracle.rel_l2(got, ref) if t.kind == POISSON else rel_err_vs_input(got, ref, float(np.linalg.norm(x)))
+            assert err <= tol("c64", t.nx, t.ny, 2), (t.kind, t.nx, t.ny, err)
 
 
 def test_server_owned_output_and_small_budget_admission(fp):

@@ -133,10 +133,12 @@ def test_every_operator_completes_with_the_oracle_result(dev):
 
 
 def test_budget_admission_waits_and_is_first_come_first_served(dev):
-    """Budget for one 64x64 request at a time (in + out = 2 fields): B waits
-    while A runs; C (small) may not overtake B."""
-    big = 2 * field_bytes(64, 64)
-    with fp.Server.host(big + 4096, 8, dev) as srv:
+    """Budget for one 64x64 request at a time (in + out + the spectrum
+    between the passes = 3 fields): B waits while A runs; C (small) may not
+    overtake B, although it would fit."""
+    big = 3 * field_bytes(64, 64)
+    small = 3 * field_bytes(16, 16)
+    with fp.Server.host(big + small, 8, dev) as srv:
         outs = [np.zeros((64, 64), np.complex128) for _ in range(2)] + [np.zeros((16, 16), np.complex128)]
         ra, xa = _req(dev, POISSON, 64, 64, out=outs[0], seed=1)
         rb, xb = _req(dev, POISSON, 64, 64, out=outs[1], seed=2)
@@ -156,7 +158,7 @@ def test_budget_admission_waits_and_is_first_come_first_served(dev):
             assert srv.wait(rid, 20)["status"] == 0
         ta, tb, tc = (srv.poll(r)["t_admit"] for r in (a, b, c))
         assert ta <= tb <= tc
-        assert srv.stats()["hbm_high_water"] <= big + 4096
+        assert srv.stats()["hbm_high_water"] <= big + small
 
 
 def test_slots_bound_concurrency(dev):
@@ -245,7 +247,7 @@ def test_server_owned_outputs_come_from_the_pool_and_coalesce(dev):
     quarter-budget requests, released in an interleaved order, leave a pool
     that must coalesce for a request that needs all of it."""
     fb = field_bytes(32, 32)
-    with fp.Server.host(4 * 2 * fb, 4, dev) as srv:   # each request: in + server-owned out
+    with fp.Server.host(4 * 3 * fb, 4, dev) as srv:   # each request: in + scratch + server-owned out
         ids, xs = [], []
         for k in range(4):
             r, x = _req(dev, POISSON, 32, 32, seed=10 + k)
@@ -260,7 +262,7 @@ def test_server_owned_outputs_come_from_the_pool_and_coalesce(dev):
         for k in (1, 3, 0, 2):
             srv.release(ids[k])
         assert srv.stats()["hbm_in_use"] == 0
-        # one request with in + out = the whole budget needs the coalesced pool
+        # one request with in + scratch + out = the whole budget needs the coalesced pool
         r, x = _req(dev, POISSON, 64, 64, seed=20)
         rid = srv.submit_raw(r)
         assert srv.wait(rid, 20)["status"] == 0
