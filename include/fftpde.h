@@ -259,6 +259,27 @@ int solve_wave(fftpde_ctx *ctx, const void *u0, const void *v0, void *u, void *v
                int batch, double lx, double ly, double c, double t, int dtype,
                fftpde_stream stream);
 
+/* ---- a solve that allocates nothing --------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * solve_wave_noalloc: solve_wave (same arguments, meaning and results, bit
+ *   for bit) on complex fields (FFTPDE_C64 / FFTPDE_C128) whose sides are
+ *   powers of two, with the spectrum between its passes kept in a fixed
+ *   device array of FFTPDE_NOALLOC_SCRATCH_BYTES that the library holds on
+ *   every GPU it runs on until the process ends, instead of the context's
+ *   workspace; it calls no hipMalloc or hipFree.  Batches run in chunks of
+ *   as many fields as the array holds.  A side or dtype that solve_wave takes
+ *   but this does not, or a field whose spectrum (two with a velocity input
+ *   or output) exceeds the array, is rejected with FFTPDE_EINVAL before any
+ *   work is enqueued (fftpde_last_error says which); FFTPDE_EDEVICE if the
+ *   array's address could not be found at fftpde_create.  Every call on one
+ *   GPU uses the same array: calls that overlap in time on one GPU (other
+ *   streams, other contexts or threads) race and must be serialised by the
+ *   caller. */
+#define FFTPDE_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int solve_wave_noalloc(fftpde_ctx *ctx, const void *u0, const void *v0, void *u, void *v, int nx, int ny,
+                       int batch, double lx, double ly, double c, double t, int dtype, fftpde_stream stream);
+
 /* ---- sources constant in time ------------------------------------------
  * solve_diffusion_source: u(t) for u_t = kappa lap(u) + s, u(0) = f, with s
  *   independent of t (Sec. III.B, Eq. (DiffusionIVPFS) with diffusivity

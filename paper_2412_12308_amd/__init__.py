@@ -122,6 +122,7 @@ def _declare(L):
     L.solve_poisson.argtypes = [vp, vp, vp, i, i, i, d, d, i, vp]
     L.solve_diffusion.argtypes = [vp, vp, vp, i, i, i, d, d, d, d, i, vp]
     L.solve_wave.argtypes = [vp, vp, vp, vp, vp, i, i, i, d, d, d, d, i, vp]
+    L.solve_wave_noalloc.argtypes = [vp, vp, vp, vp, vp, i, i, i, d, d, d, d, i, vp]
     L.solve_diffusion_source.argtypes = [vp, vp, vp, vp, i, i, i, d, d, d, d, i, vp]
     L.solve_wave_source.argtypes = [vp, vp, vp, vp, vp, vp, i, i, i, d, d, d, d, i, vp]
     L.fft3d_forward.argtypes = [vp, vp, vp, i, i, i, i, i, vp]
@@ -170,7 +171,7 @@ def _declare(L):
               "fftpde_batch_create", "fftpde_batch_run", "fftpde_batch_status", "fftpde_batch_info",
               "fftpde_batch_destroy", "fftpde_plan_small", "fftpde_plan_tiled", "fftpde_plan_chunk", "fftpde_evolve_create", "fftpde_evolve_step", "fftpde_evolve_destroy", "fftpde_autotune", "fftpde_plan_save", "fftpde_plan_load", "fftpde_plan_variants",
               "fftpde_plan_select", "fftpde_profile", "fftpde_profile_read", "fftpde_create", "fftpde_destroy", "fft2d_forward", "fft2d_inverse", "fft2d_r2c", "fft2d_c2r", "solve_poisson",
-              "solve_diffusion", "solve_wave", "solve_diffusion_source", "solve_wave_source", "fftpde_wave_rk4",
+              "solve_diffusion", "solve_wave", "solve_wave_noalloc", "solve_diffusion_source", "solve_wave_source", "fftpde_wave_rk4",
               "fft3d_forward", "fft3d_inverse", "solve_poisson_3d", "solve_diffusion_3d", "solve_wave_3d"):
         getattr(L, f).restype = i
 
@@ -438,6 +439,25 @@ def solve_wave(u0, v0=None, c: float = 1.0, t: float = 0.0, lx: float = 1.0, ly:
     _check(lib().solve_wave(context(u0.device.index), _ptr(u0), _ptr(v0), _ptr(out), _ptr(v_out),
                             nx, ny, batch, float(lx), float(ly), float(c), float(t), dt,
                             _stream(u0)), "solve_wave")
+    return out, v_out
+
+
+def solve_wave_noalloc(u0, v0=None, c: float = 1.0, t: float = 0.0, lx: float = 1.0, ly: float = 1.0,
+                       out=None, v_out=None, want_v: bool = False) -> Tuple:
+    """solve_wave through the entry point that allocates no device memory (its
+    scratch is a fixed array of the library; complex fields, power-of-two
+    sides).  Pass `out` (and `v_out`) to keep the call free of allocations on
+    the Python side too."""
+    nx, ny, batch, dt = _field(u0, "u0")
+    if v0 is not None:
+        if _field(v0, "v0") != (nx, ny, batch, dt) or v0.device != u0.device:
+            raise ValueError("v0 must match u0")
+    out = _like(u0, out)
+    if want_v or v_out is not None:
+        v_out = _like(u0, v_out, "v_out")
+    _check(lib().solve_wave_noalloc(context(u0.device.index), _ptr(u0), _ptr(v0), _ptr(out), _ptr(v_out),
+                                    nx, ny, batch, float(lx), float(ly), float(c), float(t), dt,
+                                    _stream(u0)), "solve_wave_noalloc")
     return out, v_out
 
 

@@ -17,6 +17,7 @@
 #include "../../include/fftpde.h"
 #include "context.hpp"
 #include "kernels.hpp"
+#include "noalloc.hpp"
 #include "rk4.hpp"
 #include "solve.hpp"
 
@@ -252,6 +253,10 @@ int fftpde_create(fftpde_ctx** out, int device) {
     delete c;
     return FFTPDE_EDEVICE;
   }
+  // this device's copy of solve_wave_noalloc's fixed scratch (once per
+  // device); a failure here only disables that entry point, which then
+  // reports FFTPDE_EDEVICE
+  (void)noalloc_bind(device);
   *out = reinterpret_cast<fftpde_ctx*>(c);
   return FFTPDE_OK;
 }
@@ -695,6 +700,39 @@ int fftpde_wave_rk4(fftpde_ctx* ctx, const fftpde_orbit_source* src, const void*
   const OrbitSource os{src->amplitude, src->sigma, src->radius, src->omega, src->gamma, src->cx, src->cy};
   return run_wave_rk4(c, dtype, os, f, g0, u, v, nx, ny, batch, x0, y0, lx, ly, c_speed, t0, dt, steps,
                       static_cast<hipStream_t>(stream));
+}
+
+int solve_wave_noalloc(fftpde_ctx* ctx, const void* u0, const void* v0, void* u, void* v, int nx, int ny, int batch,
+                       double lx, double ly, double c_speed, double t, int dtype, fftpde_stream stream) {
+  int rc = check_common(ctx, nx, ny, batch, dtype);
+  if (rc == FFTPDE_OK) rc = check_field(u0, dtype);
+  if (rc == FFTPDE_OK) rc = check_field(u, dtype);
+  if (rc == FFTPDE_OK && v0) rc = check_field(v0, dtype);
+  if (rc == FFTPDE_OK && v) rc = check_field(v, dtype);
+  if (rc == FFTPDE_OK && !(finite_pos(lx) && finite_pos(ly))) rc = FFTPDE_EINVAL;
+  if (rc == FFTPDE_OK && !(std::isfinite(c_speed) && c_speed >= 0.0 && std::isfinite(t))) rc = FFTPDE_EINVAL;
+  if (rc == FFTPDE_OK && v && (v == u || v == u0)) rc = FFTPDE_EINVAL;
+  if (rc == FFTPDE_OK && v0 && (v0 == u)) rc = FFTPDE_EINVAL;
+  if (rc != FFTPDE_OK) return rc;
+  Context* c = reinterpret_cast<Context*>(ctx);
+  DeviceGuard g(c->device);
+  SolveScratch sc;
+  sc.p = noalloc_scratch(c->device);
+  sc.bytes = noalloc_scratch_bytes();
+  if (!sc.p) {
+    std::snprintf(g_last_error, sizeof(g_last_error), "solve_wave_noalloc: no static scratch on device %d",
+                  c->device);
+    return FFTPDE_EDEVICE;
+  }
+  const size_t need = solve_scratch_per_field(c, dtype, FFTPDE_WAVE, nx, ny, v0 != nullptr, v != nullptr);
+  if (need > sc.bytes) {
+    std::snprintf(g_last_error, sizeof(g_last_error),
+                  "solve_wave_noalloc: one %dx%d field needs %zu bytes of scratch, more than the %zu-byte array",
+                  nx, ny, need, sc.bytes);
+    return FFTPDE_EINVAL;
+  }
+  return run_solve(c, dtype, FFTPDE_WAVE, u0, v0, u, v, nx, ny, batch, lx, ly, c_speed, t,
+                   static_cast<hipStream_t>(stream), sc);
 }
 
 int solve_wave(fftpde_ctx* ctx, const void* u0, const void* v0, void* u, void* v, int nx, int ny, int batch,

@@ -560,6 +560,26 @@ int run_half_transform(Context* c, int dtype, bool inverse, const void* in, void
                              : half_transform<double>(c, inverse, in, out, nx, ny, batch, s);
 }
 
+size_t solve_scratch_per_field(Context* c, int dtype, int op, int nx, int ny, bool v0, bool v) {
+  const int lx = ilog2(nx), ly = ilog2(ny);
+  const size_t field = (dtype == FFTPDE_C64 ? 8 : 16) * (size_t)nx * ny;
+  const bool two = op == FFTPDE_WAVE && (v0 || v);
+  if (!two && c->small_variant(dtype, lx, ly)) return 0;  // one launch in LDS
+  const ColVariant* cv = c->col_variant(dtype, ly, two ? 2 : 1);
+  const int tiled_bytes = c->tiled_bytes_for(dtype, lx, ly);
+  int lt = -1;
+  if (tiled_bytes > 0 && cv) {
+    const int b = dtype == FFTPDE_C64 ? 8 : 16;
+    int bt = 0;
+    while (b << (bt + 1) <= tiled_bytes) bt++;
+    lt = bt > cv->logt ? bt : cv->logt;
+    if (lt >= lx) lt = -1;
+  }
+  if (!two) return lt >= 0 ? field : 0;
+  if (lt >= 0) return 2 * field;
+  return (v0 && !v) ? field : 0;
+}
+
 int run_solve(Context* c, int dtype, int op, const void* in, const void* in2, void* out, void* out2, int nx, int ny,
               int batch, double lx, double ly, double coef, double t, hipStream_t s, const SolveScratch& sc) {
   const int sop = op == FFTPDE_POISSON ? kSymPoisson : op == FFTPDE_DIFFUSION ? kSymDiffusion : kSymWave;

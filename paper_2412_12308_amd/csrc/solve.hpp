@@ -67,6 +67,10 @@ struct SolveScratch {
 // allocate; other paths ignore it.
 int run_solve(Context* c, int dtype, int op, const void* in, const void* in2, void* out, void* out2, int nx, int ny,
               int batch, double lx, double ly, double coef, double t, hipStream_t s, const SolveScratch& sc = SolveScratch());
+// Scratch bytes per field of a chunk that run_solve needs for a complex
+// power-of-two solve (v0 / v: the wave's velocity input / output given); 0
+// when the spectrum stays in the output or the solve runs in one launch.
+size_t solve_scratch_per_field(Context* c, int dtype, int op, int nx, int ny, bool v0, bool v);
 
 // 3D fields [nz][ny][nx]: transforms and the three solves (no velocity).
 int run_transform3d(Context* c, int dtype, bool inverse, const void* in, void* out, int nx, int ny, int nz, int batch,
