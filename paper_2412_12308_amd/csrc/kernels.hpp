@@ -256,6 +256,34 @@ __device__ __forceinline__ double sqrt_fp64_ranged(double v) {
   return fma(0.5 * yd, fma(-s, s, v), s);
 }
 
+// cos(pi r) for |r| <= 1/2 in FP64: the same series through u^11; the first
+// omitted term is below (pi/2)^24 / 24! < 1e-19.
+__device__ __forceinline__ double cospi_half_fp64(double r) {
+  const double u = r * r;
+  double p = cospi_taylor(11);
+  p = fma(p, u, cospi_taylor(10));
+  p = fma(p, u, cospi_taylor(9));
+  p = fma(p, u, cospi_taylor(8));
+  p = fma(p, u, cospi_taylor(7));
+  p = fma(p, u, cospi_taylor(6));
+  p = fma(p, u, cospi_taylor(5));
+  p = fma(p, u, cospi_taylor(4));
+  p = fma(p, u, cospi_taylor(3));
+  p = fma(p, u, cospi_taylor(2));
+  p = fma(p, u, cospi_taylor(1));
+  return fma(p, u, 1.0);
+}
+
+// sqrt of v in [1e-30, 1e36] (or 0) to FP64 rounding: sqrt_fp64_ranged's
+// step taken twice (the second leaves an error near 1e-21 before rounding).
+__device__ __forceinline__ double sqrt_fp64_ranged2(double v) {
+  const float y = __builtin_amdgcn_rsqf(fmaxf(float(v), 1e-30f));
+  const double hy = 0.5 * double(y);
+  double s = v * double(y);
+  s = fma(hy, fma(-s, s, v), s);
+  return fma(hy, fma(-s, s, v), s);
+}
+
 // cos(pi h) for FP64 h >= 0 in FP32: h is reduced exactly to r in [-1, 1]
 // (h minus an even integer), then to f = r - m in [-1/2, 1/2] with m in
 // {-1, 0, 1}; cos(pi r) = (-1)^m cos(pi f).
@@ -263,6 +291,13 @@ __device__ __forceinline__ float cospi_reduced(double h) {
   const double r = fma(-2.0, rint(0.5 * h), h);
   const double m = rint(r);
   const float c = cospi_half(float(r - m));
+  return m != 0.0 ? -c : c;
+}
+// the same in FP64
+__device__ __forceinline__ double cospi_reduced_fp64(double h) {
+  const double r = fma(-2.0, rint(0.5 * h), h);
+  const double m = rint(r);
+  const double c = cospi_half_fp64(r - m);
   return m != 0.0 ? -c : c;
 }
 
@@ -304,14 +339,14 @@ struct Symbol<T, kSymWave> {
     }
   }
   // The same at the signed index b' = j + dd (j >= 0; dd a compile-time
-  // offset of the caller's unrolled loop, so hy j is formed once per j); for
-  // FP32 only where `fast` holds (split_ok).
-  __device__ __forceinline__ bool split_ok() const { return sizeof(T) == 8 || fast; }
+  // offset of the caller's unrolled loop, so hy j is formed once per j), only
+  // where `fast` holds (split_ok): the square root starts from an FP32 seed.
+  __device__ __forceinline__ bool split_ok() const { return fast; }
   __device__ __forceinline__ T split(int j, int dd) const {
     const double hyb = fma(hy, double(dd), hy * double(j));
     const double h2 = fma(hyb, hyb, hx2);
     if constexpr (sizeof(T) == 4) return scale * cospi_reduced(sqrt_fp64_ranged(h2));
-    else return scale * cospi(sqrt(h2));
+    else return scale * cospi_reduced_fp64(sqrt_fp64_ranged2(h2));
   }
 };
 
