@@ -232,6 +232,11 @@ struct RowMap {
     j = g & ((1 << lm) - 1);
     line = g >> lm;
   }
+  // butterfly slot q of thread tid (g = tid + TH q)
+  template <int TH>
+  __device__ __forceinline__ static void split_q(int tid, int q, int lm, int& line, int& j) {
+    split(tid + TH * q, lm, line, j);
+  }
   __device__ __forceinline__ static int lds(int line, int n) { return line * kStride + n + (n >> LP); }
 };
 
@@ -249,7 +254,35 @@ struct ColMap {
     j = g >> LOGT;
     (void)lm;
   }
+  template <int TH>
+  __device__ __forceinline__ static void split_q(int tid, int q, int lm, int& line, int& j) {
+    split(tid + TH * q, lm, line, j);
+  }
   __device__ __forceinline__ static int lds(int line, int n) { return (n + (n >> LP)) * T + line; }
+};
+
+// Columns with mirror-paired butterflies: at the stages with 2^MLM
+// butterflies per line (two per thread), a thread's second butterfly is the
+// mirror of its first, j1 = M - j0 (M = 2^MLM), or M/2 where j0 = 0.  Its
+// positions j + t M (t < R = N/M) then hold the rows n and N - n (signed
+// indices b' and -b') together: (j0, t) and (j1, R - 1 - t), and for the
+// thread with j0 = 0, (0, t) with (0, R - t) and (M/2, t) with (M/2, R - 1 - t).
+// Any bijection of butterflies onto threads is a valid Stockham stage, so
+// the pairing only changes which thread does which butterfly.
+template <int LOGN, int LOGT, int LP, int MLM>
+struct ColMapMirror : ColMap<LOGN, LOGT, LP> {
+  template <int TH>
+  __device__ __forceinline__ static void split_q(int tid, int q, int lm, int& line, int& j) {
+    constexpr int T = 1 << LOGT;
+    line = tid & (T - 1);
+    j = (tid >> LOGT) + (TH >> LOGT) * q;
+    if (lm == MLM && q == 1) {
+      static_assert((TH >> LOGT) == (1 << (MLM - 1)) || MLM < 0, "two butterflies per thread at the mirrored stage");
+      constexpr int h = TH >> LOGT;
+      const int j0 = tid >> LOGT;
+      j = j0 == 0 ? h : 2 * h - j0;
+    }
+  }
 };
 
 // Affine padding: with P = 2^lp, stage s's writes (groups of R outputs at
@@ -344,7 +377,7 @@ struct Engine {
 #pragma unroll
     for (int q = 0; q < E / R; q++) {
       int line, j;
-      Map::split(tid + TH * q, LOGN - LR, line, j);
+      Map::template split_q<TH>(tid, q, LOGN - LR, line, j);
 #pragma unroll
       for (int t = 0; t < R; t++) f(q * R + t, line, j + t * M);
     }
@@ -369,7 +402,7 @@ struct Engine {
 #pragma unroll
     for (int q = 0; q < E / R; q++) {
       int line, j;
-      Map::split(tid + TH * q, LOGN - LR, line, j);
+      Map::template split_q<TH>(tid, q, LOGN - LR, line, j);
 #pragma unroll
       for (int t = 0; t < R; t++) f(q * R + t, line, j, t * M);
     }
@@ -405,7 +438,7 @@ struct Engine {
 #pragma unroll
       for (int q = 0; q < E / R; q++) {
         int line, j;
-        Map::split(tid + TH * q, LOGN - LR, line, j);
+        Map::template split_q<TH>(tid, q, LOGN - LR, line, j);
         const int k = j & (NS - 1);
         const int o = ((j - k) << LR) + k;
         if constexpr (kAffine) {
@@ -422,7 +455,7 @@ struct Engine {
 #pragma unroll
       for (int q = 0; q < E / R2; q++) {
         int line, j;
-        Map::split(tid + TH * q, LOGN - LR2, line, j);
+        Map::template split_q<TH>(tid, q, LOGN - LR2, line, j);
         if constexpr (kAffine) {
           const Word* b = lds + Map::lds(line, j);
 #pragma unroll
@@ -501,7 +534,7 @@ struct Engine {
 #pragma unroll
       for (int q = 0; q < E / R; q++) {
         int line, j;
-        Map::split(tid + TH * q, LOGN - LR, line, j);
+        Map::template split_q<TH>(tid, q, LOGN - LR, line, j);
         const cx<T>* b = tws + stw_off<S>() + (j & (NS - 1));
         if constexpr (TWG > 1) {
           // lane c of a group loads t = TWG u + c + 1 (the group's last lane
@@ -530,7 +563,7 @@ struct Engine {
 #pragma unroll
       for (int q = 0; q < E / R; q++) {
         int line, j;
-        Map::split(tid + TH * q, LOGN - LR, line, j);
+        Map::template split_q<TH>(tid, q, LOGN - LR, line, j);
         const int k = j & (NS - 1);
 #pragma unroll
         for (int t = 1; t < R; t++) w[off + q * (R - 1) + t - 1] = tw[(t * k) << (kTwLog - LNS - LR)];
@@ -569,7 +602,7 @@ struct Engine {
       if constexpr (NS > 1) {
         if constexpr (SRC == TwSrc::lds) {
           int line, j;
-          Map::split(tid + TH * q, LOGN - LR, line, j);
+          Map::template split_q<TH>(tid, q, LOGN - LR, line, j);
           const int k = j & (NS - 1);
 #pragma unroll
           for (int t = 1; t < R; t++) v[t] = cmul(v[t], twl[(t * k) << (LOGN - LNS - LR)]);

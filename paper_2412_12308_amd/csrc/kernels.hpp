@@ -678,8 +678,18 @@ __global__ void __launch_bounds__(TH) col_kernel(ColArgs<T> a) {
   // kTwStageGrp: the T consecutive lanes of a butterfly index share twiddles
   static_assert(TWM != kTwStageGrp || (kOneCol && (TT == 2 || TT == 4)), "shared twiddles: tiles of 2 or 4 columns");
   constexpr int kTwg = TWM == kTwStageGrp ? TT : 1;
-  using FMap = ColMap<LOGN, LOGT, plan_pad(LOGN, MAXLR, false)>;
-  using IMap = ColMap<LOGN, LOGT, plan_pad(LOGN, MAXLR, true)>;
+  // The symbols are even in the signed row index b'.  Where the inverse's
+  // first stage gives each thread two butterflies, the fused one-field pass
+  // pairs them as mirrors (ColMapMirror), so that each thread evaluates the
+  // symbol once for rows b' and -b' (R0 + 1 evaluations for 2 R0 values).
+  constexpr int kLr0 = plan_lr(LOGN, MAXLR, 0, true);
+  constexpr int kR0 = 1 << kLr0;
+  constexpr bool kMirror = FUSED && NF == 1 && kOneCol && LOGN >= 3 && E == 2 * kR0;
+  constexpr int kMlm = kMirror ? LOGN - kLr0 : -1;
+  using FMap = typename std::conditional<kMirror, ColMapMirror<LOGN, LOGT, plan_pad(LOGN, MAXLR, false), kMlm>,
+                                         ColMap<LOGN, LOGT, plan_pad(LOGN, MAXLR, false)>>::type;
+  using IMap = typename std::conditional<kMirror, ColMapMirror<LOGN, LOGT, plan_pad(LOGN, MAXLR, true), kMlm>,
+                                         ColMap<LOGN, LOGT, plan_pad(LOGN, MAXLR, true)>>::type;
   using Fwd = Engine<T, LOGN, E, TH, MAXLR, false, FMap, SPLIT, kTwg>;
   using Inv = Engine<T, LOGN, E, TH, MAXLR, true, IMap, SPLIT, kTwg>;
   constexpr int kLdsWords = Fwd::kLdsWords > Inv::kLdsWords ? Fwd::kLdsWords : Inv::kLdsWords;
@@ -801,7 +811,34 @@ __global__ void __launch_bounds__(TH) col_kernel(ColArgs<T> a) {
       const Symbol<T, OP> sym(a.sym, int((col0 + (tid & (TT - 1))) & fmask));
       // (the kernels for all modes keep the general form: the split one's
       // registers would cost them a resident workgroup)
-      if (FUSED && sym.split_ok()) {
+      if (kMirror && sym.split_ok()) {
+        // register q R0 + t holds row j_q + t M (M = N / R0) of this
+        // thread's column, j_1 the mirror of j_0 (ColMapMirror).  Slot e of
+        // the R0 + 1 evaluations: rows j0 + e M; on the thread with j0 = 0,
+        // rows e M for e <= R0/2 and then M/2 + (e - R0/2 - 1) M.
+        constexpr int M = N / kR0, H = M / 2;
+        auto sdd = [](int d) { return d >= (N >> 1) ? d - N : d; };
+        const int j0 = tid >> LOGT;
+        const bool sp = j0 == 0;
+        T m[kR0 + 1];
+#pragma unroll
+        for (int e = 0; e <= kR0; e++) {
+          if (e <= kR0 / 2) {
+            m[e] = sym.split(j0, sdd(e * M));
+          } else {
+            const int es = e - kR0 / 2 - 1;
+            m[e] = sym.split(sp ? H : j0, sp ? sdd(es * M) : sdd((e < kR0 ? e : 0) * M));
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < kR0; t++) {
+          const T m0 = (t <= kR0 / 2) ? m[t] : (sp ? m[kR0 - t] : m[t]);
+          const int tt = kR0 - 1 - t;
+          const T m1 = sp ? m[kR0 / 2 + 1 + (t < tt ? t : tt)] : m[tt];
+          v[t] = {v[t].re * m0, -v[t].im * m0};
+          v[kR0 + t] = {v[kR0 + t].re * m1, -v[kR0 + t].im * m1};
+        }
+      } else if (FUSED && sym.split_ok()) {
         // position n = j + d of the inverse's first stage, d = t N/R a
         // compile-time multiple of N/R: its signed index is j + d, or
         // j + d - N once d reaches N/2 (N/2 is a multiple of N/R and j < N/R)
