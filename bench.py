@@ -16,8 +16,9 @@ timed beside them: two real fields per complex transform, half the bytes per
 solve (`real_fields`; 2B FP32 / B FP64 fields).
 
 Beside it: the batched uneven launch (1024 Poisson solves, sides drawn from
-32..1024, one persistent kernel replayed from a HIP graph, FP32 and FP64,
-and the FP64 solves one at a time), and the request server under an open
+32..1024, one persistent kernel replayed from a HIP graph, FP32 with its
+radix plans tuned by fftpde_batch_tune and FP64, and the FP64 solves one at
+a time), and the request server under an open
 loop of Poisson arrivals at 2000 requests/s (50 % Poisson, 30 % diffusion
 with 10..200 steps, 20 % wave with 10..500 steps, sides log-uniform in
 2^6..2^12, 64 GiB budget, per-step diagnostics from resident spectra):
@@ -388,21 +389,33 @@ def batch_leg(fp, torch, reps: int, warmup: int, check: bool):
     for name, tdt in (("fp32", torch.complex64), ("fp64", torch.complex128)):
         ins = [torch.from_numpy(ms.field).to(tdt).cuda() for ms in srcs]
         b = fp.Batch([dict(op=0, inp=x, lx=ms.lx, ly=ms.ly) for x, ms in zip(ins, srcs)])
-        for _ in range(warmup):
-            b.run()
-        torch.cuda.synchronize()
-        e0, e1 = ev(), ev()
-        e0.record()
-        for _ in range(reps):
-            b.run()
-        e1.record()
-        torch.cuda.synchronize()
-        b.status()
-        ms = e0.elapsed_time(e1) / reps
+
+        def timed():
+            for _ in range(warmup):
+                b.run()
+            torch.cuda.synchronize()
+            e0, e1 = ev(), ev()
+            e0.record()
+            for _ in range(reps):
+                b.run()
+            e1.record()
+            torch.cuda.synchronize()
+            b.status()
+            return e0.elapsed_time(e1) / reps
+
+        ms_default = timed()
+        ms = ms_default
+        d = b.describe()
+        if name == "fp32":  # FP64 batches have one radix plan
+            d = b.tune(reps=10)
+            ms = timed()
         leg = {"ms_per_launch": round(ms, 4), "solves_per_s": round(len(srcs) / (ms * 1e-3), 1),
                "alg_gbs": round(b.bytes / (ms * 1e-3) / 1e9, 1),
                "alg_frac": round(b.bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-               "tiles": b.items, "workgroups": b.grid, "alg_bytes": b.bytes}
+               "default_plan_ms_per_launch": round(ms_default, 4),
+               "plans": {f"{c['kind']}{1 << c['logn']}": c["max_radix"] for c in d["classes"]},
+               "single_pass": d["single_pass"],
+               "items": b.items, "workgroups": b.grid, "alg_bytes": b.bytes}
         if check:
             errs = []
             for i in (int(np.argmax([m.nx * m.ny for m in srcs])), 0, 511):

@@ -397,8 +397,19 @@ int fftpde_evolve_destroy(fftpde_evolve *ev);
  * column pass (forward y FFT, symbol, inverse y FFT) and an inverse row pass,
  * cut into tiles of 8192 (FP32) / 4096 (FP64) points; workgroups take tiles
  * from one queue and a job's column tiles start as soon as its own row tiles
- * are done.  Each job is computed exactly as the single-field solves above
- * define it (same symbols, same FP64 phases and exponents).
+ * are done.  A job whose field fits one tile (nx*ny <= 8192 FP32 / 4096
+ * FP64) is instead solved in one pass, all five steps in LDS, up to
+ * tile/(nx*ny) jobs of one shape and operator per queue item (one HBM read
+ * and one write per field).  Each job is computed exactly as the
+ * single-field solves above define it (same symbols, same FP64 phases and
+ * exponents).  (These are the plan / launch / destroy calls of a batched
+ * interface under the names create / run / destroy, plus status, info,
+ * plan, tune and describe.)
+ *
+ * Radix plans: in FP32 the row tiles of each log2 nx and the column tiles of
+ * each log2 ny (a "class") run one of two compiled plans: 0 = stages of
+ * radix up to 8 (default), 1 = up to 16.  Both compute the same transforms;
+ * results differ by rounding only.  FP64 batches have plan 0 only.
  *
  * fftpde_job: op = FFTPDE_POISSON (coef, t unused), FFTPDE_DIFFUSION
  *   (coef = kappa >= 0, t >= 0) or FFTPDE_WAVE (coef = c >= 0, t finite,
@@ -418,9 +429,30 @@ int fftpde_evolve_destroy(fftpde_evolve *ev);
  * fftpde_batch_status: waits for `stream`, then returns FFTPDE_OK, or
  *   FFTPDE_ETIMEOUT if a tile's wait for its job's previous step gave up
  *   (about a second; results of that run are then invalid).
- * fftpde_batch_info: number of tiles in the queue, workgroups launched and
- *   algorithmic HBM bytes of one run (6 field passes per job); NULL outputs
- *   are skipped.
+ * fftpde_batch_info: number of items in the queue, workgroups launched and
+ *   algorithmic HBM bytes of one run (6 field passes per three-pass job, 2
+ *   per single-pass job); NULL outputs are skipped.
+ * fftpde_batch_plan: sets the radix plan (0 or 1) of one class: kind 0 =
+ *   row tiles of log2 length `logn`, 1 = column tiles; logn in [4, 12].
+ *   Applies to later runs, graph replays included (the plan is written into
+ *   the queue's items in device memory).  Synchronous; the caller ensures
+ *   no run of the batch is in flight.  EINVAL for a bad class or plan (plan
+ *   1 on an FP64 batch).
+ * fftpde_batch_tune: times the batch (graph replays on `stream`, the best of
+ *   three groups of `reps` runs; reps < 1: 10) on the data its inputs hold,
+ *   then (FP32) flips the plan of each class present, most tiles first, and
+ *   keeps a flip if every job's output stays within a relative L2 distance
+ *   of 4e-6 * log2(max side) of the starting plan's output and the run got
+ *   faster.  Overwrites the outputs; allocates (and
+ *   frees) one copy of all outputs.  EINVAL for a batch with a job in place
+ *   (its input would change between runs); ETIMEOUT if a run's wait gave up
+ *   (the plan of the class then under test is restored).
+ * fftpde_batch_describe: a JSON object: dtype, jobs, items, grid, bytes,
+ *   single_pass {jobs, items}, classes [{kind "row"|"col", logn, tiles,
+ *   plan, max_radix}] and tune [{kind "start"|"row"|"col", logn, plan, us,
+ *   err, ok, kept}] (the last tuning's candidates, empty before one).
+ *   Writes at most cap bytes (NUL included) to buf (may be NULL); *need
+ *   (may be NULL) receives the full length + 1.  EINVAL if it was cut short.
  * fftpde_batch_destroy: frees the batch (waits for nothing: the caller
  *   ensures no run is still in flight); NULL ok. */
 typedef struct fftpde_job {
@@ -438,6 +470,9 @@ int fftpde_batch_create(fftpde_ctx *ctx, const fftpde_job *jobs, int njobs, int 
 int fftpde_batch_run(fftpde_batch *batch, int use_graph, fftpde_stream stream);
 int fftpde_batch_status(fftpde_batch *batch, fftpde_stream stream);
 int fftpde_batch_info(const fftpde_batch *batch, long long *items, int *grid, double *bytes);
+int fftpde_batch_plan(fftpde_batch *batch, int kind, int logn, int plan);
+int fftpde_batch_tune(fftpde_batch *batch, int reps, fftpde_stream stream);
+int fftpde_batch_describe(const fftpde_batch *batch, char *buf, size_t cap, size_t *need);
 int fftpde_batch_destroy(fftpde_batch *batch);
 
 /* ---- request server ------------------------------------------------------

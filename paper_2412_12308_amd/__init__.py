@@ -153,6 +153,9 @@ def _declare(L):
     L.fftpde_batch_status.argtypes = [vp, vp]
     L.fftpde_batch_info.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(i),
                                     ctypes.POINTER(d)]
+    L.fftpde_batch_plan.argtypes = [vp, i, i, i]
+    L.fftpde_batch_tune.argtypes = [vp, i, vp]
+    L.fftpde_batch_describe.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
     L.fftpde_batch_destroy.argtypes = [vp]
     ull, ll = ctypes.c_ulonglong, ctypes.c_longlong
     L.fftpde_server_create.argtypes = [vp, ll, i, i, ctypes.POINTER(vp)]
@@ -169,7 +172,7 @@ def _declare(L):
               "fftpde_server_wait", "fftpde_server_cancel", "fftpde_server_copy_out", "fftpde_server_release",
               "fftpde_server_stats", "fftpde_server_destroy",
               "fftpde_batch_create", "fftpde_batch_run", "fftpde_batch_status", "fftpde_batch_info",
-              "fftpde_batch_destroy", "fftpde_plan_small", "fftpde_plan_tiled", "fftpde_plan_chunk", "fftpde_evolve_create", "fftpde_evolve_step", "fftpde_evolve_destroy", "fftpde_autotune", "fftpde_plan_save", "fftpde_plan_load", "fftpde_plan_variants",
+              "fftpde_batch_plan", "fftpde_batch_tune", "fftpde_batch_describe", "fftpde_batch_destroy", "fftpde_plan_small", "fftpde_plan_tiled", "fftpde_plan_chunk", "fftpde_evolve_create", "fftpde_evolve_step", "fftpde_evolve_destroy", "fftpde_autotune", "fftpde_plan_save", "fftpde_plan_load", "fftpde_plan_variants",
               "fftpde_plan_select", "fftpde_profile", "fftpde_profile_read", "fftpde_create", "fftpde_destroy", "fft2d_forward", "fft2d_inverse", "fft2d_r2c", "fft2d_c2r", "solve_poisson",
               "solve_diffusion", "solve_wave", "solve_wave_noalloc", "solve_diffusion_source", "solve_wave_source", "fftpde_wave_rk4",
               "fft3d_forward", "fft3d_inverse", "solve_poisson_3d", "solve_diffusion_3d", "solve_wave_3d"):
@@ -686,6 +689,29 @@ class Batch:
         """Wait for the current stream; raise if a dependency wait timed out."""
         s = _torch().cuda.current_stream(self.device).cuda_stream
         _check(lib().fftpde_batch_status(self._h, s), "fftpde_batch_status")
+
+    def set_plan(self, kind: int, logn: int, plan: int):
+        """Radix plan of one class (kind 0 rows / 1 columns of log2 length
+        logn): 0 = radix up to 8, 1 = up to 16 (FP32) / 4 (FP64)."""
+        _torch().cuda.current_stream(self.device).synchronize()
+        _check(lib().fftpde_batch_plan(self._h, kind, logn, plan), "fftpde_batch_plan")
+
+    def tune(self, reps: int = 10):
+        """Time each class's other plan on the current inputs and keep the
+        faster within tolerance (fftpde_batch_tune); overwrites the outputs.
+        Returns describe()."""
+        s = _torch().cuda.current_stream(self.device).cuda_stream
+        _check(lib().fftpde_batch_tune(self._h, reps, s), "fftpde_batch_tune")
+        return self.describe()
+
+    def describe(self):
+        """Plans, single-pass items and the last tuning, as a dict."""
+        import json
+        need = ctypes.c_size_t(0)
+        _check(lib().fftpde_batch_describe(self._h, None, 0, ctypes.byref(need)), "fftpde_batch_describe")
+        buf = ctypes.create_string_buffer(need.value)
+        _check(lib().fftpde_batch_describe(self._h, buf, len(buf), ctypes.byref(need)), "fftpde_batch_describe")
+        return json.loads(buf.value.decode())
 
     def close(self):
         if self._h is not None and _lib is not None:
