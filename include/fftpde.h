@@ -158,8 +158,10 @@ int fftpde_plan_tiled(fftpde_ctx *ctx, int block_bytes);
  *   runs in chunks of about `bytes` of field data (at least one field), all
  *   three passes of a chunk before the next, so that the spectrum one pass
  *   writes is still in the GPU's 256 MiB Infinity Cache when the next pass
- *   reads it.  Default 256 MiB; 0 = the whole batch at once.  Results are
- *   bit-identical for every chunk size.  EINVAL for negative sizes. */
+ *   reads it.  Default 256 MiB; 0 = the whole batch at once.  Real fields
+ *   (solved in pairs) count their pair spectra twice, so a chunk holds half
+ *   as many pairs (not so the inverse half transform fft2d_c2r).  Results
+ *   are bit-identical for every chunk size.  EINVAL for negative sizes. */
 int fftpde_plan_chunk(fftpde_ctx *ctx, long long bytes);
 
 /* fftpde_autotune: for an (nx, ny, batch, dtype, op) solve (op one of

@@ -275,6 +275,22 @@ int small_pass(Context* c, const void* in, void* out, int nx, int ny, int batch,
   return FFTPDE_OK;
 }
 
+// Pairs of real fields per chunk.  For the solves and the forward half
+// transform the chunk size counts the real fields and their pair spectra
+// together, 2 x the spectra (at the 256 MiB default, 4 FP32 2048^2 pairs: 8
+// real fields).  With chunks of pair spectra alone (8 pairs) their column
+// pass ran 25 % slower than on complex fields of the same bytes, with the
+// same L2 traffic and hit rate; the half chunk runs the real FP32 solves 4 %
+// and the forward half transform 10 % faster.  The inverse half transform
+// keeps chunks of spectra alone (`halve` false): 9 % faster there.
+static long long pair_chunk(const Context* c, int dt, int lx, int ly, size_t pair_bytes, long long npairs,
+                            bool halve = true) {
+  const long long cb = c->chunk_bytes_for(dt, lx, ly);
+  const long long per = (halve ? 2 : 1) * (long long)pair_bytes;
+  const long long chunk = cb > 0 ? std::max<long long>(1, cb / per) : npairs;
+  return std::min<long long>(chunk, npairs);
+}
+
 // Real fields, two per complex transform.  The three symbols are real and
 // even in k, so a solve S maps real fields to real fields and is complex
 // linear: S(u1 + i u2) = S(u1) + i S(u2).  Fields 2p and 2p + 1 enter the
@@ -291,9 +307,7 @@ int solve_real_pairs(Context* c, const void* in, const void* in2, void* out, voi
   const long long pts = (long long)nx * ny;
   const size_t pair_bytes = sizeof(cx<T>) * (size_t)pts;  // one complex field per pair
   const long long npairs = (batch + 1) / 2;
-  const long long cb = c->chunk_bytes_for(dt, lx, ly);
-  long long chunk = cb > 0 ? std::max<long long>(1, cb / (long long)pair_bytes) : npairs;
-  chunk = std::min<long long>(chunk, npairs);
+  const long long chunk = pair_chunk(c, dt, lx, ly, pair_bytes, npairs);
   const int nf = (sym.op == kSymWave && (in2 || out2)) ? 2 : 1;
   const ColVariant* cv = c->col_variant(dt, ly, nf);
   if (!cv) return FFTPDE_EINVAL;
@@ -499,9 +513,7 @@ int half_transform(Context* c, bool inverse, const void* in, void* out, int nx, 
   const long long pts = (long long)nx * ny, hpts = (long long)(nx / 2 + 1) * ny;
   const size_t pair_bytes = sizeof(cx<T>) * (size_t)pts;
   const long long npairs = (batch + 1) / 2;
-  const long long cb = c->chunk_bytes_for(dt, lx, ly);
-  long long chunk = cb > 0 ? std::max<long long>(1, cb / (long long)pair_bytes) : npairs;
-  chunk = std::min<long long>(chunk, npairs);
+  const long long chunk = pair_chunk(c, dt, lx, ly, pair_bytes, npairs, !inverse);
   // the pair spectra in the column passes' tiled layout, as in the solves
   const ColVariant* cv = c->col_variant(dt, ly, 1);
   if (!cv) return FFTPDE_EINVAL;
