@@ -220,10 +220,16 @@ int fft2d_inverse(fftpde_ctx *ctx, const void *in, void *out, int nx, int ny, in
  *   spectrum from the symmetry, and the self-conjugate columns (a = 0, and
  *   a = nx/2 on even nx) replaced by (X[b][a] + conj(X[-b][a]))/2 (no change
  *   for half spectra of real fields).  Same dtypes and sides.
- * Both: in and out must not overlap (EINVAL).  Two real fields go through
- *   one complex transform (row pass with real loads or stores), their
- *   spectrum in the per-stream scratch; one more pass splits it into the
- *   two half spectra (or joins them). */
+ * Both: in and out must not overlap (EINVAL).  Powers of two with nx, ny
+ *   >= 16 (and nx ny >= 2^14 FP32 / 2^13 FP64), the real side aligned to a
+ *   complex element: each real row is read as a complex row of nx/2 points,
+ *   transformed and split into its half spectrum by the even/odd
+ *   combination of Sec. II.C (X[0] and X[nx/2] packed into one column), into
+ *   the per-stream scratch; the column pass writes the half spectra
+ *   (c2r: the same steps backwards).  Other shapes: two real fields go
+ *   through one complex transform, their spectrum in the per-stream
+ *   scratch; one more pass splits it into the two half spectra (or joins
+ *   them). */
 int fft2d_r2c(fftpde_ctx *ctx, const void *in, void *out, int nx, int ny, int batch, int dtype,
               fftpde_stream stream);
 int fft2d_c2r(fftpde_ctx *ctx, const void *in, void *out, int nx, int ny, int batch, int dtype,

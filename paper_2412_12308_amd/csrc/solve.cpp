@@ -4,10 +4,12 @@
 #include "solve.hpp"
 
 #include "diag.hpp"
+#include "halfrow.hpp"
 #include "halfspec.hpp"
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 
 #include "../../include/fftpde.h"
 
@@ -503,11 +505,82 @@ int run_transform(Context* c, int dtype, bool inverse, const void* in, void* out
                              : transform<double>(c, in, out, nx, ny, batch, inverse, s);
 }
 
+// fft2d_r2c / fft2d_c2r through the half-row passes (halfrow.hpp): each
+// real row transformed as a complex row of half the length and split into
+// its half spectrum (or joined back), one work field of M x ny complex
+// points per real field between the row and the column pass.  Chunks of
+// fields count the real fields and the work fields together.
+template <typename T>
+int half_rows(Context* c, bool inverse, const void* in, void* out, int nx, int ny, int batch, hipStream_t s) {
+  const int dt = sizeof(T) == 4 ? FFTPDE_C64 : FFTPDE_C128;
+  const int fp64 = sizeof(T) == 8;
+  const int lx = ilog2(nx), ly = ilog2(ny), lm = lx - 1;
+  const size_t rbytes = sizeof(T) * (size_t)nx * ny;                   // one real field = one work field
+  const size_t hbytes = sizeof(cx<T>) * (size_t)(nx / 2 + 1) * ny;    // one half spectrum
+  const long long cb = c->chunk_bytes_for(dt, lx, ly);
+  long long chunk = cb > 0 ? std::max<long long>(1, cb / (2 * (long long)rbytes)) : batch;
+  chunk = std::min<long long>(chunk, batch);
+  // work layout: blocks of tiled_bytes per row, at least one column tile wide
+  int lt = lm;
+  const int tiled_bytes = c->tiled_bytes_for(dt, lx, ly);
+  if (tiled_bytes > 0) {
+    int bt = 0;
+    while ((int)sizeof(cx<T>) << (bt + 1) <= tiled_bytes) bt++;
+    lt = std::min(lm, std::max(bt, halfrow_col_logt(fp64, ly)));
+  }
+  void* w = nullptr;
+  const int rcw = c->workspace(rbytes * (size_t)chunk, s, &w);
+  if (rcw != FFTPDE_OK) return rcw;
+  HalfRowArgs<T> a{};
+  a.work = static_cast<cx<T>*>(w);
+  a.tw = twiddles<T>(c);
+  a.stw = c->stage_tw<T>(ly, halfrow_col_maxlr(fp64), false);
+  a.lognx = lx;
+  a.logny = ly;
+  a.lt = lt;
+  a.scale = T(1.0 / ((double)(nx / 2) * (double)ny));
+  const char* names[4] = {sizeof(T) == 4 ? "r2c_rows_float" : "r2c_rows_double",
+                          sizeof(T) == 4 ? "r2c_cols_float" : "r2c_cols_double",
+                          sizeof(T) == 4 ? "c2r_cols_float" : "c2r_cols_double",
+                          sizeof(T) == 4 ? "c2r_rows_float" : "c2r_rows_double"};
+  for (long long f0 = 0; f0 < batch; f0 += chunk) {
+    a.fields = std::min<long long>(chunk, batch - f0);
+    const double rb = (double)rbytes * a.fields, hb = (double)hbytes * a.fields;
+    auto step = [&](int k, double bytes, hipError_t (*fn)(const HalfRowArgs<T>&, hipStream_t)) {
+      const hipError_t e = timed_launch(c, names[k], bytes, s, [&] { return fn(a, s); });
+      if (e != hipSuccess) {
+        set_last_error(names[k], e);
+        return FFTPDE_EDEVICE;
+      }
+      return FFTPDE_OK;
+    };
+    int rc;
+    if (!inverse) {
+      a.rin = static_cast<const T*>(at<T>(in, rbytes * (size_t)f0));
+      a.hout = static_cast<cx<T>*>(at<T>(out, hbytes * (size_t)f0));
+      rc = step(0, 2 * rb, launch_r2c_rows<T>);
+      if (rc == FFTPDE_OK) rc = step(1, rb + hb, launch_r2c_cols<T>);
+    } else {
+      a.hin = static_cast<const cx<T>*>(at<T>(in, hbytes * (size_t)f0));
+      a.rout = static_cast<T*>(at<T>(out, rbytes * (size_t)f0));
+      rc = step(2, hb + rb, launch_c2r_cols<T>);
+      if (rc == FFTPDE_OK) rc = step(3, 2 * rb, launch_c2r_rows<T>);
+    }
+    if (rc != FFTPDE_OK) return rc;
+  }
+  return FFTPDE_OK;
+}
+
 // fft2d_r2c / fft2d_c2r: real fields in pairs, each pair one complex field
 // (row pass with real loads or stores), its spectrum in the per-stream
 // scratch, and the half spectra split off (forward) or joined (inverse).
 template <typename T>
 int half_transform(Context* c, bool inverse, const void* in, void* out, int nx, int ny, int batch, hipStream_t s) {
+  // the real side is read (or written) as complex points: it must be aligned like them
+  const void* real = inverse ? out : in;
+  if (halfrow_supported(sizeof(T) == 8, ilog2(nx), ilog2(ny)) &&
+      reinterpret_cast<uintptr_t>(real) % sizeof(cx<T>) == 0)
+    return half_rows<T>(c, inverse, in, out, nx, ny, batch, s);
   const int dt = sizeof(T) == 4 ? FFTPDE_C64 : FFTPDE_C128;
   const int lx = ilog2(nx), ly = ilog2(ny);
   const long long pts = (long long)nx * ny, hpts = (long long)(nx / 2 + 1) * ny;

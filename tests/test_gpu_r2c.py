@@ -12,6 +12,9 @@ pytestmark = pytest.mark.gpu
 THREADS = oracle.default_threads()
 
 SHAPES = [(2, 4), (8, 2), (64, 32), (256, 1024), (4096, 16), (16, 4096), (2048, 2048)]
+# half-row passes (nx, ny >= 16 and a column tile no wider than nx/2): every
+# row length from 16 to 4096 and column lengths 16..4096
+SHAPES += [(32, 1024), (512, 64), (1024, 16), (128, 4096), (4096, 256), (16, 2048)]
 # 7-smooth sides (the mixed-radix passes), odd and even nx
 SHAPES += [(3, 2), (5, 7), (12, 20), (45, 64), (64, 45), (96, 30), (105, 7), (1536, 10), (9, 2048), (4050, 3)]
 
@@ -98,3 +101,26 @@ def test_smallest_fields(fp, dt):
     assert np.abs(X[0] - ref).max() <= (1e-15 if dt == "f64" else 1e-6) * np.abs(ref).max()
     y = fp.fft2d_c2r(fp.fft2d_r2c(_dev(x, dt)), 2).cpu().numpy()
     assert np.abs(y - x).max() <= (1e-15 if dt == "f64" else 1e-6) * np.abs(x).max()
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_real_side_not_aligned_like_complex_points(fp, dt):
+    """A real input (or output) that starts one element into its buffer is
+    not aligned like the complex points the half-row passes read: the pair
+    route takes it, with the same results."""
+    import torch
+    nx, ny = 256, 128
+    say(f"r2c unaligned {dt}")
+    x = _real((1, ny, nx), 17, dt)
+    buf = torch.zeros(nx * ny + 1, dtype=torch.float32 if dt == "f32" else torch.float64, device="cuda:0")
+    view = buf[1:].view(1, ny, nx)
+    view.copy_(_dev(x, dt))
+    X = fp.fft2d_r2c(view).cpu().numpy().astype(np.complex128)
+    ref = oracle.rfft2d(x[0], threads=THREADS)
+    assert oracle.rel_l2(X[0], ref) <= _tol(dt, nx, ny)
+    Xa = fp.fft2d_r2c(_dev(x, dt)).cpu().numpy().astype(np.complex128)
+    assert oracle.rel_l2(Xa[0], ref) <= _tol(dt, nx, ny)
+    out = torch.zeros_like(buf)
+    fp.fft2d_c2r(fp.fft2d_r2c(_dev(x, dt)), nx, out=out[1:].view(1, ny, nx))
+    y = out[1:].view(1, ny, nx).cpu().numpy()
+    assert np.linalg.norm(y[0] - x[0]) <= 2 * _tol(dt, nx, ny) * np.linalg.norm(x[0])
