@@ -222,10 +222,10 @@ int fft2d_inverse(fftpde_ctx *ctx, const void *in, void *out, int nx, int ny, in
  *   for half spectra of real fields).  Same dtypes and sides.
  * Both: in and out must not overlap (EINVAL).  Powers of two with nx, ny
  *   >= 16 (and nx ny >= 2^14 FP32 / 2^13 FP64), the real side aligned to a
- *   complex element: each real row is read as a complex row of nx/2 points,
- *   transformed and split into its half spectrum by the even/odd
- *   combination of Sec. II.C (X[0] and X[nx/2] packed into one column), into
- *   the per-stream scratch; the column pass writes the half spectra
+ *   complex element: each real field is read as a complex field of nx/2
+ *   columns, its column transforms go to the per-stream scratch, and a row
+ *   pass over row pairs (b, -b) transforms the rows and splits them into
+ *   whole half-spectrum rows by the even/odd combination of Sec. II.C
  *   (c2r: the same steps backwards).  Other shapes: two real fields go
  *   through one complex transform, their spectrum in the per-stream
  *   scratch; one more pass splits it into the two half spectra (or joins

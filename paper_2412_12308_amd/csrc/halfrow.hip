@@ -1,10 +1,9 @@
-// halfrow.hip -- the half-row passes of fft2d_r2c / fft2d_c2r (see
-// halfrow.hpp for the algebra).  Row passes: persistent workgroups over
-// tiles of whole rows, the M-point transform in registers and LDS, the
-// even/odd split (or join) through one more LDS round trip for the mirrored
-// index.  Column passes: one workgroup per tile of adjacent columns of one
-// field, stage-table twiddles; the tile holding column 0 unpacks (or packs)
-// columns 0 and M.
+// halfrow.hip -- the passes of fft2d_r2c / fft2d_c2r on real fields (see
+// halfrow.hpp for the algebra).  Column passes: one workgroup per tile of
+// adjacent columns of the complex view of one field, stage-table twiddles.
+// Row passes: persistent workgroups over tiles of row pairs (b, -b), the
+// M-point transforms in registers and LDS, the even/odd combination through
+// one more LDS round trip for the mirrored row and index.
 #include <array>
 #include <utility>
 
@@ -15,7 +14,7 @@ namespace fftpde {
 namespace {
 
 constexpr int kRowE = 8;
-constexpr int kRowTH = 256;
+constexpr int kRowTH = 512;
 constexpr int kRowMaxLr = 3;
 constexpr int kRowMinLm = 3;   // nx >= 16
 constexpr int kRowMaxLm = 11;  // nx <= 4096
@@ -38,115 +37,134 @@ __device__ __forceinline__ long long work_at(long long row, int n, int logny, in
   return (f << (logny + LM)) + ((long long)(n >> lt) << (logny + lt)) + (y << lt) + (n & ((1 << lt) - 1));
 }
 
+// Row passes: tiles of LINES rows = LINES / 2 row pairs (b, -b); pair p of a
+// field is rows (p, ny - p) for p > 0, and pair 0 is rows 0 and ny/2, each
+// its own mirror.
 template <typename T, int LM>
 struct RowCfg {
   static constexpr int M = 1 << LM;
   static constexpr int LINES = kRowE * kRowTH / M;
+  static constexpr int PAIRS = LINES / 2;
   using Map = RowMap<LM, LINES, plan_pad(LM, kRowMaxLr, false)>;
   using Eng = Engine<T, LM, kRowE, kRowTH, kRowMaxLr, false, Map, false>;
   static constexpr int kLds = Map::kLdsElems > Eng::kLdsWords ? Map::kLdsElems : Eng::kLdsWords;
-  static_assert(LINES >= 1 && LINES * M == kRowE * kRowTH, "tile must hold whole rows");
+  static_assert(PAIRS >= 1 && LINES * M == kRowE * kRowTH, "tile must hold whole row pairs");
 };
 
-// Real rows -> M-point transforms -> X[0..M] (X[0] + i X[M] in column 0) into
-// the work field.
+struct PairLine {
+  long long row;  // f ny + b
+  int mirror;     // the line holding row -b (the line itself for b = 0, ny/2)
+  bool live;      // a pair of the launch (padding lines reread the last pair)
+};
+
+template <int LINES>
+__device__ __forceinline__ PairLine pair_line(long long tile, int line, long long npairs, int logny) {
+  constexpr int PAIRS = LINES / 2;
+  const long long q0 = tile * PAIRS + (line >> 1);
+  const long long q = min(q0, npairs - 1);
+  const int half = 1 << (logny - 1);
+  const long long f = q >> (logny - 1);
+  const int p = (int)(q & (half - 1));
+  const int b = (line & 1) == 0 ? p : (p == 0 ? half : 2 * half - p);
+  return {(f << logny) + b, p == 0 ? line : (line ^ 1), q0 < npairs};
+}
+
+// r2c, second pass: work field rows (Zc) -> M-point transforms of row pairs
+// -> half-spectrum rows X[b][0..M].
 template <typename T, int LM>
 __global__ void __launch_bounds__(kRowTH) r2c_rows_kernel(HalfRowArgs<T> a) {
   using C = RowCfg<T, LM>;
   using Map = typename C::Map;
   using Eng = typename C::Eng;
-  constexpr int M = C::M, LINES = C::LINES;
+  constexpr int M = C::M, LINES = C::LINES, PAIRS = C::PAIRS;
   __shared__ cx<T> lds[C::kLds];
   int tid = threadIdx.x;
-  const long long nrows = a.fields << a.logny;
-  const long long ntiles = (nrows + LINES - 1) / LINES;
+  const long long npairs = a.fields << (a.logny - 1);
+  const long long ntiles = (npairs + PAIRS - 1) / PAIRS;
   const TileWalk<1> walk(ntiles);
   if (walk.first < 0) return;
   cx<T> wall[Eng::kTwRegs];
   Eng::load_all_tw(wall, a.tw, tid);
-  const cx<T>* in = reinterpret_cast<const cx<T>*>(a.rin);  // row r: M complex points from r M
-  const int sh = kTwLog - a.lognx;                          // w^n = tw[n << sh], w = exp(-2 pi i / nx)
+  const int sh = kTwLog - a.lognx;  // w^k = tw[k << sh], w = exp(-2 pi i / nx)
   const T h = T(0.5);
   for (long long tile = walk.first; tile >= 0; tile = walk.next(tile)) {
     tid = opaque(tid);
-    const long long row0 = tile * LINES;
     cx<T> x[kRowE];
-    // rows past the last reread it and are never stored
     Eng::for_each_input(tid, [&](int i, int line, int n) {
-      const long long row = min(row0 + line, nrows - 1);
-      x[i] = load_stream(&in[(row << LM) + n]);
+      x[i] = a.work[work_at<LM>(pair_line<LINES>(tile, line, npairs, a.logny).row, n, a.logny, a.lt)];
     });
     Eng::run_regs(x, lds, wall, tid);
     Eng::for_each_output(tid, [&](int i, int line, int n) { lds[Map::lds(line, n)] = x[i]; });
     lds_barrier();
-    Eng::for_each_output(tid, [&](int i, int line, int n) {
+    Eng::for_each_output(tid, [&](int i, int line, int k) {
+      const PairLine pl = pair_line<LINES>(tile, line, npairs, a.logny);
       const cx<T> z = x[i];
-      cx<T> X;
-      if (n == 0) {
-        // E[0] = Re Z[0], O[0] = Im Z[0]: X[0] = E + O, X[M] = E - O
-        X = {z.re + z.im, z.re - z.im};
-      } else {
-        const cx<T> zm = lds[Map::lds(line, M - n)];
-        const cx<T> e = {h * (z.re + zm.re), h * (z.im - zm.im)};  // (Z + conj Zm) / 2
-        const cx<T> o = {h * (z.im + zm.im), h * (zm.re - z.re)};  // -i (Z - conj Zm) / 2
-        X = e + cmul(o, a.tw[n << sh]);
+      const cx<T> zm = lds[Map::lds(pl.mirror, (M - k) & (M - 1))];  // Zr[-b][-k]
+      const cx<T> e = {h * (z.re + zm.re), h * (z.im - zm.im)};      // (Zr + conj Zr-) / 2
+      const cx<T> o = {h * (z.im + zm.im), h * (zm.re - z.re)};      // -i (Zr - conj Zr-) / 2
+      if (pl.live) {
+        cx<T>* out = a.hout + pl.row * (M + 1);
+        out[k] = e + cmul(o, a.tw[k << sh]);
+        if (k == 0) out[M] = e - o;  // w^M = -1
       }
-      const long long row = row0 + line;
-      if (row < nrows) a.work[work_at<LM>(row, n, a.logny, a.lt)] = X;
     });
     lds_barrier();  // the LDS is free for the next tile
   }
 }
 
-// Work field (X[0..M], column 0 packed) -> Z = E + i O -> M-point inverse
-// transforms -> real rows, times a.scale.
+// c2r, first pass: half-spectrum rows of each pair -> Zr = E + i O (the
+// Hermitian extension) -> M-point inverse transforms -> work field rows.
 template <typename T, int LM>
 __global__ void __launch_bounds__(kRowTH) c2r_rows_kernel(HalfRowArgs<T> a) {
   using C = RowCfg<T, LM>;
   using Map = typename C::Map;
   using Eng = typename C::Eng;
-  constexpr int M = C::M, LINES = C::LINES;
+  constexpr int M = C::M, LINES = C::LINES, PAIRS = C::PAIRS;
   __shared__ cx<T> lds[C::kLds];
+  __shared__ cx<T> last[LINES];  // column M of each line's row
   int tid = threadIdx.x;
-  const long long nrows = a.fields << a.logny;
-  const long long ntiles = (nrows + LINES - 1) / LINES;
+  const long long npairs = a.fields << (a.logny - 1);
+  const long long ntiles = (npairs + PAIRS - 1) / PAIRS;
   const TileWalk<1> walk(ntiles);
   if (walk.first < 0) return;
   cx<T> wall[Eng::kTwRegs];
   Eng::load_all_tw(wall, a.tw, tid);
-  cx<T>* out = reinterpret_cast<cx<T>*>(a.rout);
   const int sh = kTwLog - a.lognx;
   const T h = T(0.5);
   for (long long tile = walk.first; tile >= 0; tile = walk.next(tile)) {
     tid = opaque(tid);
-    const long long row0 = tile * LINES;
     cx<T> x[kRowE];
     Eng::for_each_input(tid, [&](int i, int line, int n) {
-      const long long row = min(row0 + line, nrows - 1);
-      x[i] = a.work[work_at<LM>(row, n, a.logny, a.lt)];
+      const cx<T>* in = a.hin + pair_line<LINES>(tile, line, npairs, a.logny).row * (M + 1);
+      x[i] = in[n];
+      lds[Map::lds(line, n)] = x[i];
+      if (n == 0) last[line] = in[M];
     });
-    Eng::for_each_input(tid, [&](int i, int line, int n) { lds[Map::lds(line, n)] = x[i]; });
     lds_barrier();
-    Eng::for_each_input(tid, [&](int i, int line, int n) {
-      const cx<T> v = x[i];
-      cx<T> z;
-      if (n == 0) {
-        // v = X[0] + i X[M]: E[0] = (X[0] + X[M]) / 2, O[0] = (X[0] - X[M]) / 2, both real
-        z = {h * (v.re + v.im), h * (v.re - v.im)};
+    Eng::for_each_input(tid, [&](int i, int line, int k) {
+      const PairLine pl = pair_line<LINES>(tile, line, npairs, a.logny);
+      cx<T> e, o;
+      if (k == 0) {
+        // the Hermitian parts of columns 0 and M: H = (X[b] + conj X[-b]) / 2
+        const cx<T> x0 = x[i], x0m = lds[Map::lds(pl.mirror, 0)];
+        const cx<T> xM = last[line], xMm = last[pl.mirror];
+        const cx<T> h0 = {h * (x0.re + x0m.re), h * (x0.im - x0m.im)};
+        const cx<T> hM = {h * (xM.re + xMm.re), h * (xM.im - xMm.im)};
+        e = {h * (h0.re + hM.re), h * (h0.im + hM.im)};
+        o = {h * (h0.re - hM.re), h * (h0.im - hM.im)};
       } else {
-        const cx<T> vm = lds[Map::lds(line, M - n)];
-        const cx<T> e = {h * (v.re + vm.re), h * (v.im - vm.im)};  // (X + conj Xm) / 2
-        const cx<T> d = {h * (v.re - vm.re), h * (v.im + vm.im)};  // (X - conj Xm) / 2
-        const cx<T> o = cmul(d, conjg(a.tw[n << sh]));             // times w^-n
-        z = {e.re - o.im, e.im + o.re};                             // E + i O
+        const cx<T> v = x[i];
+        const cx<T> vm = lds[Map::lds(pl.mirror, M - k)];  // X~[b][k + M] = conj X[-b][M - k]
+        e = {h * (v.re + vm.re), h * (v.im - vm.im)};
+        o = cmul(cx<T>{h * (v.re - vm.re), h * (v.im + vm.im)}, conjg(a.tw[k << sh]));  // times w^-k
       }
-      x[i] = conjg(z);  // the inverse by conjugation
+      x[i] = {e.re - o.im, -(e.im + o.re)};  // conj(E + i O): the inverse by conjugation
     });
     lds_barrier();
     Eng::run_regs(x, lds, wall, tid);
     Eng::for_each_output(tid, [&](int i, int line, int n) {
-      const long long row = row0 + line;
-      if (row < nrows) out[(row << LM) + n] = {x[i].re * a.scale, -x[i].im * a.scale};
+      const PairLine pl = pair_line<LINES>(tile, line, npairs, a.logny);
+      if (pl.live) a.work[work_at<LM>(pl.row, n, a.logny, a.lt)] = conjg(x[i]);
     });
   }
 }
@@ -170,83 +188,58 @@ struct ColTileCfg {
   static_assert(kColTH % TT == 0, "every thread stays on one column of the tile");
   using Map = ColMap<LOGN, LOGT, plan_pad(LOGN, MAXLR, false)>;
   using Eng = Engine<T, LOGN, E, kColTH, MAXLR, false, Map, false>;
-  static constexpr int kLds = Map::kLdsElems > Eng::kLdsWords ? Map::kLdsElems : Eng::kLdsWords;
+  static constexpr int kLds = Eng::kLdsWords;
 };
 
-// Work field -> forward column transforms -> half spectra [ny][M + 1];
-// column 0 (P = Y0 + i YM) unpacks into columns 0 and M.
+// Column tile addresses: field f, first column x0, this thread's column x
+struct ColTile {
+  long long f;
+  int x;
+};
+
+template <int LOGT>
+__device__ __forceinline__ ColTile col_tile(int lm) {
+  const long long per = (1ll << lm) >> LOGT;  // tiles per field
+  const long long tile = xcd_tile();
+  const long long f = tile / per;
+  return {f, ((int)(tile - f * per) << LOGT) + (int)(threadIdx.x & ((1 << LOGT) - 1))};
+}
+
+// r2c, first pass: the complex view z[y][a] of the real fields -> forward
+// column transforms -> work field.
 template <typename T, int LOGN>
 __global__ void __launch_bounds__(kColTH) r2c_cols_kernel(HalfRowArgs<T> a) {
   using C = ColTileCfg<T, LOGN>;
-  using Map = typename C::Map;
   using Eng = typename C::Eng;
-  constexpr int N = C::N, TT = C::TT, LOGT = C::LOGT;
   __shared__ cx<T> lds[C::kLds];
   const int tid = threadIdx.x;
-  const int LM = a.lognx - 1, M = 1 << LM, H = M + 1;
-  const long long per = M >> LOGT;  // tiles per field
-  const long long tile = xcd_tile();
-  const long long f = tile / per;
-  const int x0 = (int)(tile - f * per) << LOGT;
-  const int col = tid & (TT - 1), x = x0 + col;
-  const int lt = a.lt;
-  const cx<T>* src = a.work + (f << (LOGN + LM)) + ((long long)(x >> lt) << (LOGN + lt)) + (x & ((1 << lt) - 1));
+  const int lm = a.lognx - 1, lt = a.lt;
+  const ColTile t = col_tile<C::LOGT>(lm);
+  const cx<T>* src = reinterpret_cast<const cx<T>*>(a.rin) + (t.f << (LOGN + lm)) + t.x;
   cx<T> v[C::E];
-  Eng::for_each_input(tid, [&](int i, int, int n) { v[i] = src[(long long)n << lt]; });
+  Eng::for_each_input(tid, [&](int i, int, int n) { v[i] = load_stream(&src[(long long)n << lm]); });
   Eng::run_stage(v, lds, a.stw, tid);
-  cx<T>* dst = a.hout + f * (long long)N * H;
-  if (x0 == 0) {
-    Eng::for_each_output(tid, [&](int i, int line, int n) { lds[Map::lds(line, n)] = v[i]; });
-    lds_barrier();
-  }
-  const T h = T(0.5);
-  Eng::for_each_output(tid, [&](int i, int, int n) {
-    if (x == 0) {
-      const cx<T> p = v[i], pm = lds[Map::lds(0, (N - n) & (N - 1))];
-      dst[(long long)n * H] = {h * (p.re + pm.re), h * (p.im - pm.im)};      // (P + conj Pm) / 2
-      dst[(long long)n * H + M] = {h * (p.im + pm.im), h * (pm.re - p.re)};  // -i (P - conj Pm) / 2
-    } else {
-      dst[(long long)n * H + x] = v[i];
-    }
-  });
+  cx<T>* dst = a.work + (t.f << (LOGN + lm)) + ((long long)(t.x >> lt) << (LOGN + lt)) + (t.x & ((1 << lt) - 1));
+  Eng::for_each_output(tid, [&](int i, int, int n) { dst[(long long)n << lt] = v[i]; });
 }
 
-// Half spectra -> inverse column transforms -> work field; column 0 carries
-// the Hermitian parts of columns 0 and M packed as H0 + i HM.
+// c2r, second pass: work field -> inverse column transforms (by
+// conjugation), times 1 / (M ny) -> the complex view of the real fields.
 template <typename T, int LOGN>
 __global__ void __launch_bounds__(kColTH) c2r_cols_kernel(HalfRowArgs<T> a) {
   using C = ColTileCfg<T, LOGN>;
   using Eng = typename C::Eng;
-  constexpr int N = C::N, TT = C::TT, LOGT = C::LOGT;
   __shared__ cx<T> lds[C::kLds];
   const int tid = threadIdx.x;
-  const int LM = a.lognx - 1, M = 1 << LM, H = M + 1;
-  const long long per = M >> LOGT;
-  const long long tile = xcd_tile();
-  const long long f = tile / per;
-  const int x0 = (int)(tile - f * per) << LOGT;
-  const int col = tid & (TT - 1), x = x0 + col;
-  const int lt = a.lt;
-  const cx<T>* src = a.hin + f * (long long)N * H;
-  const T h = T(0.5);
+  const int lm = a.lognx - 1, lt = a.lt;
+  const ColTile t = col_tile<C::LOGT>(lm);
+  const cx<T>* src = a.work + (t.f << (LOGN + lm)) + ((long long)(t.x >> lt) << (LOGN + lt)) + (t.x & ((1 << lt) - 1));
   cx<T> v[C::E];
-  Eng::for_each_input(tid, [&](int i, int, int n) {
-    cx<T> w;
-    if (x == 0) {
-      const int nm = (N - n) & (N - 1);
-      const cx<T> a0 = src[(long long)n * H], b0 = src[(long long)nm * H];
-      const cx<T> aM = src[(long long)n * H + M], bM = src[(long long)nm * H + M];
-      const cx<T> h0 = {h * (a0.re + b0.re), h * (a0.im - b0.im)};
-      const cx<T> hM = {h * (aM.re + bM.re), h * (aM.im - bM.im)};
-      w = {h0.re - hM.im, h0.im + hM.re};  // H0 + i HM
-    } else {
-      w = src[(long long)n * H + x];
-    }
-    v[i] = conjg(w);
-  });
+  Eng::for_each_input(tid, [&](int i, int, int n) { v[i] = conjg(src[(long long)n << lt]); });
   Eng::run_stage(v, lds, a.stw, tid);
-  cx<T>* dst = a.work + (f << (LOGN + LM)) + ((long long)(x >> lt) << (LOGN + lt)) + (x & ((1 << lt) - 1));
-  Eng::for_each_output(tid, [&](int i, int, int n) { dst[(long long)n << lt] = conjg(v[i]); });
+  cx<T>* dst = reinterpret_cast<cx<T>*>(a.rout) + (t.f << (LOGN + lm)) + t.x;
+  const T sc = a.scale;
+  Eng::for_each_output(tid, [&](int i, int, int n) { dst[(long long)n << lm] = {v[i].re * sc, -v[i].im * sc}; });
 }
 
 // ---- launch tables --------------------------------------------------------
@@ -269,8 +262,8 @@ template <typename T, int LM, bool FWD>
 hipError_t launch_rows(const HalfRowArgs<T>& a, hipStream_t s) {
   static const int slots = row_slots<T, LM, FWD>();  // thread-safe one-time query
   if (slots <= 0) return hipErrorInvalidValue;
-  constexpr int LINES = RowCfg<T, LM>::LINES;
-  const long long ntiles = ((a.fields << a.logny) + LINES - 1) / LINES;
+  constexpr int PAIRS = RowCfg<T, LM>::PAIRS;
+  const long long ntiles = ((a.fields << (a.logny - 1)) + PAIRS - 1) / PAIRS;
   const long long grid = std::min<long long>(ntiles, slots);
   if (grid <= 0) return hipSuccess;
   if constexpr (FWD) hipLaunchKernelGGL((r2c_rows_kernel<T, LM>), dim3((unsigned)grid), dim3(kRowTH), 0, s, a);

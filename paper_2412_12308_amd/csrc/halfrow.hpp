@@ -1,26 +1,29 @@
-// halfrow.hpp -- half spectra of real fields through half-length complex
-// row transforms.
+// halfrow.hpp -- half spectra of real fields in two passes, columns first.
 //
-// A real row x of even length N read as the complex row z[m] = x[2m] +
-// i x[2m + 1] of length M = N/2 has the M-point spectrum Z = E + i O, with
-// E, O the spectra of the even and odd samples.  Both are Hermitian (the
-// samples are real, Sec. II.B), so with Zm[k] = conj(Z[(M - k) mod M])
-//   E[k] = (Z[k] + Zm[k]) / 2,   O[k] = -i (Z[k] - Zm[k]) / 2,
-// and the row's N-point spectrum for k = 0..M is the even/odd combination of
-// Sec. II.C, X[k] = E[k] + w^k O[k], w = exp(-2 pi i / N).  X[0] and X[M]
-// are real; they travel packed as X[0] + i X[M] in column 0, so every row
-// stays M complex values and the column pass is the complex one over M
-// columns.  The packed column transforms to P = Y0 + i YM, where Y0 and YM
-// (the spectra of two real columns) are Hermitian in the row index b:
-//   Y0[b] = (P[b] + conj P[-b]) / 2,   YM[b] = -i (P[b] - conj P[-b]) / 2.
-// The inverse runs the same steps backwards: columns of the half spectrum
-// (column 0 packed with the Hermitian parts of columns 0 and M), then per
-// row E[k] = (X[k] + conj X[M - k]) / 2, O[k] = w^-k (X[k] - conj X[M - k]) / 2,
-// Z = E + i O and the M-point inverse transform, whose real and imaginary
-// parts are the even and odd samples of the real row.
+// A real field x[ny][nx] read as complex points is z[y][a] = x[y][2a] +
+// i x[y][2a + 1], a < M = nx/2: a complex field of M columns.  Its column
+// transforms Zc[b][a] (b the row frequency) hold the column spectra of the
+// even and odd columns of x, Ge + i Go; both are Hermitian in b (the columns
+// are real, Sec. II.B), so with the mirrored row -b
+//   Ge[b] = (Zc[b] + conj Zc[-b]) / 2,   Go[b] = -i (Zc[b] - conj Zc[-b]) / 2.
+// The row transform over x of row b then splits into the M-point transforms
+// of its even and odd samples (Sec. II.C): with Zr[b] the M-point transform of
+// Zc[b][.] and E[k], O[k] those of Ge[b], Go[b],
+//   E[k] = (Zr[b][k] + conj Zr[-b][-k]) / 2,   O[k] = -i (Zr[b][k] - conj Zr[-b][-k]) / 2,
+//   X[b][k] = E[k mod M] + w^k O[k mod M],  k = 0..M,  w = exp(-2 pi i / nx).
+// So r2c is a column pass over the complex view (-> work field) and a row
+// pass over row pairs (b, -b): M-point transforms of both rows, the
+// combination above, and whole half-spectrum rows [ny][M + 1] written out.
+// c2r runs the same steps backwards: per row pair, from the Hermitian
+// extension X~ of the half spectrum (columns 0 and M replaced by their
+// Hermitian parts, X~[b][k + M] = conj X~[-b][M - k]),
+//   E[k] = (X~[b][k] + X~[b][k + M]) / 2,   O[k] = w^-k (X~[b][k] - X~[b][k + M]) / 2,
+//   Zr[b][k] = E[k] + i O[k],
+// M-point inverse transforms into the work field, then the inverse column
+// pass writes the complex view of the real field.
 //
-// Two passes, each one read and one write: real fields (b P) -> M x ny
-// complex work field (b P) -> half spectra, and back.
+// Each pass reads and writes once: real field (b P) <-> work field of M x ny
+// complex points (b P) <-> half spectra.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -40,7 +43,7 @@ struct HalfRowArgs {
   const cx<T>* stw;     // stage table of the column plan (column passes)
   long long fields;
   int lognx, logny, lt;
-  T scale;              // c2r row pass: 1 / (M ny)
+  T scale;              // c2r column pass: 1 / (M ny)
 };
 
 // Shapes with compiled half-row kernels: nx in [16, 4096], ny in [16, 4096],
@@ -51,13 +54,16 @@ int halfrow_col_logt(int fp64, int logny);
 // radix plan of the column passes (maximum log-radix)
 int halfrow_col_maxlr(int fp64);
 
-template <typename T>
-hipError_t launch_r2c_rows(const HalfRowArgs<T>& a, hipStream_t s);
+// r2c: launch_r2c_cols (real fields -> work), then launch_r2c_rows (work ->
+// half spectra).  c2r: launch_c2r_rows (half spectra -> work), then
+// launch_c2r_cols (work -> real fields).
 template <typename T>
 hipError_t launch_r2c_cols(const HalfRowArgs<T>& a, hipStream_t s);
 template <typename T>
-hipError_t launch_c2r_cols(const HalfRowArgs<T>& a, hipStream_t s);
+hipError_t launch_r2c_rows(const HalfRowArgs<T>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_c2r_rows(const HalfRowArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_c2r_cols(const HalfRowArgs<T>& a, hipStream_t s);
 
 }  // namespace fftpde

@@ -505,11 +505,12 @@ int run_transform(Context* c, int dtype, bool inverse, const void* in, void* out
                              : transform<double>(c, in, out, nx, ny, batch, inverse, s);
 }
 
-// fft2d_r2c / fft2d_c2r through the half-row passes (halfrow.hpp): each
-// real row transformed as a complex row of half the length and split into
-// its half spectrum (or joined back), one work field of M x ny complex
-// points per real field between the row and the column pass.  Chunks of
-// fields count the real fields and the work fields together.
+// fft2d_r2c / fft2d_c2r in two passes (halfrow.hpp): the column pass over
+// the real fields read as complex fields of nx/2 columns, then the row pass
+// over row pairs (b, -b) that writes whole half-spectrum rows (c2r: the
+// reverse), one work field of M x ny complex points per real field between
+// them.  Chunks of fields count the real fields and the work fields
+// together.
 template <typename T>
 int half_rows(Context* c, bool inverse, const void* in, void* out, int nx, int ny, int batch, hipStream_t s) {
   const int dt = sizeof(T) == 4 ? FFTPDE_C64 : FFTPDE_C128;
@@ -539,10 +540,10 @@ int half_rows(Context* c, bool inverse, const void* in, void* out, int nx, int n
   a.logny = ly;
   a.lt = lt;
   a.scale = T(1.0 / ((double)(nx / 2) * (double)ny));
-  const char* names[4] = {sizeof(T) == 4 ? "r2c_rows_float" : "r2c_rows_double",
-                          sizeof(T) == 4 ? "r2c_cols_float" : "r2c_cols_double",
-                          sizeof(T) == 4 ? "c2r_cols_float" : "c2r_cols_double",
-                          sizeof(T) == 4 ? "c2r_rows_float" : "c2r_rows_double"};
+  const char* names[4] = {sizeof(T) == 4 ? "r2c_cols_float" : "r2c_cols_double",
+                          sizeof(T) == 4 ? "r2c_rows_float" : "r2c_rows_double",
+                          sizeof(T) == 4 ? "c2r_rows_float" : "c2r_rows_double",
+                          sizeof(T) == 4 ? "c2r_cols_float" : "c2r_cols_double"};
   for (long long f0 = 0; f0 < batch; f0 += chunk) {
     a.fields = std::min<long long>(chunk, batch - f0);
     const double rb = (double)rbytes * a.fields, hb = (double)hbytes * a.fields;
@@ -558,13 +559,13 @@ int half_rows(Context* c, bool inverse, const void* in, void* out, int nx, int n
     if (!inverse) {
       a.rin = static_cast<const T*>(at<T>(in, rbytes * (size_t)f0));
       a.hout = static_cast<cx<T>*>(at<T>(out, hbytes * (size_t)f0));
-      rc = step(0, 2 * rb, launch_r2c_rows<T>);
-      if (rc == FFTPDE_OK) rc = step(1, rb + hb, launch_r2c_cols<T>);
+      rc = step(0, 2 * rb, launch_r2c_cols<T>);
+      if (rc == FFTPDE_OK) rc = step(1, rb + hb, launch_r2c_rows<T>);
     } else {
       a.hin = static_cast<const cx<T>*>(at<T>(in, hbytes * (size_t)f0));
       a.rout = static_cast<T*>(at<T>(out, rbytes * (size_t)f0));
-      rc = step(2, hb + rb, launch_c2r_cols<T>);
-      if (rc == FFTPDE_OK) rc = step(3, 2 * rb, launch_c2r_rows<T>);
+      rc = step(2, hb + rb, launch_c2r_rows<T>);
+      if (rc == FFTPDE_OK) rc = step(3, 2 * rb, launch_c2r_cols<T>);
     }
     if (rc != FFTPDE_OK) return rc;
   }
