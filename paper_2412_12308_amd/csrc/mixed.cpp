@@ -10,6 +10,7 @@
 #include "../../include/fftpde.h"
 #include "halfspec.hpp"
 #include "mixed.hpp"
+#include "rpass.hpp"
 #include "solve.hpp"
 
 namespace fftpde {
@@ -79,6 +80,35 @@ int mr_pass(Context* c, int mode, int nf, const void* in0, const void* in1, void
             void* rout = nullptr, long long nreal = 0) {
   const bool col = mode >= kMrColFwd;
   const int n = col ? ny : nx;
+  const char* name = col ? (sizeof(T) == 4 ? "mixed_col_float" : "mixed_col_double")
+                         : (sizeof(T) == 4 ? "mixed_row_float" : "mixed_row_double");
+  if (nf == 1 && !rin && !rout && !in1 && !out1 && rp_pass_ok(mode, n, sizeof(T) == 8)) {
+    // n = R 2^m: the radix-R step around the power-of-two register engine
+    int r = 0, lp = 0;
+    rp_split(n, col, sizeof(T) == 8, &r, &lp);
+    RpArgs<T> p{};
+    p.in = static_cast<const cx<T>*>(in0);
+    p.out = static_cast<cx<T>*>(out0);
+    p.twn = mr_table<T>(c, n);
+    if (!p.twn) return FFTPDE_EDEVICE;
+    if constexpr (sizeof(T) == 4) p.tw = c->tw32;
+    else p.tw = c->tw64;
+    p.stwf = c->stage_tw<T>(lp, 3, false);
+    p.stwr = c->stage_tw<T>(lp, 3, true);
+    p.nx = nx;
+    p.ny = ny;
+    p.fields = fields;
+    p.mode = mode;
+    p.scale = T(scale);
+    p.sym = sym;
+    const double bytes = 2.0 * sizeof(cx<T>) * (double)nx * ny * (double)fields;
+    const hipError_t e = timed_launch(c, name, bytes, s, [&] { return rp_launch<T>(p, s); });
+    if (e != hipSuccess) {
+      set_last_error(name, e);
+      return FFTPDE_EDEVICE;
+    }
+    return FFTPDE_OK;
+  }
   MrArgs<T> a{};
   a.plan = mr_plan(n);
   if (a.plan.nst == 0) return FFTPDE_EINVAL;
@@ -117,8 +147,6 @@ int mr_pass(Context* c, int mode, int nf, const void* in0, const void* in1, void
   double bytes = (double)sizeof(cx<T>) * (double)nx * ny * (double)fields * (nin + nout);
   if (rin || rout)  // one real side, one pair-field side
     bytes = (double)nx * ny * ((double)sizeof(T) * (double)nreal + (double)sizeof(cx<T>) * (double)fields);
-  const char* name = col ? (sizeof(T) == 4 ? "mixed_col_float" : "mixed_col_double")
-                         : (sizeof(T) == 4 ? "mixed_row_float" : "mixed_row_double");
   const hipError_t e = timed_launch(c, name, bytes, s, [&] { return mr_launch<T>(a, nf, small, (int)grid, s); });
   if (e != hipSuccess) {
     set_last_error(name, e);

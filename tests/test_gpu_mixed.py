@@ -270,3 +270,45 @@ def test_real_solve_matches_the_complex_path_on_a_7_smooth_grid(fp, dt):
     bound = TOL_FP64 if dt == "r64" else tol("c64", nx, ny, 2)
     err = np.linalg.norm(whole.cpu().numpy() - zc) / np.linalg.norm(zc)
     assert err <= bound
+
+
+# Sides R 2^m (R = 1, 3, 5, 7; m >= 5) take the radix-R step around the
+# power-of-two register engine: rows and columns of every R, the longest
+# 2^m of each, odd R on both axes, and the fused column pass of the solves
+# (FP32 R <= 3, FP64 R = 1; the other solves' columns stay on the LDS-stage
+# kernel, their rows on the new one).
+RP_SHAPES = [(96, 160), (160, 96), (448, 96), (384, 640), (3072, 32), (32, 3072), (2560, 32), (32, 3584),
+             (3584, 64), (1536, 96), (96, 1536)]
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("nx,ny", RP_SHAPES)
+def test_radix_step_passes_vs_oracle(fp, nx, ny, dt):
+    say(f"radix-step transforms {nx}x{ny} {dt}")
+    x = W.random_field((2, ny, nx), seed=nx * 7 + ny)
+    X = to_host(fp.fft2d_forward(to_dev(x, dt)))
+    for k in range(2):
+        ref = oracle.fft2d(as_oracle_input(x[k], dt), threads=THREADS)
+        assert oracle.rel_l2(X[k], ref) <= tol(dt, nx, ny, 1), k
+    ref = oracle.fft2d(as_oracle_input(x[1], dt), threads=THREADS)
+    y = to_host(fp.fft2d_inverse(to_dev(ref, dt)))
+    ref_i = oracle.ifft2d(as_oracle_input(ref, dt), threads=THREADS)
+    assert oracle.rel_l2(y, ref_i) <= tol(dt, nx, ny, 1)
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("nx,ny", [(160, 96), (64, 1536), (1536, 96), (448, 224), (96, 128)])
+def test_radix_step_solves_vs_oracle(fp, nx, ny, dt):
+    say(f"radix-step solves {nx}x{ny} {dt}")
+    lx, ly = 1.5, 0.75
+    u0 = W.random_field((ny, nx), seed=nx + 3 * ny)
+    s = u0 - u0.mean()
+    u = to_host(fp.solve_poisson(to_dev(s, dt), lx, ly))
+    ref = oracle.solve_poisson(as_oracle_input(s, dt), lx, ly, threads=THREADS)
+    assert rel_err_vs_input(u, ref, np.linalg.norm(ref)) <= tol(dt, nx, ny, 2)
+    d = to_host(fp.solve_diffusion(to_dev(u0, dt), 0.01, 0.2, lx, ly))
+    ref = oracle.solve_diffusion(as_oracle_input(u0, dt), lx, ly, 0.01, 0.2, threads=THREADS)
+    assert rel_err_vs_input(d, ref, np.linalg.norm(u0)) <= tol(dt, nx, ny, 2)
+    w, _ = fp.solve_wave(to_dev(u0, dt), None, 0.9, 0.37, lx, ly)
+    ref, _ = oracle.solve_wave(as_oracle_input(u0, dt), None, lx, ly, 0.9, 0.37, threads=THREADS)
+    assert rel_err_vs_input(to_host(w), ref, np.linalg.norm(u0)) <= tol(dt, nx, ny, 2)
