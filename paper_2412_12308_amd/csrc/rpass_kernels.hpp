@@ -128,6 +128,16 @@ __global__ void __launch_bounds__(kColTH) cols_kernel(RpArgs<T> a) {
   cx<T>* dst = a.out + f * (long long)nx * N + c;
   const OddRoots<R, T> rt(a.twn, P);
   const T sgn = (!SOLVE && a.mode == kMrColInv) ? T(-1) : T(1);
+  // the solve's symbol at the positions (a', b' = k1 + R k2) the inverse
+  // engine takes, evaluated before the loads land (it needs no data)
+  T msym[SOLVE ? R : 1][kE];
+  if constexpr (SOLVE) {
+    const int ai = mr_sidx(cl, nx);
+    Inv::for_each_input(tid, [&](int i, int, int k2) {
+#pragma unroll
+      for (int k = 0; k < R; k++) msym[k][i] = mr_symbol<T>(a.sym, ai, mr_sidx(k + R * k2, N));
+    });
+  }
   cx<T> x[R][kE];
   Fwd::for_each_input(tid, [&](int i, int, int n) {
     cx<T> v[R];
@@ -150,15 +160,12 @@ __global__ void __launch_bounds__(kColTH) cols_kernel(RpArgs<T> a) {
       });
     }
   } else {
-    // the symbol at (a', b' = k1 + R k2), then the conjugate for the inverse
-    const int ai = mr_sidx(cl, nx);
-    Inv::for_each_input(tid, [&](int i, int, int k2) {
+    // the symbol, then the conjugate for the inverse
 #pragma unroll
-      for (int k = 0; k < R; k++) {
-        const T m = mr_symbol<T>(a.sym, ai, mr_sidx(k + R * k2, N));
-        x[k][i] = {x[k][i].re * m, -x[k][i].im * m};
-      }
-    });
+    for (int k = 0; k < R; k++) {
+#pragma unroll
+      for (int i = 0; i < kE; i++) x[k][i] = {x[k][i].re * msym[k][i], -x[k][i].im * msym[k][i]};
+    }
 #pragma unroll
     for (int k = 0; k < R; k++) Inv::run_stage(x[k], lds, a.stwr, tid);
     if (c < nx) {
