@@ -93,8 +93,9 @@ int mr_pass(Context* c, int mode, int nf, const void* in0, const void* in1, void
     if (!p.twn) return FFTPDE_EDEVICE;
     if constexpr (sizeof(T) == 4) p.tw = c->tw32;
     else p.tw = c->tw64;
-    p.stwf = c->stage_tw<T>(lp, 3, false);
-    p.stwr = c->stage_tw<T>(lp, 3, true);
+    const int mlr = col ? rp_col_maxlr(sizeof(T) == 8, r, mode == kMrColSolve) : 3;
+    p.stwf = c->stage_tw<T>(lp, mlr, false);
+    p.stwr = c->stage_tw<T>(lp, mlr, true);
     p.nx = nx;
     p.ny = ny;
     p.fields = fields;

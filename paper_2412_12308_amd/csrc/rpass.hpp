@@ -27,10 +27,12 @@ namespace fftpde {
 // 5..11, columns: lp 5..12), n <= 4096; false otherwise.
 bool rp_split(int n, bool col, bool fp64, int* r, int* lp);
 // The fused column pass of a solve keeps R engine tiles in registers through
-// the FP64 evaluation of the symbol: compiled without spills for R <= 3
-// (FP32) and R = 1 (FP64) only; the other solves' column passes take the
-// LDS-stage kernel (mixed.hip).
-constexpr bool rp_solve_radix(bool fp64, int r) { return fp64 ? r == 1 : r <= 3; }
+// the evaluation of the symbol.  For R >= 5 (FP32) and R = 3 (FP64) its
+// engine takes 4 points per thread in radix-4 stages (half the tile), which
+// fits the registers without spills; otherwise 8 points, radix-8 stages.
+constexpr bool rp_col_small(bool fp64, int r, bool solve) { return solve && (fp64 ? r >= 3 : r >= 5); }
+constexpr int rp_col_maxlr(bool fp64, int r, bool solve) { return rp_col_small(fp64, r, solve) ? 2 : 3; }
+constexpr bool rp_solve_radix(bool fp64, int r) { return fp64 ? r <= 3 : r <= 7; }
 // A pass of `mode` (kMr*) over lines of length n that these kernels take.
 bool rp_pass_ok(int mode, int n, bool fp64);
 
@@ -40,7 +42,7 @@ struct RpArgs {
   cx<T>* out;
   const cx<T>* twn;   // exp(-2 pi i e / n), e < n: the radix-R step's twiddles
   const cx<T>* tw;    // exp(-2 pi i e / 4096): the row engine's
-  const cx<T>* stwf;  // column engine's stage tables, forward plan
+  const cx<T>* stwf;  // column engine's stage tables, forward plan (rp_col_maxlr)
   const cx<T>* stwr;  // and reversed plan (the solve's inverse)
   int nx, ny;
   long long fields;

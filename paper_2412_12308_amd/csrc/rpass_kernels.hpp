@@ -104,10 +104,22 @@ __global__ void __launch_bounds__(kRowTH) rows_kernel(RpArgs<T> a) {
 // Workgroups are dealt to the 8 XCDs round robin; tile = (b mod 8) G/8 +
 // b/8 gives each XCD a contiguous range of tiles, so adjacent column tiles,
 // which share the cache lines of their row pieces, meet in one L2.
+// Column tile shape: E points per thread per engine tile, radix up to
+// 2^MAXLR, TT = E kColTH / P columns.
+template <typename T, int R, bool SOLVE>
+struct ColShape {
+  static constexpr bool kSmall = rp_col_small(sizeof(T) == 8, R, SOLVE);
+  static constexpr int E = kSmall ? 4 : 8;
+  static constexpr int MAXLR = rp_col_maxlr(sizeof(T) == 8, R, SOLVE);
+  static constexpr int LOGPTS = kSmall ? 11 : 12;  // log2(E kColTH)
+};
+
 template <typename T, int R, int LP, bool SOLVE>
 __global__ void __launch_bounds__(kColTH) cols_kernel(RpArgs<T> a) {
+  using S = ColShape<T, R, SOLVE>;
+  constexpr int kE = S::E, kMaxLr = S::MAXLR;
   constexpr int P = 1 << LP, N = R * P;
-  constexpr int LOGT = 12 - LP;  // kE kColTH = 4096 = TT P
+  constexpr int LOGT = S::LOGPTS - LP;  // E kColTH = TT P
   constexpr int TT = 1 << LOGT;
   static_assert(kColTH % TT == 0, "every thread stays on one column of the tile");
   using FMap = ColMap<LP, LOGT, plan_pad(LP, kMaxLr, false)>;
@@ -209,11 +221,12 @@ hipError_t launch_rows(const RpArgs<T>& a, hipStream_t s) {
 
 template <typename T, int R, int LP>
 hipError_t launch_cols(const RpArgs<T>& a, hipStream_t s) {
-  constexpr int TT = 1 << (12 - LP);
-  const long long grid = a.fields * (long long)((a.nx + TT - 1) / TT);
+  const bool solve = a.mode == kMrColSolve;
+  const int tt = 1 << ((solve ? ColShape<T, R, true>::LOGPTS : ColShape<T, R, false>::LOGPTS) - LP);
+  const long long grid = a.fields * (long long)((a.nx + tt - 1) / tt);
   if (grid <= 0) return hipSuccess;
   if (grid > 0x7fffffffll) return hipErrorInvalidValue;
-  if (a.mode == kMrColSolve) {
+  if (solve) {
     if constexpr (rp_solve_radix(sizeof(T) == 8, R))
       hipLaunchKernelGGL((cols_kernel<T, R, LP, true>), dim3((unsigned)grid), dim3(kColTH), 0, s, a);
     else

@@ -63,8 +63,11 @@ def test_largest_sides_vs_oracle(fp, nx, ny, dt):
 
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
-def test_batched_and_in_place(fp, dt):
-    nx, ny, b = 60, 35, 3
+@pytest.mark.parametrize("nx,ny,b", [(60, 35, 3), (96, 1536, 3), (1536, 96, 2), (160, 96, 3)])
+def test_batched_and_in_place(fp, nx, ny, b, dt):
+    """In place, batched; (96, 1536): the radix-3 step's passes on columns of
+    3 x 512 (12 tiles of 8 columns); (1536, 96): rows of 3 x 512, columns of
+    3 x 32 in tiles of 128; (160, 96): the last column tile ragged."""
     say(f"mixed batch {nx}x{ny}x{b} {dt}")
     x = _field(nx, ny, b, 11)
     d = to_dev(x, dt)
@@ -272,11 +275,10 @@ def test_real_solve_matches_the_complex_path_on_a_7_smooth_grid(fp, dt):
     assert err <= bound
 
 
-# Sides R 2^m (R = 1, 3, 5, 7; m >= 5) take the radix-R step around the
-# power-of-two register engine: rows and columns of every R, the longest
-# 2^m of each, odd R on both axes, and the fused column pass of the solves
-# (FP32 R <= 3, FP64 R = 1; the other solves' columns stay on the LDS-stage
-# kernel, their rows on the new one).
+# Sides R 2^m (R = 1, 3, 5, 7, FP64 R <= 3; m >= 5) take the radix-R step
+# around the power-of-two register engine: rows and columns of every R, the
+# longest 2^m of each, odd R on both axes, and the fused column pass of the
+# solves (4 points per thread for R >= 5 in FP32 and R = 3 in FP64).
 RP_SHAPES = [(96, 160), (160, 96), (448, 96), (384, 640), (3072, 32), (32, 3072), (2560, 32), (32, 3584),
              (3584, 64), (1536, 96), (96, 1536)]
 
@@ -297,7 +299,8 @@ def test_radix_step_passes_vs_oracle(fp, nx, ny, dt):
 
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
-@pytest.mark.parametrize("nx,ny", [(160, 96), (64, 1536), (1536, 96), (448, 224), (96, 128)])
+@pytest.mark.parametrize("nx,ny", [(160, 96), (64, 1536), (1536, 96), (448, 224), (96, 128), (96, 160),
+                                   (64, 2560), (32, 3584), (3072, 64)])
 def test_radix_step_solves_vs_oracle(fp, nx, ny, dt):
     say(f"radix-step solves {nx}x{ny} {dt}")
     lx, ly = 1.5, 0.75
