@@ -237,9 +237,10 @@ def leg_3d(fp, torch, steps: int, warmup: int, check: bool):
 
 
 def mixed_leg(fp, torch, steps: int, warmup: int, check: bool, n: int = 1536, batch: int = 8):
-    """The wave problem on a side that is not a power of two (1536 = 2^9 3,
-    the mixed-radix path), FP32 complex, batch 8: three passes, algorithmic
-    bytes 6 b P per solve; per-pass times from a second, profiled run."""
+    """The wave problem on a side that is not a power of two (1536 = 3 x 2^9:
+    a radix-3 step around the 512-point register engine), FP32 complex,
+    batch 8: three passes, algorithmic bytes 6 b P per solve; per-pass times
+    from a second, profiled run."""
     import numpy as np
 
     dev = torch.device("cuda:0")
@@ -257,7 +258,7 @@ def mixed_leg(fp, torch, steps: int, warmup: int, check: bool, n: int = 1536, ba
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     alg = 6.0 * 8 * n * n * batch * steps
-    res = {"workload": f"wave2d_{n}x{n}_periodic_unit_square (mixed radix 8, 8, 8, 3), FP32 complex",
+    res = {"workload": f"wave2d_{n}x{n}_periodic_unit_square (3 x 512: radix-3 step + 512-point engine), FP32 complex",
            "batch": batch, "solves_per_s": round(batch * steps / (ms * 1e-3), 2),
            "ms_per_step": round(ms / steps, 4), "alg_gbs": round(alg / (ms * 1e-3) / 1e9, 1),
            "alg_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
