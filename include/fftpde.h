@@ -221,7 +221,7 @@ int fft2d_inverse(fftpde_ctx *ctx, const void *in, void *out, int nx, int ny, in
  *   a = nx/2 on even nx) replaced by (X[b][a] + conj(X[-b][a]))/2 (no change
  *   for half spectra of real fields).  Same dtypes and sides.
  * Both: in and out must not overlap (EINVAL).  Powers of two with nx, ny
- *   >= 16 (and nx ny >= 2^14 FP32 / 2^13 FP64), the real side aligned to a
+ *   >= 16 (and nx ny >= 2^15 FP32 / 2^14 FP64), the real side aligned to a
  *   complex element: each real field is read as a complex field of nx/2
  *   columns, its column transforms go to the per-stream scratch, and a row
  *   pass over row pairs (b, -b) transforms the rows and splits them into

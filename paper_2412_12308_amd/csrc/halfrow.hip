@@ -18,7 +18,7 @@ constexpr int kRowTH = 512;
 constexpr int kRowMaxLr = 3;
 constexpr int kRowMinLm = 3;   // nx >= 16
 constexpr int kRowMaxLm = 11;  // nx <= 4096
-constexpr int kColTH = 512;
+constexpr int kColTH = 1024;
 constexpr int kColMinLog = 4;
 constexpr int kColMaxLog = 12;
 
@@ -26,7 +26,7 @@ template <typename T>
 struct ColCfg {
   static constexpr int E = sizeof(T) == 4 ? 16 : 8;
   static constexpr int MAXLR = sizeof(T) == 4 ? 4 : 3;
-  static constexpr int kLogTile = sizeof(T) == 4 ? 13 : 12;  // points per tile
+  static constexpr int kLogTile = sizeof(T) == 4 ? 14 : 13;  // points per tile
 };
 
 // offset of element (row, n) of the work field: rows r = f ny + y, blocks of
@@ -311,7 +311,7 @@ hipError_t run(const HalfRowArgs<T>& a, hipStream_t s) {
 
 }  // namespace
 
-int halfrow_col_logt(int fp64, int logny) { return (fp64 ? 12 : 13) - logny; }
+int halfrow_col_logt(int fp64, int logny) { return (fp64 ? 13 : 14) - logny; }
 int halfrow_col_maxlr(int fp64) { return fp64 ? 3 : 4; }
 
 bool halfrow_supported(int fp64, int lognx, int logny) {
