@@ -105,27 +105,39 @@ __global__ void __launch_bounds__(kRowTH) rows_kernel(RpArgs<T> a) {
 // b/8 gives each XCD a contiguous range of tiles, so adjacent column tiles,
 // which share the cache lines of their row pieces, meet in one L2.
 // Column tile shape: E points per thread per engine tile, radix up to
-// 2^MAXLR, TT = E kColTH / P columns.
-template <typename T, int R, bool SOLVE>
+// 2^MAXLR, TH threads, TT = E TH / P columns.  The solves with R > 1 and the
+// FP64 passes with R > 1 keep R engine tiles (and the symbol) in registers:
+// 140-250 VGPRs, two or three waves per SIMD, so a 512-thread workgroup
+// (two waves per SIMD) runs alone on its CU with nothing to overlap its
+// loads.  They take 256 threads (two or three workgroups per CU) where the
+// tile's row pieces stay at least 32 bytes wide (solves) or 128 bytes wide
+// (plain FP64 transforms, which measured slower on 64-byte pieces than on
+// one workgroup per CU with 128-byte pieces).
+template <typename T, int R, int LP, bool SOLVE>
 struct ColShape {
   static constexpr bool kSmall = rp_col_small(sizeof(T) == 8, R, SOLVE);
   static constexpr int E = kSmall ? 4 : 8;
   static constexpr int MAXLR = rp_col_maxlr(sizeof(T) == 8, R, SOLVE);
-  static constexpr int LOGPTS = kSmall ? 11 : 12;  // log2(E kColTH)
+  static constexpr int kLogE = kSmall ? 2 : 3;
+  static constexpr bool kHeavy = R > 1 && (SOLVE || sizeof(T) == 8);
+  // bytes of a row piece with 256 threads: 2^(log2(E 256) - LP) columns
+  static constexpr int kPiece256 = kLogE + 8 >= LP ? (1 << (kLogE + 8 - LP)) * int(2 * sizeof(T)) : 0;
+  static constexpr int TH = kHeavy && kPiece256 >= (SOLVE ? 32 : 128) ? 256 : kColTH;
+  static constexpr int LOGPTS = kLogE + (TH == 256 ? 8 : 9);  // log2(E TH)
 };
 
 template <typename T, int R, int LP, bool SOLVE>
-__global__ void __launch_bounds__(kColTH) cols_kernel(RpArgs<T> a) {
-  using S = ColShape<T, R, SOLVE>;
-  constexpr int kE = S::E, kMaxLr = S::MAXLR;
+__global__ void __launch_bounds__((ColShape<T, R, LP, SOLVE>::TH)) cols_kernel(RpArgs<T> a) {
+  using S = ColShape<T, R, LP, SOLVE>;
+  constexpr int kE = S::E, kMaxLr = S::MAXLR, TH = S::TH;
   constexpr int P = 1 << LP, N = R * P;
-  constexpr int LOGT = S::LOGPTS - LP;  // E kColTH = TT P
+  constexpr int LOGT = S::LOGPTS - LP;  // E TH = TT P
   constexpr int TT = 1 << LOGT;
-  static_assert(kColTH % TT == 0, "every thread stays on one column of the tile");
+  static_assert(TH % TT == 0, "every thread stays on one column of the tile");
   using FMap = ColMap<LP, LOGT, plan_pad(LP, kMaxLr, false)>;
   using IMap = ColMap<LP, LOGT, plan_pad(LP, kMaxLr, true)>;
-  using Fwd = Engine<T, LP, kE, kColTH, kMaxLr, false, FMap, false>;
-  using Inv = Engine<T, LP, kE, kColTH, kMaxLr, true, IMap, false>;
+  using Fwd = Engine<T, LP, kE, TH, kMaxLr, false, FMap, false>;
+  using Inv = Engine<T, LP, kE, TH, kMaxLr, true, IMap, false>;
   constexpr int kLds = Fwd::kLdsWords > Inv::kLdsWords ? Fwd::kLdsWords : Inv::kLdsWords;
   __shared__ cx<T> lds[kLds];
   const int tid = threadIdx.x;
@@ -222,17 +234,19 @@ hipError_t launch_rows(const RpArgs<T>& a, hipStream_t s) {
 template <typename T, int R, int LP>
 hipError_t launch_cols(const RpArgs<T>& a, hipStream_t s) {
   const bool solve = a.mode == kMrColSolve;
-  const int tt = 1 << ((solve ? ColShape<T, R, true>::LOGPTS : ColShape<T, R, false>::LOGPTS) - LP);
+  using SS = ColShape<T, R, LP, true>;
+  using SF = ColShape<T, R, LP, false>;
+  const int tt = 1 << ((solve ? SS::LOGPTS : SF::LOGPTS) - LP);
   const long long grid = a.fields * (long long)((a.nx + tt - 1) / tt);
   if (grid <= 0) return hipSuccess;
   if (grid > 0x7fffffffll) return hipErrorInvalidValue;
   if (solve) {
     if constexpr (rp_solve_radix(sizeof(T) == 8, R))
-      hipLaunchKernelGGL((cols_kernel<T, R, LP, true>), dim3((unsigned)grid), dim3(kColTH), 0, s, a);
+      hipLaunchKernelGGL((cols_kernel<T, R, LP, true>), dim3((unsigned)grid), dim3(SS::TH), 0, s, a);
     else
       return hipErrorInvalidValue;
   } else {
-    hipLaunchKernelGGL((cols_kernel<T, R, LP, false>), dim3((unsigned)grid), dim3(kColTH), 0, s, a);
+    hipLaunchKernelGGL((cols_kernel<T, R, LP, false>), dim3((unsigned)grid), dim3(SF::TH), 0, s, a);
   }
   return hipGetLastError();
 }
