@@ -2,8 +2,9 @@
 // T = 2^LOGT columns per tile (64-byte row segments at T = 8), S = split
 // real/imaginary LDS exchange, PF = prefetch the next tile, TW = twiddle
 // source (2 LDS copy, 3 per-stage tables, 4 per-stage tables with each value
-// loaded by one lane of the tile's columns).  The first entry of each length
-// is the default plan.
+// loaded by one lane of the tile's columns); _XW: the fused pass with its
+// exchanges around the radix-8 stage inside each wavefront.  The first entry
+// of each length is the default plan.
 #include "kernels.hpp"
 
 namespace fftpde {
@@ -22,6 +23,7 @@ const ColVariant kCols[] = {
     FFTPDE_COL_VARIANT(float, 10, 3, 8, 1024, 3, 1, 0, 1, 2),
     FFTPDE_COL_VARIANT(float, 10, 3, 8, 1024, 3, 1, 0, 0, 3),
     FFTPDE_COL_VARIANT(float, 10, 2, 8, 512, 3, 1, 0, 0, 3),
+    FFTPDE_COL_VARIANT_XW(float, 11, 2, 16, 512, 4, 1, 1, 0, 2),
     FFTPDE_COL_VARIANT(float, 11, 2, 16, 512, 4, 1, 1, 0, 2),
     FFTPDE_COL_VARIANT(float, 11, 2, 16, 512, 4, 1, 0, 0, 3),
     FFTPDE_COL_VARIANT(float, 11, 2, 16, 512, 3, 1, 0, 0, 3),

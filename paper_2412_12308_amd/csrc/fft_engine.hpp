@@ -232,12 +232,15 @@ struct RowMap {
     j = g & ((1 << lm) - 1);
     line = g >> lm;
   }
-  // butterfly slot q of thread tid (g = tid + TH q)
-  template <int TH>
+  // butterfly slot q of thread tid (g = tid + TH q) at stage S
+  template <int TH, int S = 0>
   __device__ __forceinline__ static void split_q(int tid, int q, int lm, int& line, int& j) {
     split(tid + TH * q, lm, line, j);
   }
   __device__ __forceinline__ static int lds(int line, int n) { return line * kStride + n + (n >> LP); }
+  // every exchange goes through LDS
+  template <int S>
+  static constexpr bool in_wave() { return false; }
 };
 
 // Columns: the T lines of a tile fastest, so a wavefront covers T adjacent
@@ -254,11 +257,13 @@ struct ColMap {
     j = g >> LOGT;
     (void)lm;
   }
-  template <int TH>
+  template <int TH, int S = 0>
   __device__ __forceinline__ static void split_q(int tid, int q, int lm, int& line, int& j) {
     split(tid + TH * q, lm, line, j);
   }
   __device__ __forceinline__ static int lds(int line, int n) { return (n + (n >> LP)) * T + line; }
+  template <int S>
+  static constexpr bool in_wave() { return false; }
 };
 
 // Columns with mirror-paired butterflies: at the stages with 2^MLM
@@ -271,7 +276,7 @@ struct ColMap {
 // the pairing only changes which thread does which butterfly.
 template <int LOGN, int LOGT, int LP, int MLM>
 struct ColMapMirror : ColMap<LOGN, LOGT, LP> {
-  template <int TH>
+  template <int TH, int S = 0>
   __device__ __forceinline__ static void split_q(int tid, int q, int lm, int& line, int& j) {
     constexpr int T = 1 << LOGT;
     line = tid & (T - 1);
@@ -282,6 +287,95 @@ struct ColMapMirror : ColMap<LOGN, LOGT, LP> {
       const int j0 = tid >> LOGT;
       j = j0 == 0 ? h : 2 * h - j0;
     }
+  }
+};
+
+// Columns of N = 2048 in tiles of 4 (lane bits 0-1), 16 points per thread on
+// 512 threads, radix plan 16 16 8 (forward) and 8 16 16 (reversed), with the
+// exchange between the two stages that meet the radix-8 stage kept inside
+// each wavefront.  For the Stockham exchange into a stage of radix R2 with
+// Ns' = N / R2, butterfly j' reads the outputs of butterflies t Ns + (j' mod
+// Ns), t < R2, of the stage before (Ns its sub-length): a wavefront that owns
+// every butterfly of a set of residues mod Ns on both sides owns the whole
+// exchange.  Wave w takes the residues {w, 16 - w} mod 16 ({0, 8} for w = 0),
+// lane bit 2 choosing one of the two (kbit), lane bits 3-5 a 3-bit index h:
+//   layout 1, radix 16 of sub-length 16:   j = 16 h + k
+//   layout 2, radix 8 of sub-length 256:   j = 16 (h + 8 q) + k   (q the slot)
+//   layout 3, radix 16 of sub-length 8:    j = 8 k + h
+// Forward: stage 0 as ColMap (the loads), layout 1, in-wave exchange,
+// layout 2.  Reversed: layout 2 (the same registers), in-wave exchange,
+// layout 3, then ColMap (the stores).  In both in-wave exchanges the value in
+// register 8 q + b of the lane with index h goes to register 8 q + h of the
+// lane with index b (b, h < 8): a transpose of lane bits 3-5 with register
+// bits 0-2, done as three swaps of one lane bit with one register bit.
+// The other exchanges go through LDS as in ColMap.
+template <int LP, bool REV>
+struct ColMapWave : ColMap<11, 2, LP> {
+  using Base = ColMap<11, 2, LP>;
+  static constexpr int layout(int s) { return REV ? (s == 0 ? 2 : s == 1 ? 3 : 0) : (s == 0 ? 0 : s == 1 ? 1 : 2); }
+  template <int S>
+  static constexpr bool in_wave() { return REV ? S == 0 : S == 1; }
+  // the residue mod 16 this lane's butterflies share
+  __device__ __forceinline__ static int residue(int tid) {
+    const int w = tid >> 6, kb = (tid >> 2) & 1;
+    return kb ? (w ? 16 - w : 8) : w;
+  }
+  template <int TH, int S = 0>
+  __device__ __forceinline__ static void split_q(int tid, int q, int lm, int& line, int& j) {
+    static_assert(TH == 512, "512 threads: 8 wavefronts, one per residue pair");
+    constexpr int L = layout(S);
+    if constexpr (L == 0) {
+      Base::template split_q<TH>(tid, q, lm, line, j);
+    } else {
+      line = tid & 3;
+      const int k = residue(tid), h = (tid >> 3) & 7;
+      if constexpr (L == 1) j = 16 * h + k;
+      else if constexpr (L == 2) j = 16 * (h + 8 * q) + k;
+      else j = 8 * k + h;
+    }
+  }
+  // Swap lane bit LB with register bit RB over the 32-bit words of x:
+  // afterwards the lane with lane bit 0 holds its own register with RB = 0
+  // and its partner's register with RB = 0 in place of RB = 1; the lane with
+  // lane bit 1 its partner's RB = 1 register in place of RB = 0.
+  template <int LB, int RB, typename T, int E>
+  __device__ __forceinline__ static void swap_bits(cx<T> (&x)[E], int tid) {
+    static_assert(sizeof(T) == 4, "FP32 words");
+    const bool hi = (tid >> LB) & 1;
+#pragma unroll
+    for (int r = 0; r < E; r++) {
+      if ((r >> RB) & 1) continue;
+      float* a = &x[r].re;
+      float* b = &x[r | (1 << RB)].re;
+#pragma unroll
+      for (int c = 0; c < 2; c++) {
+        if constexpr (LB == 5) {
+          // v_permlane32_swap: the upper 32 lanes of a with the lower 32 of b
+          const auto v = __builtin_amdgcn_permlane32_swap(__float_as_uint(a[c]), __float_as_uint(b[c]), false, false);
+          a[c] = __uint_as_float(v[0]);
+          b[c] = __uint_as_float(v[1]);
+        } else if constexpr (LB == 4) {
+          // v_permlane16_swap: the odd rows of a with the even rows of b
+          const auto v = __builtin_amdgcn_permlane16_swap(__float_as_uint(a[c]), __float_as_uint(b[c]), false, false);
+          a[c] = __uint_as_float(v[0]);
+          b[c] = __uint_as_float(v[1]);
+        } else {
+          static_assert(LB == 3, "lane bits 3, 4, 5");
+          // DPP row_ror:8 reads lane l ^ 8 within each row of 16
+          const float send = hi ? a[c] : b[c];
+          const float got = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(send), 0x128, 0xf, 0xf, false));
+          a[c] = hi ? got : a[c];
+          b[c] = hi ? b[c] : got;
+        }
+      }
+    }
+  }
+  template <int S, typename T, int E>
+  __device__ __forceinline__ static void wave_exchange(cx<T> (&x)[E], int tid) {
+    static_assert(E == 16, "16 points per thread");
+    swap_bits<3, 0>(x, tid);
+    swap_bits<4, 1>(x, tid);
+    swap_bits<5, 2>(x, tid);
   }
 };
 
@@ -377,7 +471,7 @@ struct Engine {
 #pragma unroll
     for (int q = 0; q < E / R; q++) {
       int line, j;
-      Map::template split_q<TH>(tid, q, LOGN - LR, line, j);
+      Map::template split_q<TH, S>(tid, q, LOGN - LR, line, j);
 #pragma unroll
       for (int t = 0; t < R; t++) f(q * R + t, line, j + t * M);
     }
@@ -402,7 +496,7 @@ struct Engine {
 #pragma unroll
     for (int q = 0; q < E / R; q++) {
       int line, j;
-      Map::template split_q<TH>(tid, q, LOGN - LR, line, j);
+      Map::template split_q<TH, S>(tid, q, LOGN - LR, line, j);
 #pragma unroll
       for (int t = 0; t < R; t++) f(q * R + t, line, j, t * M);
     }
@@ -438,7 +532,7 @@ struct Engine {
 #pragma unroll
       for (int q = 0; q < E / R; q++) {
         int line, j;
-        Map::template split_q<TH>(tid, q, LOGN - LR, line, j);
+        Map::template split_q<TH, S>(tid, q, LOGN - LR, line, j);
         const int k = j & (NS - 1);
         const int o = ((j - k) << LR) + k;
         if constexpr (kAffine) {
@@ -455,7 +549,7 @@ struct Engine {
 #pragma unroll
       for (int q = 0; q < E / R2; q++) {
         int line, j;
-        Map::template split_q<TH>(tid, q, LOGN - LR2, line, j);
+        Map::template split_q<TH, S + 1>(tid, q, LOGN - LR2, line, j);
         if constexpr (kAffine) {
           const Word* b = lds + Map::lds(line, j);
 #pragma unroll
@@ -481,6 +575,14 @@ struct Engine {
       take([](cx<T>& v, const cx<T>& w) { v = w; });
       lds_barrier();
     }
+  }
+
+  // The exchange after stage S: across the lanes of each wavefront where the
+  // map keeps it inside them, else through LDS.
+  template <int S>
+  __device__ __forceinline__ static void xchg(cx<T> (&x)[E], Word* lds, int tid) {
+    if constexpr (Map::template in_wave<S>()) Map::template wave_exchange<S>(x, tid);
+    else exchange<S>(x, lds, tid);
   }
 
   // Twiddles of stage S for this thread: w_{Ns R}^{t k}, t = 1..R-1, per butterfly.
@@ -534,7 +636,7 @@ struct Engine {
 #pragma unroll
       for (int q = 0; q < E / R; q++) {
         int line, j;
-        Map::template split_q<TH>(tid, q, LOGN - LR, line, j);
+        Map::template split_q<TH, S>(tid, q, LOGN - LR, line, j);
         const cx<T>* b = tws + stw_off<S>() + (j & (NS - 1));
         if constexpr (TWG > 1) {
           // lane c of a group loads t = TWG u + c + 1 (the group's last lane
@@ -563,7 +665,7 @@ struct Engine {
 #pragma unroll
       for (int q = 0; q < E / R; q++) {
         int line, j;
-        Map::template split_q<TH>(tid, q, LOGN - LR, line, j);
+        Map::template split_q<TH, S>(tid, q, LOGN - LR, line, j);
         const int k = j & (NS - 1);
 #pragma unroll
         for (int t = 1; t < R; t++) w[off + q * (R - 1) + t - 1] = tw[(t * k) << (kTwLog - LNS - LR)];
@@ -602,7 +704,7 @@ struct Engine {
       if constexpr (NS > 1) {
         if constexpr (SRC == TwSrc::lds) {
           int line, j;
-          Map::template split_q<TH>(tid, q, LOGN - LR, line, j);
+          Map::template split_q<TH, S>(tid, q, LOGN - LR, line, j);
           const int k = j & (NS - 1);
 #pragma unroll
           for (int t = 1; t < R; t++) v[t] = cmul(v[t], twl[(t * k) << (LOGN - LNS - LR)]);
@@ -622,10 +724,10 @@ struct Engine {
         cx<T> wn[twn<S + 1>() > 0 ? twn<S + 1>() : 1];
         if constexpr (SRC == TwSrc::stage) load_tw_stage<S + 1>(wn, 0, tw, tid);
         else load_tw<S + 1>(wn, 0, tw, tid);
-        exchange<S>(x, lds, tid);
+        xchg<S>(x, lds, tid);
         stage<S + 1, SRC>(x, lds, tw, twl, tid, wn);
       } else {
-        exchange<S>(x, lds, tid);
+        xchg<S>(x, lds, tid);
         stage<S + 1, SRC>(x, lds, tw, twl, tid, w);
       }
     }

@@ -666,7 +666,11 @@ __global__ void __launch_bounds__(TH) row_kernel(RowArgs<T> a) {
 // two workgroups fit per CU at the large sizes); PF prefetches the next tile;
 // FUSED compiles the [forward, symbol, inverse] mode alone.
 // ---------------------------------------------------------------------------
-template <typename T, int LOGN, int LOGT, int E, int TH, int MAXLR, int NF, bool SPLIT, bool PF, int TWM, bool FUSED>
+// XW: the two exchanges around the radix-8 stage stay inside each wavefront
+// (ColMapWave: 2048-point FP32 columns, tiles of 4, 16 points per thread on
+// 512 threads, the fused one-field pass).
+template <typename T, int LOGN, int LOGT, int E, int TH, int MAXLR, int NF, bool SPLIT, bool PF, int TWM, bool FUSED,
+          bool XW = false>
 __global__ void __launch_bounds__(TH) col_kernel(ColArgs<T> a) {
   constexpr int N = 1 << LOGN;
   constexpr int TT = 1 << LOGT;
@@ -684,12 +688,17 @@ __global__ void __launch_bounds__(TH) col_kernel(ColArgs<T> a) {
   // symbol once for rows b' and -b' (R0 + 1 evaluations for 2 R0 values).
   constexpr int kLr0 = plan_lr(LOGN, MAXLR, 0, true);
   constexpr int kR0 = 1 << kLr0;
-  constexpr bool kMirror = FUSED && NF == 1 && kOneCol && LOGN >= 3 && E == 2 * kR0;
+  static_assert(!XW || (sizeof(T) == 4 && LOGN == 11 && LOGT == 2 && E == 16 && TH == 512 && MAXLR == 4 && NF == 1 &&
+                        FUSED),
+                "in-wave exchanges: the fused 2048-point FP32 pass on 4-column tiles");
+  constexpr bool kMirror = !XW && FUSED && NF == 1 && kOneCol && LOGN >= 3 && E == 2 * kR0;
   constexpr int kMlm = kMirror ? LOGN - kLr0 : -1;
-  using FMap = typename std::conditional<kMirror, ColMapMirror<LOGN, LOGT, plan_pad(LOGN, MAXLR, false), kMlm>,
-                                         ColMap<LOGN, LOGT, plan_pad(LOGN, MAXLR, false)>>::type;
-  using IMap = typename std::conditional<kMirror, ColMapMirror<LOGN, LOGT, plan_pad(LOGN, MAXLR, true), kMlm>,
-                                         ColMap<LOGN, LOGT, plan_pad(LOGN, MAXLR, true)>>::type;
+  using FMap0 = typename std::conditional<kMirror, ColMapMirror<LOGN, LOGT, plan_pad(LOGN, MAXLR, false), kMlm>,
+                                          ColMap<LOGN, LOGT, plan_pad(LOGN, MAXLR, false)>>::type;
+  using IMap0 = typename std::conditional<kMirror, ColMapMirror<LOGN, LOGT, plan_pad(LOGN, MAXLR, true), kMlm>,
+                                          ColMap<LOGN, LOGT, plan_pad(LOGN, MAXLR, true)>>::type;
+  using FMap = typename std::conditional<XW, ColMapWave<plan_pad(LOGN, MAXLR, false), false>, FMap0>::type;
+  using IMap = typename std::conditional<XW, ColMapWave<plan_pad(LOGN, MAXLR, true), true>, IMap0>::type;
   using Fwd = Engine<T, LOGN, E, TH, MAXLR, false, FMap, SPLIT, kTwg>;
   using Inv = Engine<T, LOGN, E, TH, MAXLR, true, IMap, SPLIT, kTwg>;
   constexpr int kLdsWords = Fwd::kLdsWords > Inv::kLdsWords ? Fwd::kLdsWords : Inv::kLdsWords;
@@ -811,7 +820,41 @@ __global__ void __launch_bounds__(TH) col_kernel(ColArgs<T> a) {
       const Symbol<T, OP> sym(a.sym, int((col0 + (tid & (TT - 1))) & fmask));
       // (the kernels for all modes keep the general form: the split one's
       // registers would cost them a resident workgroup)
-      if (kMirror && sym.split_ok()) {
+      if constexpr (XW) {
+        if (sym.split_ok()) {
+          // register 8 q + t holds row j_q + 256 t, j_q = 16 (h + 8 q) + k
+          // (ColMapWave layout 2).  In waves 1-7 the row of register 8 + t
+          // is the mirror of the row of register 7 - t of lane l ^ 60 (the
+          // other residue, h -> 7 - h), so each lane evaluates its 8 rows
+          // of q = 0 and reads the other 8 values from that lane; wave 0
+          // (residues 0 and 8, which pair differently) evaluates all 16.
+          auto sdd = [](int d) { return d >= (N >> 1) ? d - N : d; };
+          const int k = FMap::residue(tid), h = (tid >> 3) & 7;
+          const int j0 = 16 * h + k;
+          T m0[8], m1[8];
+#pragma unroll
+          for (int t = 0; t < 8; t++) m0[t] = sym.split(j0, sdd(256 * t));
+          if (__builtin_amdgcn_readfirstlane(tid >> 6) == 0) {
+#pragma unroll
+            for (int t = 0; t < 8; t++) m1[t] = sym.split(j0 + 128, sdd(256 * t));
+          } else {
+            const int src = ((tid & 63) ^ 60) << 2;
+#pragma unroll
+            for (int t = 0; t < 8; t++)
+              m1[t] = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(m0[7 - t])));
+          }
+#pragma unroll
+          for (int t = 0; t < 8; t++) {
+            v[t] = {v[t].re * m0[t], -v[t].im * m0[t]};
+            v[8 + t] = {v[8 + t].re * m1[t], -v[8 + t].im * m1[t]};
+          }
+        } else {
+          Inv::for_each_input(tid, [&](int i, int, int n) {
+            const T m = sym(n);
+            v[i] = {v[i].re * m, -v[i].im * m};
+          });
+        }
+      } else if (kMirror && sym.split_ok()) {
         // register q R0 + t holds row j_q + t M (M = N / R0) of this
         // thread's column, j_1 the mirror of j_0 (ColMapMirror).  Slot e of
         // the R0 + 1 evaluations: rows j0 + e M; on the thread with j0 = 0,
@@ -1014,21 +1057,23 @@ int occ_row() {
   return n;
 }
 
-template <typename T, int LOGN, int LOGT, int E, int TH, int MAXLR, int NF, bool SPLIT, bool PF, int TWM, bool FUSED>
+template <typename T, int LOGN, int LOGT, int E, int TH, int MAXLR, int NF, bool SPLIT, bool PF, int TWM, bool FUSED,
+          bool XW = false>
 hipError_t launch_col(const void* args, long long ncols, long long max_blocks, hipStream_t s) {
   long long grid = (ncols + (1 << LOGT) - 1) >> LOGT;
   if (max_blocks > 0 && grid > max_blocks) grid = max_blocks;
   if (grid <= 0 || grid > 0x7fffffffll) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((col_kernel<T, LOGN, LOGT, E, TH, MAXLR, NF, SPLIT, PF, TWM, FUSED>), dim3((unsigned)grid),
+  hipLaunchKernelGGL((col_kernel<T, LOGN, LOGT, E, TH, MAXLR, NF, SPLIT, PF, TWM, FUSED, XW>), dim3((unsigned)grid),
                      dim3(TH), 0, s, *static_cast<const ColArgs<T>*>(args));
   return hipGetLastError();
 }
 
-template <typename T, int LOGN, int LOGT, int E, int TH, int MAXLR, int NF, bool SPLIT, bool PF, int TWM, bool FUSED>
+template <typename T, int LOGN, int LOGT, int E, int TH, int MAXLR, int NF, bool SPLIT, bool PF, int TWM, bool FUSED,
+          bool XW = false>
 int occ_col() {
   int n = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &n, col_kernel<T, LOGN, LOGT, E, TH, MAXLR, NF, SPLIT, PF, TWM, FUSED>, TH, 0) != hipSuccess)
+          &n, col_kernel<T, LOGN, LOGT, E, TH, MAXLR, NF, SPLIT, PF, TWM, FUSED, XW>, TH, 0) != hipSuccess)
     return 0;
   return n;
 }
@@ -1064,6 +1109,19 @@ constexpr int lds_elems_col(int logt) {
    int(::fftpde::lds_elems_col<LOGN, MAXLR>(LOGT) * ((SPLIT) ? sizeof(T) : sizeof(::fftpde::cx<T>)) + \
        ((TWM) == 2 ? (1 << (LOGN)) * sizeof(::fftpde::cx<T>) : 0)),                                  \
    "col_" #T "_n" #LOGN "_t" #LOGT "_e" #E "_th" #TH "_r" #MAXLR "_f" #NF "_s" #SPLIT "_pf" #PF "_tw" #TWM}
+
+// The same configuration with its fused pass on in-wave exchanges around the
+// radix-8 stage (col_kernel XW, ColMapWave); its other modes run the plain
+// kernel.
+#define FFTPDE_COL_VARIANT_XW(T, LOGN, LOGT, E, TH, MAXLR, NF, SPLIT, PF, TWM)                        \
+  {&::fftpde::launch_col<T, LOGN, LOGT, E, TH, MAXLR, NF, SPLIT, PF, TWM, false>,                     \
+   &::fftpde::occ_col<T, LOGN, LOGT, E, TH, MAXLR, NF, SPLIT, PF, TWM, false>,                        \
+   &::fftpde::launch_col<T, LOGN, LOGT, E, TH, MAXLR, NF, SPLIT, PF, TWM, true, true>,                \
+   &::fftpde::occ_col<T, LOGN, LOGT, E, TH, MAXLR, NF, SPLIT, PF, TWM, true, true>,                   \
+   LOGN, LOGT, E, TH, MAXLR, NF, SPLIT, PF, TWM,                                                      \
+   int(::fftpde::lds_elems_col<LOGN, MAXLR>(LOGT) * ((SPLIT) ? sizeof(T) : sizeof(::fftpde::cx<T>)) + \
+       ((TWM) == 2 ? (1 << (LOGN)) * sizeof(::fftpde::cx<T>) : 0)),                                  \
+   "col_" #T "_n" #LOGN "_t" #LOGT "_e" #E "_th" #TH "_r" #MAXLR "_f" #NF "_s" #SPLIT "_pf" #PF "_tw" #TWM "_xw"}
 
 // Tables defined in the per-dtype translation units.
 const RowVariant* row_variants_f32(int* count);

@@ -154,3 +154,35 @@ def test_autotune_picks_an_admitted_variant_and_round_trips(fp, dt, tmp_path):
     assert f"tiled {code} 8 9 {rep['tiled_bytes']}" in open(path).read()
     assert f"chunk {code} 8 9 {rep['chunk_bytes']}" in open(path).read()
     fp.plan_select(None)
+
+
+def _xw_cases():
+    return [pytest.param(v, id=v["name"]) for v in _variants() if v["name"].endswith("_xw")]
+
+
+@pytest.mark.parametrize("v", _xw_cases())
+def test_in_wave_exchange_variant_all_symbols(fp, v):
+    """The fused column pass whose exchanges around the radix-8 stage stay in
+    each wavefront (2048-row columns, 4-column tiles): the Poisson, diffusion
+    and wave solves against the oracle, on 6 tiles per field and a batch of 2.
+    The wave solve's symbol is shared between mirrored rows across lanes, and
+    wave 0 of each tile takes the residues 0 and 8, which pair differently:
+    every tile has both kinds, so a wrong pairing shows at any column."""
+    nx, ny, batch = 24, 2048, 2
+    fp.plan_select(None)
+    fp.plan_select(v["name"])
+    say(f"variant {v['name']} nx={nx} ny={ny} batch={batch}")
+    try:
+        x = W.random_field((batch, ny, nx), seed=2048 + 24)
+        xd = to_dev(x, "c64")
+        u_p = to_host(fp.solve_poisson(xd, 1.0, 2.0))
+        u_d = to_host(fp.solve_diffusion(xd, 0.05, 0.02, 1.0, 2.0))
+        u_w, _ = fp.solve_wave(xd, None, 1.0, 0.37, 1.0, 2.0)
+        u_w = to_host(u_w)
+        for b in range(batch):
+            xb = as_oracle_input(x[b], "c64")
+            assert oracle.rel_l2(u_p[b], oracle.solve_poisson(xb, 1.0, 2.0)) <= tol("c64", nx, ny, 2)
+            assert oracle.rel_l2(u_d[b], oracle.solve_diffusion(xb, 1.0, 2.0, 0.05, 0.02)) <= tol("c64", nx, ny, 2)
+            assert oracle.rel_l2(u_w[b], oracle.solve_wave(xb, None, 1.0, 2.0, 1.0, 0.37)[0]) <= tol("c64", nx, ny, 2)
+    finally:
+        fp.plan_select(None)
