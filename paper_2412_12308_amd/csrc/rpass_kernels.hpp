@@ -110,9 +110,10 @@ __global__ void __launch_bounds__(kRowTH) rows_kernel(RpArgs<T> a) {
 // 140-250 VGPRs, two or three waves per SIMD, so a 512-thread workgroup
 // (two waves per SIMD) runs alone on its CU with nothing to overlap its
 // loads.  They take 256 threads (two or three workgroups per CU) where the
-// tile's row pieces stay at least 32 bytes wide (solves) or 128 bytes wide
-// (plain FP64 transforms, which measured slower on 64-byte pieces than on
-// one workgroup per CU with 128-byte pieces).
+// tile's row pieces stay at least 16 bytes wide (solves: faster even on
+// 16-byte pieces) or 128 bytes wide (plain FP64 transforms, which measured
+// slower on 64-byte pieces than on one workgroup per CU with 128-byte
+// pieces).
 template <typename T, int R, int LP, bool SOLVE>
 struct ColShape {
   static constexpr bool kSmall = rp_col_small(sizeof(T) == 8, R, SOLVE);
@@ -122,7 +123,7 @@ struct ColShape {
   static constexpr bool kHeavy = R > 1 && (SOLVE || sizeof(T) == 8);
   // bytes of a row piece with 256 threads: 2^(log2(E 256) - LP) columns
   static constexpr int kPiece256 = kLogE + 8 >= LP ? (1 << (kLogE + 8 - LP)) * int(2 * sizeof(T)) : 0;
-  static constexpr int TH = kHeavy && kPiece256 >= (SOLVE ? 32 : 128) ? 256 : kColTH;
+  static constexpr int TH = kHeavy && kPiece256 >= (SOLVE ? 16 : 128) ? 256 : kColTH;
   static constexpr int LOGPTS = kLogE + (TH == 256 ? 8 : 9);  // log2(E TH)
 };
 
