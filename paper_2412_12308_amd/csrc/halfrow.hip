@@ -86,6 +86,16 @@ __global__ void __launch_bounds__(kRowTH) r2c_rows_kernel(HalfRowArgs<T> a) {
   cx<T> wall[Eng::kTwRegs];
   Eng::load_all_tw(wall, a.tw, tid);
   const int sh = kTwLog - a.lognx;  // w^k = tw[k << sh], w = exp(-2 pi i / nx)
+  // FP32: w^k at this thread's output positions k, which no tile changes,
+  // loaded once, so no tile waits on them after its transform (FP64 loads
+  // them per tile: held in registers they would cost a resident wave)
+  constexpr bool kHold = sizeof(T) == 4;
+  cx<T> wk[kHold ? kRowE : 1];
+  if constexpr (kHold) Eng::for_each_output(tid, [&](int i, int, int k) { wk[i] = a.tw[k << sh]; });
+  auto w_at = [&](int i, int k) -> cx<T> {
+    if constexpr (kHold) return wk[i];
+    else return a.tw[k << sh];
+  };
   const T h = T(0.5);
   for (long long tile = walk.first; tile >= 0; tile = walk.next(tile)) {
     tid = opaque(tid);
@@ -104,7 +114,7 @@ __global__ void __launch_bounds__(kRowTH) r2c_rows_kernel(HalfRowArgs<T> a) {
       const cx<T> o = {h * (z.im + zm.im), h * (zm.re - z.re)};      // -i (Zr - conj Zr-) / 2
       if (pl.live) {
         cx<T>* out = a.hout + pl.row * (M + 1);
-        out[k] = e + cmul(o, a.tw[k << sh]);
+        out[k] = e + cmul(o, w_at(i, k));
         if (k == 0) out[M] = e - o;  // w^M = -1
       }
     });
@@ -130,6 +140,15 @@ __global__ void __launch_bounds__(kRowTH) c2r_rows_kernel(HalfRowArgs<T> a) {
   cx<T> wall[Eng::kTwRegs];
   Eng::load_all_tw(wall, a.tw, tid);
   const int sh = kTwLog - a.lognx;
+  // FP32: w^-k at this thread's input positions k, loaded once (no tile
+  // changes them; FP64 loads them per tile, as in the r2c rows)
+  constexpr bool kHold = sizeof(T) == 4;
+  cx<T> wk[kHold ? kRowE : 1];
+  if constexpr (kHold) Eng::for_each_input(tid, [&](int i, int, int k) { wk[i] = conjg(a.tw[k << sh]); });
+  auto wc_at = [&](int i, int k) -> cx<T> {
+    if constexpr (kHold) return wk[i];
+    else return conjg(a.tw[k << sh]);
+  };
   const T h = T(0.5);
   for (long long tile = walk.first; tile >= 0; tile = walk.next(tile)) {
     tid = opaque(tid);
@@ -156,7 +175,7 @@ __global__ void __launch_bounds__(kRowTH) c2r_rows_kernel(HalfRowArgs<T> a) {
         const cx<T> v = x[i];
         const cx<T> vm = lds[Map::lds(pl.mirror, M - k)];  // X~[b][k + M] = conj X[-b][M - k]
         e = {h * (v.re + vm.re), h * (v.im - vm.im)};
-        o = cmul(cx<T>{h * (v.re - vm.re), h * (v.im + vm.im)}, conjg(a.tw[k << sh]));  // times w^-k
+        o = cmul(cx<T>{h * (v.re - vm.re), h * (v.im + vm.im)}, wc_at(i, k));  // times w^-k
       }
       x[i] = {e.re - o.im, -(e.im + o.re)};  // conj(E + i O): the inverse by conjugation
     });
