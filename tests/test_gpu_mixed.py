@@ -278,7 +278,9 @@ def test_real_solve_matches_the_complex_path_on_a_7_smooth_grid(fp, dt):
 # Sides R 2^m (R = 1, 3, 5, 7, FP64 R <= 3; m >= 5) take the radix-R step
 # around the power-of-two register engine: rows and columns of every R, the
 # longest 2^m of each, odd R on both axes, and the fused column pass of the
-# solves (4 points per thread for R >= 5 in FP32 and R = 3 in FP64).
+# solves (4 points per thread for R >= 5 in FP32 and R = 3 in FP64; 256-thread
+# workgroups for the solves with R > 1, down to tiles of one FP64 or two FP32
+# columns at 3072 rows).
 RP_SHAPES = [(96, 160), (160, 96), (448, 96), (384, 640), (3072, 32), (32, 3072), (2560, 32), (32, 3584),
              (3584, 64), (1536, 96), (96, 1536)]
 
@@ -300,7 +302,7 @@ def test_radix_step_passes_vs_oracle(fp, nx, ny, dt):
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
 @pytest.mark.parametrize("nx,ny", [(160, 96), (64, 1536), (1536, 96), (448, 224), (96, 128), (96, 160),
-                                   (64, 2560), (32, 3584), (3072, 64)])
+                                   (64, 2560), (32, 3584), (3072, 64), (32, 3072)])
 def test_radix_step_solves_vs_oracle(fp, nx, ny, dt):
     say(f"radix-step solves {nx}x{ny} {dt}")
     lx, ly = 1.5, 0.75
