@@ -81,7 +81,7 @@ extern "C" int fftpde_autotune(fftpde_ctx* ctx, int nx, int ny, int batch, int d
   if (rc != FFTPDE_OK) return fail(rc);
 
   // time the current plan of every slot, then each candidate in turn
-  auto time_solve = [&](double* us, double* err) -> int {
+  auto time_once = [&](double* us, double* err) -> int {
     int r = solve(sc.out);  // warm-up (and occupancy queries)
     if (r != FFTPDE_OK) return r;
     if (hipEventRecord(sc.e0, s) != hipSuccess) return FFTPDE_EDEVICE;
@@ -100,6 +100,31 @@ extern "C" int fftpde_autotune(fftpde_ctx* ctx, int nx, int ny, int batch, int d
     *err = h[1] > 0 ? std::sqrt(h[0] / h[1]) : std::sqrt(h[0]);
     return FFTPDE_OK;
   };
+  // each candidate timed twice, the faster window kept (one slow window, a
+  // clock step or another process, does not decide a plan)
+  auto time_solve = [&](double* us, double* err) -> int {
+    double us2 = 0, err2 = 0;
+    int r = time_once(us, err);
+    if (r == FFTPDE_OK) r = time_once(&us2, &err2);
+    if (r == FFTPDE_OK) {
+      *us = std::min(*us, us2);
+      *err = std::max(*err, err2);
+    }
+    return r;
+  };
+  // The first tens of milliseconds of back-to-back work after the GPU idles
+  // run up to 15 % slower while its clocks settle; about 100 ms of the current
+  // plan first, so that the candidates timed first are not the ones that
+  // pay for it.
+  {
+    double spent = 0;
+    for (int i = 0; i < 64 && spent < 1e5; i++) {
+      double us = 0, err = 0;
+      rc = time_once(&us, &err);
+      if (rc != FFTPDE_OK) return fail(rc);
+      spent += us * (reps + 1);
+    }
+  }
 
   std::string out = "{\"nx\": " + std::to_string(nx) + ", \"ny\": " + std::to_string(ny) + ", \"batch\": " +
                     std::to_string(batch) + ", \"dtype\": " + std::to_string(dtype) + ", \"op\": " +

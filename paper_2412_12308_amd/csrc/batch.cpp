@@ -403,6 +403,21 @@ int fftpde_batch_tune(fftpde_batch* b, int reps, fftpde_stream stream) {
   for (const fftpde_job& j : b->jobs) maxlog = std::max(maxlog, std::max(ilog2(j.nx), ilog2(j.ny)));
   // the two plans differ by rounding only
   const double tol = dt == FFTPDE_C64 ? 2.0 * 2e-6 * maxlog : 1e-12;
+  // about 100 ms of replays before the first timing: the first tens of
+  // milliseconds after the GPU idles run up to 15 % slower (clocks settling),
+  // which would make the starting plan look slow against every flip
+  {
+    float spent = 0.f;
+    for (int i = 0; i < 16 && spent < 100.f; i++) {
+      if (!dev(hipEventRecord(e0, s))) return done(FFTPDE_EDEVICE);
+      for (int r = 0; r < 8; r++)
+        if (!dev(hipGraphLaunch(b->exec, s))) return done(FFTPDE_EDEVICE);
+      float ms = 0.f;
+      if (!dev(hipEventRecord(e1, s)) || !dev(hipEventSynchronize(e1)) || !dev(hipEventElapsedTime(&ms, e0, e1)))
+        return done(FFTPDE_EDEVICE);
+      spent += ms;
+    }
+  }
   double cur_us = 0, err = 0;
   rc = measure(&cur_us, &err);
   if (rc != FFTPDE_OK) return done(rc);
