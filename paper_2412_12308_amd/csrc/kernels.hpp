@@ -629,7 +629,12 @@ __global__ void __launch_bounds__(TH) row_kernel(RowArgs<T> a) {
         if (more) rload(nt);
       }
     } else if constexpr (PF) {
+      // FP32: the next tile's loads at raised wave priority, ahead of the
+      // other resident workgroups' arithmetic (2048 rows: 94.3 -> 93.0 us per
+      // 8-field chunk)
+      if constexpr (sizeof(T) == 4) __builtin_amdgcn_s_setprio(3);
       if (more) load(nt, nxt);
+      if constexpr (sizeof(T) == 4) __builtin_amdgcn_s_setprio(0);
     }
 #pragma unroll
     for (int i = 0; i < E; i++) x[i].im *= sgn;
