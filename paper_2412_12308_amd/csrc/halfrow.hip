@@ -153,12 +153,16 @@ __global__ void __launch_bounds__(kRowTH) c2r_rows_kernel(HalfRowArgs<T> a) {
   for (long long tile = walk.first; tile >= 0; tile = walk.next(tile)) {
     tid = opaque(tid);
     cx<T> x[kRowE];
+    // FP32: the tile's loads at raised wave priority, ahead of the other
+    // resident workgroup's transform (2048: 70.4 -> 68-69 us per 8 fields)
+    if constexpr (kHold) __builtin_amdgcn_s_setprio(3);
     Eng::for_each_input(tid, [&](int i, int line, int n) {
       const cx<T>* in = a.hin + pair_line<LINES>(tile, line, npairs, a.logny).row * (M + 1);
       x[i] = in[n];
       lds[Map::lds(line, n)] = x[i];
       if (n == 0) last[line] = in[M];
     });
+    if constexpr (kHold) __builtin_amdgcn_s_setprio(0);
     lds_barrier();
     Eng::for_each_input(tid, [&](int i, int line, int k) {
       const PairLine pl = pair_line<LINES>(tile, line, npairs, a.logny);
