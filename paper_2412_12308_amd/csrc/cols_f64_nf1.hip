@@ -16,8 +16,8 @@ const ColVariant kCols[] = {
     FFTPDE_COL_VARIANT(double, 8, 4, 8, 512, 3, 1, 0, 1, 3),
     FFTPDE_COL_VARIANT(double, 9, 3, 8, 512, 3, 1, 0, 1, 3),
     FFTPDE_COL_VARIANT(double, 10, 2, 8, 512, 3, 1, 0, 1, 3),
-    FFTPDE_COL_VARIANT(double, 11, 1, 8, 512, 3, 1, 0, 0, 4),
     FFTPDE_COL_VARIANT(double, 11, 1, 8, 512, 3, 1, 0, 0, 3),
+    FFTPDE_COL_VARIANT(double, 11, 1, 8, 512, 3, 1, 0, 0, 4),
     FFTPDE_COL_VARIANT(double, 11, 1, 16, 256, 3, 1, 0, 0, 3),
     FFTPDE_COL_VARIANT(double, 11, 2, 8, 1024, 3, 1, 0, 0, 3),
     FFTPDE_COL_VARIANT(double, 11, 2, 16, 512, 3, 1, 1, 0, 3),
